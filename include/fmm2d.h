@@ -1,0 +1,208 @@
+/*
+ * fmm2d.h -- C ABI of the MI355X (gfx950) hierarchical 2D FMM library.
+ *
+ * The library evaluates the complex logarithmic potential
+ *
+ *     Phi_j = sum_{i=1..N} u_i * log(y_j - x_i),   j = 1..M,   x, y in C
+ *
+ * (Luo & Duraiswami, "Alternative tilings for the fast multipole method on
+ * the plane", arXiv:1204.3105, Sec. 2, eqs. 1-2) with the fast multipole
+ * method on one of the paper's three tilings: the square quadtree (Sec. 4),
+ * the hexagonal septree with base-7 GBT addressing (Sec. 5) or the
+ * triangle-quadtree (Sec. 6).  The expansion and translation operators,
+ * which the paper cites but omits, are those of Greengard & Rokhlin (1987),
+ * Lemmas 2.1-2.5.  Every step of a solve runs in HIP kernels on one GPU.
+ *
+ * Conventions shared by every entry point
+ *  - Points are complex128 arrays: 2*n doubles, interleaved (x0, y0, x1, y1,
+ *    ...).  Strengths are n real doubles.  The output Phi is 2*M doubles,
+ *    interleaved (Re, Im), in the caller's target order.
+ *  - Branch: log z = ln|z| + i Arg z with Arg in (-pi, pi]; a -0 imaginary
+ *    part counts as +0.  Far-field terms carry the branch of the expansion,
+ *    Log(c_T - c_S) + Log((y - x)/(c_T - c_S)) for the unique separated cell
+ *    pair (S, T), so Im Phi may differ from the principal-branch direct sum
+ *    by multiples of 2 pi u_i; Re Phi is branch-free.
+ *  - A source and a target with bitwise-equal coordinates do not interact.
+ *  - Ownership: the caller owns every buffer it passes.  fmm_plan copies the
+ *    coordinates into plan-owned device memory; the caller may free them on
+ *    return.  A plan owns all of its device memory until fmm_plan_destroy.
+ *  - Pointers are host pointers unless options.device_pointers is set, in
+ *    which case they are device pointers on the current HIP device and the
+ *    work is ordered on options.stream (hipStream_t; NULL = a stream the
+ *    plan creates).  With host pointers every call is synchronous.
+ *  - Errors are status codes, never exceptions; fmm_last_error() returns a
+ *    thread-local message for the last non-OK status.
+ *  - Plans are independent; one plan must not be evaluated concurrently
+ *    from two threads.
+ */
+#ifndef FMM2D_H
+#define FMM2D_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FMM_QUADTREE = 0,     /* square quadtree, Morton Z order (Sec. 4)          */
+    FMM_SEPTREE = 1,      /* hexagonal septree, base-7 GBT addresses (Sec. 5) */
+    FMM_TRIQUADTREE = 2   /* triangle-quadtree (Sec. 6)                       */
+} fmm_tiling;
+
+typedef enum {
+    FMM_PREC_AUTO = 0,    /* MIXED for eps >= 1e-6, FP64 below                */
+    FMM_PREC_FP64 = 1,    /* every step in FP64                               */
+    FMM_PREC_MIXED = 2    /* M2L as BF16x3 split products on MFMA with FP32
+                             accumulation, P2P in FP32 with compensated sums;
+                             monopole/log terms, P2M, M2M, L2L, L2P in FP64   */
+} fmm_precision;
+
+typedef enum {
+    FMM_OK = 0,
+    FMM_E_INVALID = 1,    /* null pointer with n > 0, n < 0, eps not in
+                             (0, 0.5), bad tiling, non-finite coordinate,
+                             option out of range                             */
+    FMM_E_DOMAIN = 2,     /* an explicit geometry does not cover the points  */
+    FMM_E_NOMEM = 3,      /* device allocation failed or budget exceeded     */
+    FMM_E_DEVICE = 4,     /* a HIP runtime call failed                        */
+    FMM_E_BUSY = 5        /* serving: result not ready yet                    */
+} fmm_status;
+
+typedef struct fmm_plan_s *fmm_plan_t;
+
+/* Plan options.  Call fmm_options_default first, then override fields. */
+typedef struct {
+    uint32_t struct_size;    /* sizeof(fmm_options)                           */
+    int32_t leaf_size;       /* target mean points per occupied leaf (64)     */
+    int32_t lmax;            /* leaf level; -1 = from leaf_size               */
+    int32_t p;               /* expansion order; -1 = from eps and the
+                                tiling's separation ratio (Sec. 8)            */
+    int32_t precision;       /* fmm_precision                                 */
+    int32_t has_geometry;    /* 1 = use geometry[] and lmax as given          */
+    double geometry[3];      /* origin x, origin y, scale: quadtree = lower-
+                                left corner and side of the root square;
+                                septree = centre of leaf hexagon 0 and leaf
+                                circumradius; triangle-quadtree = root
+                                centroid and leaf circumradius                */
+    void *stream;            /* hipStream_t for device-pointer calls          */
+    int32_t device_pointers; /* 1 = all data pointers are device pointers     */
+    int32_t reserved;
+} fmm_options;
+
+/* Read-only summary of a plan. */
+typedef struct {
+    int32_t tiling;
+    int32_t lmax;            /* leaf level L (root = level 0)                 */
+    int32_t p;               /* expansion order                               */
+    int32_t precision;       /* resolved precision (FP64 or MIXED)            */
+    double geometry[3];      /* as in fmm_options                             */
+    int64_t n_src, n_tgt;
+    int32_t targets_are_sources;
+    int32_t e4_width;        /* slots per M2L list: 27 / 42 / 39              */
+    int64_t n_cells[32];     /* occupied cells per level (sources or targets) */
+    int64_t n_m2l_pairs;     /* nonempty M2L (E4) cell pairs, all levels      */
+    int64_t n_near_pairs;    /* source-target point pairs in the near field   */
+    int64_t device_bytes;    /* device memory held by the plan                */
+    double plan_ms;          /* GPU time of the last fmm_plan                 */
+    double eval_ms;          /* GPU time of the last fmm_eval                 */
+    double stage_ms[8];      /* last eval: upward, M2L, downward, near+L2P,
+                                (rest reserved)                               */
+} fmm_plan_info;
+
+/* Fill *opt with defaults: leaf_size 64, lmax -1, p -1, AUTO precision,
+ * host pointers, no explicit geometry. */
+fmm_status fmm_options_default(fmm_options *opt);
+
+/* Build a plan (Secs. 4-6: CellIndex keys at the leaf level, sort, per-level
+ * occupied cells, Neighbors and NeighborsE4 lists).  src: n_src complex128
+ * points; tgt: n_tgt complex128 points (tgt may equal src, in which case the
+ * sorted arrays are shared).  eps in (0, 0.5) selects p when opt->p < 0.
+ * opt may be NULL (defaults).  On success *out holds the plan. */
+fmm_status fmm_plan(fmm_tiling tiling, const double *src, int64_t n_src, const double *tgt,
+                    int64_t n_tgt, double eps, const fmm_options *opt, fmm_plan_t *out);
+
+/* Evaluate Phi for strengths u (n_src doubles) into phi (2*n_tgt doubles):
+ * P2M, M2M, M2L, L2L, L2P and the P2P near field (GR87 Lemmas 2.1-2.5).
+ * Allocates nothing.  n_src = 0 gives Phi = 0. */
+fmm_status fmm_eval(fmm_plan_t plan, const double *u, double *phi);
+
+/* Summary of a plan.  info->n_cells holds lmax+1 valid entries. */
+fmm_status fmm_plan_info_get(fmm_plan_t plan, fmm_plan_info *info);
+
+/* Export the plan's tree for parity checks (host buffers, caller-sized):
+ *  src_keys[n_src], tgt_keys[n_tgt]: leaf keys (base 4 or 7) in caller order;
+ *  src_perm[n_src], tgt_perm[n_tgt]: original index of each sorted position.
+ * Any pointer may be NULL. */
+fmm_status fmm_plan_export_points(fmm_plan_t plan, int64_t *src_keys, int64_t *tgt_keys,
+                                  int64_t *src_perm, int64_t *tgt_perm);
+
+/* Export level `level` (0..lmax), n = info.n_cells[level] cells in key
+ * order: keys[n]; occupancy[n] (bit 0 = holds sources, bit 1 = targets);
+ * src_range[2n] and tgt_range[2n] ([begin, end) into the sorted order);
+ * e4[n * e4_width]: keys of the source-occupied NeighborsE4 cells of every
+ * target-occupied cell (-1 padded, ascending); near[n * 13]: keys of the
+ * source-occupied cells among {n} u Neighbors(n) at the leaf level (-1
+ * padded, ascending; only filled when level == lmax).  Any pointer may be
+ * NULL. */
+fmm_status fmm_plan_export_level(fmm_plan_t plan, int32_t level, int64_t *keys,
+                                 int32_t *occupancy, int64_t *src_range, int64_t *tgt_range,
+                                 int64_t *e4, int64_t *near);
+
+/* Release every resource of the plan.  NULL is a no-op. */
+void fmm_plan_destroy(fmm_plan_t plan);
+
+/* Thread-local message for the last non-OK status ("" if none). */
+const char *fmm_last_error(void);
+
+/* Expansion order from eps: p = ceil(ln eps / ln q) - 1 with the tiling's
+ * separation ratio q = max(r/R, 1/(1 + rho/r)) (Sec. 8 error bounds; septree
+ * q measured on GBT aggregates).  Returns -1 for bad arguments. */
+int32_t fmm_order_for_eps(fmm_tiling tiling, double eps);
+
+/* ------------------------------------------------------------------ serving
+ * A request loop that admits independent solves by free device memory,
+ * keeps their plans resident, and runs the same phase of every admitted
+ * request in one batched kernel launch per phase (continuous batching).
+ * Results are bitwise identical to the same request solved alone.       */
+typedef struct fmm_server_s *fmm_server_t;
+
+typedef struct {
+    uint32_t struct_size;
+    int64_t hbm_budget_bytes;   /* admission budget for resident plans        */
+    int32_t max_inflight;       /* maximum admitted requests at once          */
+    int32_t leaf_size;          /* as fmm_options.leaf_size                   */
+} fmm_server_options;
+
+typedef struct {
+    int32_t tiling;             /* fmm_tiling                                 */
+    int32_t precision;          /* fmm_precision                              */
+    double eps;
+    int64_t n_src, n_tgt;
+    const double *src;          /* host complex128 points (copied on submit)  */
+    const double *tgt;          /* NULL = targets are the sources             */
+    const double *u;            /* host strengths (copied on submit)          */
+} fmm_request;
+
+typedef struct {
+    fmm_status status;          /* OK, or the request's error                 */
+    int32_t p, lmax;
+    double t_submit, t_admit, t_start, t_end;  /* seconds, steady clock       */
+} fmm_result;
+
+fmm_status fmm_server_create(const fmm_server_options *opt, fmm_server_t *out);
+/* Queue a request; returns its ticket.  Inputs are copied before return. */
+fmm_status fmm_submit(fmm_server_t s, const fmm_request *req, uint64_t *ticket);
+/* FMM_E_BUSY until the request is done; then copies Phi (2*n_tgt doubles,
+ * host) into phi (may be NULL) and fills *res.  A ticket is consumed by the
+ * first non-BUSY poll. */
+fmm_status fmm_poll(fmm_server_t s, uint64_t ticket, double *phi, fmm_result *res);
+/* Block until every queued request is done. */
+fmm_status fmm_server_drain(fmm_server_t s);
+fmm_status fmm_server_destroy(fmm_server_t s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FMM2D_H */

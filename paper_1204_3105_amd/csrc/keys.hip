@@ -1,0 +1,261 @@
+// keys.hip -- bounding box, leaf-key assignment (CellIndex) and point gather.
+//
+// CellIndex for the three tilings (paper Sec. 4, Sec. 5 "CellIndex",
+// Sec. 6 "CellIndex").  Keys are integers whose base-4 (quadtree,
+// triangle-quadtree) or base-7 (septree) digits are the hierarchical
+// address, most significant digit = level 1, so the level-l key is a prefix.
+//
+// The floating-point decisions (floor of the scaled offset; nearest of the
+// candidate lattice centres) follow one fixed expression order with no FMA
+// contraction (this file is compiled with -ffp-contract=off), so the integer
+// keys are reproducible bit for bit on any IEEE FP64 machine.  The integer
+// parts are done in exact integer arithmetic: Morton interleave for the
+// quadtree, Eisenstein-integer division by beta = 1 + 2w for the septree's
+// GBT digits (w = e^{i pi/3}), integer triangle-centre units for the
+// triangle-quadtree.
+#include "fmm_internal.h"
+
+namespace fmm {
+
+// ------------------------------------------------------------ bounding box
+__global__ void k_bbox(const double *__restrict__ pts, int64_t n, double *__restrict__ partial)
+{
+    double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY, bad = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        double x = pts[2 * i], y = pts[2 * i + 1];
+        if (!isfinite(x) || !isfinite(y)) {
+            bad += 1.0;
+            continue;
+        }
+        mnx = fmin(mnx, x);
+        mxx = fmax(mxx, x);
+        mny = fmin(mny, y);
+        mxy = fmax(mxy, y);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        mnx = fmin(mnx, __shfl_xor(mnx, o));
+        mxx = fmax(mxx, __shfl_xor(mxx, o));
+        mny = fmin(mny, __shfl_xor(mny, o));
+        mxy = fmax(mxy, __shfl_xor(mxy, o));
+        bad += __shfl_xor(bad, o);
+    }
+    __shared__ double sh[5][16];
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+        sh[0][w] = mnx;
+        sh[1][w] = mxx;
+        sh[2][w] = mny;
+        sh[3][w] = mxy;
+        sh[4][w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int nw = blockDim.x >> 6;
+        for (int k = 1; k < nw; ++k) {
+            sh[0][0] = fmin(sh[0][0], sh[0][k]);
+            sh[1][0] = fmax(sh[1][0], sh[1][k]);
+            sh[2][0] = fmin(sh[2][0], sh[2][k]);
+            sh[3][0] = fmax(sh[3][0], sh[3][k]);
+            sh[4][0] += sh[4][k];
+        }
+        for (int k = 0; k < 5; ++k) partial[5 * blockIdx.x + k] = sh[k][0];
+    }
+}
+
+__global__ void k_bbox_final(const double *__restrict__ partial, int nparts, double *__restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY, bad = 0.0;
+    for (int k = 0; k < nparts; ++k) {
+        mnx = fmin(mnx, partial[5 * k]);
+        mxx = fmax(mxx, partial[5 * k + 1]);
+        mny = fmin(mny, partial[5 * k + 2]);
+        mxy = fmax(mxy, partial[5 * k + 3]);
+        bad += partial[5 * k + 4];
+    }
+    // Accumulate into out[0..4] (callers run this once per point set).
+    out[0] = fmin(out[0], mnx);
+    out[1] = fmax(out[1], mxx);
+    out[2] = fmin(out[2], mny);
+    out[3] = fmax(out[3], mxy);
+    out[4] += bad;
+}
+
+void launch_bbox(const double *pts, int64_t n, double *partial, int nblocks, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bbox, dim3(nblocks), dim3(256), 0, s, pts, n, partial);
+}
+
+void launch_bbox_final(const double *partial, int nparts, double *out4, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, partial, nparts, out4);
+}
+
+// ------------------------------------------------------------------ keys
+__device__ __forceinline__ uint32_t spread16(uint32_t v)
+{
+    v &= 0xffffu;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+// Quadtree: cell (floor((x-ox)/h), floor((y-oy)/h)) at the leaf level,
+// h = side / 2^L; Morton key with x in the even bits.
+__device__ int64_t key_quad(const GeoParams &g, double x, double y)
+{
+    double h = ldexp(g.size, -g.L);
+    double fx = floor((x - g.ox) / h);
+    double fy = floor((y - g.oy) / h);
+    double n = ldexp(1.0, g.L);
+    if (!(fx >= 0.0 && fx < n && fy >= 0.0 && fy < n)) return -1;
+    return (int64_t)(spread16((uint32_t)fx) | (spread16((uint32_t)fy) << 1));
+}
+
+// Eisenstein value z = a + b w -> GBT digits (least significant first) by
+// repeated division by beta.  The residue of z modulo beta is (a + 3b) mod 7
+// (w = 3 mod beta); residue -> digit k whose value w^(k-1) has that residue.
+__device__ __forceinline__ int64_t gbt_encode(int64_t a, int64_t b, int ndig)
+{
+    // residue r -> digit, and the digit's (a, b) value
+    const int rdig[7] = {0, 1, 3, 2, 5, 6, 4};
+    const int da[7] = {0, 1, 0, -1, -1, 0, 1};
+    const int db[7] = {0, 0, 1, 1, 0, -1, -1};
+    int64_t key = 0, pw = 1;
+    for (int i = 0; i < ndig; ++i) {
+        int64_t r = (a + 3 * b) % 7;
+        if (r < 0) r += 7;
+        int d = rdig[r];
+        a -= da[d];
+        b -= db[d];
+        int64_t na = 3 * a + 2 * b;   // z * conj(beta), conj(beta) = 3 - 2w
+        int64_t nb = b - 2 * a;
+        a = na / 7;
+        b = nb / 7;
+        key += d * pw;
+        pw *= 7;
+    }
+    if (a != 0 || b != 0) return -1;   // needs more than ndig digits
+    return key;
+}
+
+// Septree: change of basis (b, c) = (2X/(3r), (sqrt3 Y - X)/(3r)), the four
+// floor/ceil candidates, nearest lattice centre (3 r b/2, r sqrt3 (2c+b)/2)
+// by squared distance with strict '<' in the listed order, then GBT digits.
+__device__ int64_t key_sept(const GeoParams &g, double x, double y)
+{
+    const double r = g.size, s3 = g.s3;
+    double X = x - g.ox, Y = y - g.oy;
+    double b = (2.0 * X) / (3.0 * r);
+    double c = (s3 * Y - X) / (3.0 * r);
+    if (!isfinite(b) || !isfinite(c) || fabs(b) > 1e12 || fabs(c) > 1e12) return -1;
+    double bf = floor(b), bc = ceil(b), cf = floor(c), cc = ceil(c);
+    double cb[4] = {bf, bc, bf, bc};
+    double ccc[4] = {cf, cf, cc, cc};
+    int best = 0;
+    double bestd = INFINITY;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double px = (3.0 * r * cb[i]) / 2.0;
+        double py = (r * s3 * (2.0 * ccc[i] + cb[i])) / 2.0;
+        double dx = X - px, dy = Y - py;
+        double d2 = dx * dx + dy * dy;
+        if (d2 < bestd) {
+            bestd = d2;
+            best = i;
+        }
+    }
+    return gbt_encode((int64_t)cb[best], (int64_t)ccc[best], g.L);
+}
+
+// Triangle-quadtree: root triangle check, then descend L levels choosing
+// the nearest of the four child centroids (strict '<', types 0..3).
+// Centres are integer units (U, V): x = U (sqrt3/2) r, y = V r/2.
+__device__ int64_t key_tri(const GeoParams &g, double x, double y)
+{
+    const double r = g.size, s3 = g.s3;
+    double X = x - g.ox, Y = y - g.oy;
+    double rho0 = ldexp(r, g.L - 1);
+    double hs3 = s3 / 2.0;
+    if (!isfinite(X) || !isfinite(Y)) return -1;
+    if (Y < -rho0 || hs3 * X + 0.5 * Y > rho0 || -hs3 * X + 0.5 * Y > rho0) return -1;
+    double ax = (s3 * r) / 2.0, ay = r / 2.0;
+    int64_t U = 0, V = 0, key = 0;
+    int up = 1;
+    for (int i = 1; i <= g.L; ++i) {
+        int64_t R = (int64_t)1 << (g.L - i);
+        int64_t cu[4] = {U, U, U - R, U + R};
+        int64_t cv[4] = {V, V + 2 * up * R, V - up * R, V - up * R};
+        int best = 0;
+        double bestd = INFINITY;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            double px = (double)cu[t] * ax, py = (double)cv[t] * ay;
+            double dx = X - px, dy = Y - py;
+            double d2 = dx * dx + dy * dy;
+            if (d2 < bestd) {
+                bestd = d2;
+                best = t;
+            }
+        }
+        U = cu[best];
+        V = cv[best];
+        if (best == 0) up = -up;
+        key = key * 4 + best;
+    }
+    return key;
+}
+
+__global__ void k_keys(GeoParams g, const double *__restrict__ pts, int64_t n,
+                       uint32_t *__restrict__ key, int32_t *__restrict__ idx,
+                       int32_t *__restrict__ bad)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double x = pts[2 * i], y = pts[2 * i + 1];
+    int64_t k;
+    if (g.tiling == kQuad)
+        k = key_quad(g, x, y);
+    else if (g.tiling == kSept)
+        k = key_sept(g, x, y);
+    else
+        k = key_tri(g, x, y);
+    if (k < 0) {
+        atomicAdd(bad, 1);
+        k = 0;
+    }
+    key[i] = (uint32_t)k;
+    idx[i] = (int32_t)i;
+}
+
+void launch_keys(const GeoParams &g, const double *pts, int64_t n, uint32_t *key, int32_t *idx,
+                 int32_t *bad_count, hipStream_t s)
+{
+    if (n <= 0) return;
+    int64_t nb = (n + 255) / 256;
+    hipLaunchKernelGGL(k_keys, dim3((unsigned)nb), dim3(256), 0, s, g, pts, n, key, idx,
+                       bad_count);
+}
+
+__global__ void k_gather_points(const double *__restrict__ pts, const int32_t *__restrict__ perm,
+                                int64_t n, double *__restrict__ x, double *__restrict__ y)
+{
+    int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    int64_t i = perm[j];
+    x[j] = pts[2 * i];
+    y[j] = pts[2 * i + 1];
+}
+
+void launch_gather_points(const double *pts, const int32_t *perm, int64_t n, double *x, double *y,
+                          hipStream_t s)
+{
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_gather_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pts,
+                       perm, n, x, y);
+}
+
+}  // namespace fmm

@@ -1,0 +1,719 @@
+// plan.hip -- host side of the C ABI: planner, plan/eval drivers, exports,
+// error reporting and the device-memory pool.
+//
+// Planner (paper Sec. 8 for p; the leaf-level rule targets a mean number of
+// points per occupied leaf, the S_opt idea of Sec. 8 with the density given
+// by the caller):
+//   quadtree          root square = bounding square of the points, side
+//                     w (1 + 2^-20) from the lower-left corner;
+//                     L = smallest with max(N, M) / 4^L <= leaf_size.
+//   septree           leaf hexagon 0 at the bounding-box centre; for each L
+//                     the leaf radius r that makes the root aggregate's
+//                     inscribed disk (c_L sqrt7^L r sqrt3) cover the box's
+//                     circumscribed disk; L = smallest whose mean occupancy
+//                     (box area / leaf area) is <= leaf_size.
+//   triangle-quadtree upright root triangle at the box centre whose inscribed
+//                     disk covers the box's circumscribed disk; L as above.
+//   p = ceil(ln eps / ln q) - 1, q = max(r/R, 1/(1 + rho/r)) of the tiling.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fmm_internal.h"
+#include "fmm_tables.h"
+
+namespace fmm {
+
+// ------------------------------------------------------------ errors
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+
+static fmm_status fail(fmm_status st, const std::string &msg)
+{
+    g_err = msg;
+    return st;
+}
+
+// ------------------------------------------------------------ pool
+// Device memory is taken in 2 MiB granules and cached on release, keyed by
+// size, so repeated plans of similar size reuse their buffers.
+struct PoolBlock {
+    void *p;
+    size_t bytes;
+    int device;
+};
+static std::mutex g_pool_mu;
+static std::vector<PoolBlock> g_pool;
+static size_t g_pool_cached = 0;
+static const size_t kPoolCap = (size_t)16 << 30;
+
+static size_t round_granule(size_t b) { return (b + ((size_t)2 << 20) - 1) & ~(((size_t)2 << 20) - 1); }
+
+void *dev_alloc(size_t bytes, int *err)
+{
+    bytes = round_granule(bytes ? bytes : 1);
+    int dev = 0;
+    hipGetDevice(&dev);
+    {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        int best = -1;
+        for (int i = 0; i < (int)g_pool.size(); ++i) {
+            const PoolBlock &b = g_pool[i];
+            if (b.device == dev && b.bytes >= bytes && b.bytes <= 2 * bytes &&
+                (best < 0 || b.bytes < g_pool[best].bytes))
+                best = i;
+        }
+        if (best >= 0) {
+            void *p = g_pool[best].p;
+            g_pool_cached -= g_pool[best].bytes;
+            g_pool.erase(g_pool.begin() + best);
+            return p;
+        }
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        // release the cache and retry once
+        {
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            for (auto &b : g_pool) hipFree(b.p);
+            g_pool.clear();
+            g_pool_cached = 0;
+        }
+        (void)hipGetLastError();
+        e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            if (err) *err = 1;
+            return nullptr;
+        }
+    }
+    return p;
+}
+
+void dev_free(void *p, size_t bytes)
+{
+    if (!p) return;
+    bytes = round_granule(bytes ? bytes : 1);
+    int dev = 0;
+    hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (g_pool_cached + bytes > kPoolCap) {
+        hipFree(p);
+        return;
+    }
+    g_pool.push_back({p, bytes, dev});
+    g_pool_cached += bytes;
+}
+
+// ------------------------------------------------------------ plan storage
+struct PlanImpl : Plan {
+    std::vector<std::pair<void *, size_t>> allocs;
+    int64_t device_bytes = 0;
+    int64_t n_items_cap = 0;
+    void *scratch = nullptr;
+    size_t scratch_sz = 0;
+};
+
+template <typename T>
+static T *take(PlanImpl *P, int64_t count, int *err)
+{
+    size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    void *p = dev_alloc(bytes, err);
+    if (p) {
+        P->allocs.push_back({p, bytes});
+        P->device_bytes += (int64_t)round_granule(bytes);
+    }
+    return (T *)p;
+}
+
+static void release(PlanImpl *P)
+{
+    if (P->stream) hipStreamSynchronize(P->stream);
+    for (auto &a : P->allocs) dev_free(a.first, a.second);
+    P->allocs.clear();
+    for (auto &e : P->ev)
+        if (e) hipEventDestroy(e);
+    if (P->own_stream && P->stream) hipStreamDestroy(P->stream);
+}
+
+// ------------------------------------------------------------ rules
+static const double kQ[3] = {
+    0.54691816067802259,   // quadtree 1/(1 + 2(sqrt2 - 1))
+    0.5244,                // septree, GBT aggregates (coarse-level rho/r = 0.907)
+    0.60762521851393328    // triangle-quadtree 1/(sqrt7 - 1)
+};
+
+static int order_for(int tiling, double eps)
+{
+    if (!(eps > 0.0 && eps < 0.5) || tiling < 0 || tiling > 2) return -1;
+    int p = (int)ceil(log(eps) / log(kQ[tiling])) - 1;
+    return std::max(1, std::min(p, kMaxP));
+}
+
+struct BBox {
+    double x0, x1, y0, y1;
+};
+
+static void choose_geometry(int tiling, const BBox &bb, int64_t nmax, int leaf, int lmax_opt,
+                            GeoParams &g)
+{
+    double cx = 0.5 * (bb.x0 + bb.x1), cy = 0.5 * (bb.y0 + bb.y1);
+    double wx = bb.x1 - bb.x0, wy = bb.y1 - bb.y0;
+    double rho = 0.5 * hypot(wx, wy);
+    if (!(rho > 0.0)) rho = 1.0;
+    double area = std::max(wx * wy, 0.01 * M_PI * rho * rho);
+    double dens = (double)std::max<int64_t>(nmax, 1);
+    g.tiling = tiling;
+    g.s3 = sqrt(3.0);
+    if (tiling == kQuad) {
+        double w = std::max(wx, wy);
+        if (!(w > 0.0)) w = 1.0;
+        g.ox = bb.x0;
+        g.oy = bb.y0;
+        g.size = w * (1.0 + ldexp(1.0, -20));
+        int L = 0;
+        while (L < 15 && dens / ldexp(1.0, 2 * L) > leaf) ++L;
+        g.L = lmax_opt >= 0 ? lmax_opt : L;
+    } else if (tiling == kSept) {
+        g.ox = cx;
+        g.oy = cy;
+        double rr = rho * (1.0 + 1e-9);
+        int Lmax = (int)(sizeof(kSeptInscribed) / sizeof(double)) - 1;
+        int L = 0;
+        double r = 0;
+        for (L = 0; L <= Lmax; ++L) {
+            r = rr / (kSeptInscribed[L] * (1.0 - 1e-9) * pow(sqrt(7.0), L) * sqrt(3.0));
+            double leaf_area = 1.5 * sqrt(3.0) * r * r;
+            if (dens / std::max(1.0, area / leaf_area) <= leaf || L == Lmax) break;
+        }
+        if (lmax_opt >= 0) {
+            L = std::min(lmax_opt, Lmax);
+            r = rr / (kSeptInscribed[L] * (1.0 - 1e-9) * pow(sqrt(7.0), L) * sqrt(3.0));
+        }
+        g.L = L;
+        g.size = r;
+    } else {
+        g.ox = cx;
+        g.oy = cy;
+        double rr = rho * (1.0 + 1e-9);
+        int L = 0;
+        double r = 0;
+        for (L = 0; L <= 15; ++L) {
+            r = 2.0 * rr / ldexp(1.0, L);
+            double leaf_area = 0.75 * sqrt(3.0) * r * r;
+            if (dens / std::max(1.0, area / leaf_area) <= leaf || L == 15) break;
+        }
+        if (lmax_opt >= 0) {
+            L = lmax_opt;
+            r = 2.0 * rr / ldexp(1.0, L);
+        }
+        g.L = L;
+        g.size = r;
+    }
+}
+
+static double level_scale(const GeoParams &g, int l)
+{
+    if (g.tiling == kQuad) return ldexp(g.size, -l);
+    if (g.tiling == kSept) return g.size * sqrt(3.0) * pow(sqrt(7.0), g.L - l);
+    return ldexp(g.size, g.L - l);
+}
+
+static int key_bits(const GeoParams &g)
+{
+    if (g.tiling == kSept) {
+        double k = 1;
+        for (int i = 0; i < g.L; ++i) k *= 7.0;
+        int b = 0;
+        while ((double)((uint64_t)1 << b) < k) ++b;
+        return b;
+    }
+    return 2 * g.L;
+}
+
+static float elapsed(hipEvent_t a, hipEvent_t b)
+{
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.f;
+    }
+    return ms;
+}
+
+// ------------------------------------------------------------ plan
+static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t n_src,
+                             const double *tgt, int64_t n_tgt, double eps, const fmm_options &o)
+{
+    int err = 0;
+    hipStream_t s = P->stream;
+    const bool same = P->same;
+    // Device copies of the inputs.
+    const double *dsrc = src, *dtgt = tgt;
+    if (!o.device_pointers) {
+        double *a = take<double>(P, 2 * std::max<int64_t>(n_src, 1), &err);
+        double *b = same ? a : take<double>(P, 2 * std::max<int64_t>(n_tgt, 1), &err);
+        if (err) return fail(FMM_E_NOMEM, "device allocation failed (inputs)");
+        if (n_src) FMM_HIP_CHECK(hipMemcpyAsync(a, src, 16 * n_src, hipMemcpyHostToDevice, s));
+        if (!same && n_tgt)
+            FMM_HIP_CHECK(hipMemcpyAsync(b, tgt, 16 * n_tgt, hipMemcpyHostToDevice, s));
+        dsrc = a;
+        dtgt = b;
+    }
+    FMM_HIP_CHECK(hipEventRecord(P->ev[0], s));
+
+    // Bounding box (sources and targets), also flags non-finite input.
+    const int nbb = 256;
+    double *bbp = take<double>(P, 5 * 2 * nbb + 8, &err);
+    if (err) return fail(FMM_E_NOMEM, "device allocation failed (bbox)");
+    double *bbo = bbp + 10 * nbb;
+    double init[5] = {INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
+    FMM_HIP_CHECK(hipMemcpyAsync(bbo, init, sizeof(init), hipMemcpyHostToDevice, s));
+    if (n_src) {
+        launch_bbox(dsrc, n_src, bbp, nbb, s);
+        launch_bbox_final(bbp, nbb, bbo, s);
+    }
+    if (n_tgt && !same) {
+        launch_bbox(dtgt, n_tgt, bbp + 5 * nbb, nbb, s);
+        launch_bbox_final(bbp + 5 * nbb, nbb, bbo, s);
+    }
+    double hb[5];
+    FMM_HIP_CHECK(hipMemcpyAsync(hb, bbo, sizeof(hb), hipMemcpyDeviceToHost, s));
+    FMM_HIP_CHECK(hipStreamSynchronize(s));
+    if (hb[4] > 0) return fail(FMM_E_INVALID, "non-finite coordinate in the input");
+    if (n_src + n_tgt == 0) hb[0] = hb[2] = 0.0, hb[1] = hb[3] = 1.0;
+
+    GeoParams &g = P->geo;
+    if (o.has_geometry) {
+        if (o.lmax < 0 || o.lmax > kMaxL) return fail(FMM_E_INVALID, "explicit geometry needs 0 <= lmax <= 16");
+        if (!(o.geometry[2] > 0.0) || !isfinite(o.geometry[0]) || !isfinite(o.geometry[1]))
+            return fail(FMM_E_INVALID, "bad explicit geometry");
+        g.tiling = tiling;
+        g.L = o.lmax;
+        g.ox = o.geometry[0];
+        g.oy = o.geometry[1];
+        g.size = o.geometry[2];
+        g.s3 = sqrt(3.0);
+    } else {
+        BBox bb{hb[0], hb[1], hb[2], hb[3]};
+        choose_geometry(tiling, bb, std::max(n_src, n_tgt), o.leaf_size, o.lmax, g);
+    }
+    if (g.L > kMaxL || (tiling == kSept && g.L > 11))
+        return fail(FMM_E_INVALID, "tree too deep for 32-bit keys");
+    P->p = o.p > 0 ? std::min(o.p, kMaxP) : order_for(tiling, eps);
+    for (int l = 0; l <= g.L; ++l) P->scale[l] = level_scale(g, l);
+
+    // Keys and sort.
+    const int64_t N = n_src, M = n_tgt;
+    P->skey = take<uint32_t>(P, N, &err);
+    P->sperm = take<int32_t>(P, N, &err);
+    P->sx = take<double>(P, N, &err);
+    P->sy = take<double>(P, N, &err);
+    if (same) {
+        P->tkey = P->skey;
+        P->tperm = P->sperm;
+        P->tx = P->sx;
+        P->ty = P->sy;
+    } else {
+        P->tkey = take<uint32_t>(P, M, &err);
+        P->tperm = take<int32_t>(P, M, &err);
+        P->tx = take<double>(P, M, &err);
+        P->ty = take<double>(P, M, &err);
+    }
+    int32_t *bad = take<int32_t>(P, 8, &err);
+    size_t rtmp = std::max(radix_tmp_bytes(N), radix_tmp_bytes(M));
+    char *sort_tmp = take<char>(P, (int64_t)rtmp, &err);
+    if (err) return fail(FMM_E_NOMEM, "device allocation failed (keys)");
+    FMM_HIP_CHECK(hipMemsetAsync(bad, 0, 8 * sizeof(int32_t), s));
+    launch_keys(g, dsrc, N, P->skey, P->sperm, bad, s);
+    if (!same) launch_keys(g, dtgt, M, P->tkey, P->tperm, bad, s);
+    int bits = key_bits(g);
+    radix_sort(P->skey, P->sperm, N, bits, sort_tmp, s);
+    if (!same) radix_sort(P->tkey, P->tperm, M, bits, sort_tmp, s);
+    launch_gather_points(dsrc, P->sperm, N, P->sx, P->sy, s);
+    if (!same) launch_gather_points(dtgt, P->tperm, M, P->tx, P->ty, s);
+
+    // Levels: dense key spaces.
+    int64_t dense_total = 0;
+    for (int l = 0; l <= g.L; ++l) {
+        int64_t K = 1;
+        for (int k = 0; k < l; ++k) K *= base_of(tiling);
+        P->lev[l].K = K;
+        P->lev[l].dense_off = dense_total;
+        dense_total += K;
+    }
+    P->dense_total = dense_total;
+    int32_t *flags = take<int32_t>(P, 2 * dense_total + 1, &err);
+    P->dense = take<int32_t>(P, dense_total, &err);
+    char *scan_tmp = take<char>(P, (int64_t)scan_tmp_bytes(std::max<int64_t>(dense_total, 256 * 1024)) + 4096, &err);
+    int32_t *total = take<int32_t>(P, 4, &err);
+    if (err) return fail(FMM_E_NOMEM, "device allocation failed (levels)");
+    FMM_HIP_CHECK(hipMemsetAsync(flags, 0, sizeof(int32_t) * dense_total, s));
+    launch_mark_cells(g, P->lev, P->skey, N, 1, flags, s);
+    launch_mark_cells(g, P->lev, P->tkey, M, 2, flags, s);
+    launch_flags_to_ids(flags, dense_total, s);
+    int32_t *ids = flags + dense_total;
+    scan_exclusive(ids, ids, dense_total, total, scan_tmp, s);
+    // Level boundaries -> host.
+    std::vector<int32_t> bnd(g.L + 2);
+    for (int l = 0; l <= g.L; ++l)
+        FMM_HIP_CHECK(hipMemcpyAsync(&bnd[l], ids + P->lev[l].dense_off, sizeof(int32_t),
+                                     hipMemcpyDeviceToHost, s));
+    FMM_HIP_CHECK(hipMemcpyAsync(&bnd[g.L + 1], total, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    int32_t hbad = 0;
+    FMM_HIP_CHECK(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    FMM_HIP_CHECK(hipStreamSynchronize(s));
+    if (hbad) return fail(FMM_E_DOMAIN, "points outside the root of the given geometry");
+    for (int l = 0; l <= g.L; ++l) {
+        P->lev[l].cell_off = bnd[l];
+        P->lev[l].n = bnd[l + 1] - bnd[l];
+    }
+    P->n_cells = bnd[g.L + 1];
+    const int64_t C = std::max<int64_t>(P->n_cells, 1);
+    const int64_t NL = std::max<int64_t>(P->lev[g.L].n, 1);
+
+    // Per-cell arrays.
+    P->tables = build_tables(tiling);
+    const int ew = P->tables.e4_width, nw = P->tables.near_width;
+    P->cell_key = take<uint32_t>(P, C, &err);
+    P->cell_occ = take<uint8_t>(P, C, &err);
+    P->sb = take<int32_t>(P, C, &err);
+    P->se = take<int32_t>(P, C, &err);
+    if (same) {
+        P->tb = P->sb;
+        P->te = P->se;
+    } else {
+        P->tb = take<int32_t>(P, C, &err);
+        P->te = take<int32_t>(P, C, &err);
+    }
+    P->cx = take<double>(P, C, &err);
+    P->cy = take<double>(P, C, &err);
+    P->parent = take<int32_t>(P, C, &err);
+    P->group = take<uint8_t>(P, C, &err);
+    P->e4 = take<int32_t>(P, C * ew, &err);
+    P->near = take<int32_t>(P, NL * nw, &err);
+    P->mp = take<double>(P, C * 2 * (P->p + 1), &err);
+    P->lc = take<double>(P, C * 2 * (P->p + 1), &err);
+    P->binom = take<double>(P, (2 * kMaxP + 2) * (2 * kMaxP + 2), &err);
+    P->su = take<double>(P, N, &err);
+    int32_t *ncount = take<int32_t>(P, NL + 1, &err);
+    int64_t items_cap = (M + kChunk - 1) / kChunk + NL + 1;
+    P->work_near = take<int32_t>(P, 2 * items_cap, &err);
+    unsigned long long *pairs = take<unsigned long long>(P, 2, &err);
+    if (err) return fail(FMM_E_NOMEM, "device allocation failed (cells)");
+
+    launch_compact(g, P->lev, dense_total, flags, ids, P->dense, P->cell_key, P->cell_occ, s);
+    FMM_HIP_CHECK(hipMemsetAsync(P->sb, 0, sizeof(int32_t) * C, s));
+    FMM_HIP_CHECK(hipMemsetAsync(P->se, 0, sizeof(int32_t) * C, s));
+    if (!same) {
+        FMM_HIP_CHECK(hipMemsetAsync(P->tb, 0, sizeof(int32_t) * C, s));
+        FMM_HIP_CHECK(hipMemsetAsync(P->te, 0, sizeof(int32_t) * C, s));
+    }
+    launch_cell_ranges(g, P->lev, P->skey, N, P->dense, P->sb, P->se, s);
+    if (!same) launch_cell_ranges(g, P->lev, P->tkey, M, P->dense, P->tb, P->te, s);
+    launch_cell_geometry(g, P->lev, P->n_cells, P->cell_key, P->dense, P->sb, P->se, P->tb, P->te,
+                         P->cx, P->cy, P->parent, P->group, P->cell_occ, s);
+    launch_lists(g, P->lev, P->tables, P->n_cells, P->cell_key, P->group, P->cell_occ, P->dense,
+                 P->e4, P->near, s);
+    launch_near_items(P->lev, g.L, P->tb, P->te, ncount, s);
+    scan_exclusive(ncount, ncount, P->lev[g.L].n, total, scan_tmp, s);
+    launch_near_items_fill(P->lev, g.L, P->tb, P->te, ncount, P->work_near, s);
+    FMM_HIP_CHECK(hipMemsetAsync(pairs, 0, 2 * sizeof(unsigned long long), s));
+    launch_count_pairs(P->lev, g.L, ew, nw, P->e4, P->near, P->cell_occ, P->sb, P->se, P->tb,
+                       P->te, pairs, s);
+    launch_binom(P->binom, s);
+    FMM_HIP_CHECK(hipMemsetAsync(P->lc, 0, sizeof(double) * 2 * (P->p + 1) * C, s));
+    if (P->precision == FMM_PREC_MIXED) {
+        P->sxl = take<float>(P, N, &err);
+        P->syl = take<float>(P, N, &err);
+        P->suf = take<float>(P, N, &err);
+        if (same) {
+            P->txl = P->sxl;
+            P->tyl = P->syl;
+        } else {
+            P->txl = take<float>(P, M, &err);
+            P->tyl = take<float>(P, M, &err);
+        }
+        if (err) return fail(FMM_E_NOMEM, "device allocation failed (mixed)");
+        launch_local_coords(P->sx, P->sy, P->skey, N, g, P->lev, P->dense, P->cx, P->cy, P->sxl,
+                            P->syl, s);
+        if (!same)
+            launch_local_coords(P->tx, P->ty, P->tkey, M, g, P->lev, P->dense, P->cx, P->cy,
+                                P->txl, P->tyl, s);
+        size_t mb = mixed_bytes(*P);
+        P->mixed = take<char>(P, (int64_t)mb, &err);
+        if (err) return fail(FMM_E_NOMEM, "device allocation failed (mixed M2L)");
+        if (mixed_setup(*P)) return fail(FMM_E_DEVICE, "mixed-precision setup failed");
+    }
+    int32_t hitems = 0;
+    unsigned long long hp[2] = {0, 0};
+    FMM_HIP_CHECK(hipMemcpyAsync(&hitems, total, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    FMM_HIP_CHECK(hipMemcpyAsync(hp, pairs, sizeof(hp), hipMemcpyDeviceToHost, s));
+    FMM_HIP_CHECK(hipEventRecord(P->ev[1], s));
+    FMM_HIP_CHECK(hipStreamSynchronize(s));
+    P->n_work_near = P->lev[g.L].n > 0 ? hitems : 0;
+    P->n_m2l_pairs = (int64_t)hp[0];
+    P->n_near_pairs = (int64_t)hp[1];
+    P->plan_ms = elapsed(P->ev[0], P->ev[1]);
+    if (!o.device_pointers) {
+        P->io_u = take<double>(P, std::max<int64_t>(N, 1), &err);
+        P->io_phi = take<double>(P, 2 * std::max<int64_t>(M, 1), &err);
+        if (err) return fail(FMM_E_NOMEM, "device allocation failed (io)");
+    }
+    return FMM_OK;
+}
+
+}  // namespace fmm
+
+using namespace fmm;
+
+extern "C" {
+
+fmm_status fmm_options_default(fmm_options *opt)
+{
+    if (!opt) return fail(FMM_E_INVALID, "null options");
+    memset(opt, 0, sizeof(*opt));
+    opt->struct_size = sizeof(fmm_options);
+    opt->leaf_size = 64;
+    opt->lmax = -1;
+    opt->p = -1;
+    opt->precision = FMM_PREC_AUTO;
+    return FMM_OK;
+}
+
+int32_t fmm_order_for_eps(fmm_tiling tiling, double eps) { return order_for((int)tiling, eps); }
+
+fmm_status fmm_plan(fmm_tiling tiling, const double *src, int64_t n_src, const double *tgt,
+                    int64_t n_tgt, double eps, const fmm_options *opt, fmm_plan_t *out)
+{
+    g_err.clear();
+    if (!out) return fail(FMM_E_INVALID, "null output plan pointer");
+    *out = nullptr;
+    fmm_options o;
+    fmm_options_default(&o);
+    if (opt) {
+        if (opt->struct_size != sizeof(fmm_options)) return fail(FMM_E_INVALID, "fmm_options.struct_size mismatch");
+        o = *opt;
+    }
+    if ((int)tiling < 0 || (int)tiling > 2) return fail(FMM_E_INVALID, "bad tiling");
+    if (n_src < 0 || n_tgt < 0) return fail(FMM_E_INVALID, "negative point count");
+    if (n_src > INT32_MAX / 2 || n_tgt > INT32_MAX / 2) return fail(FMM_E_INVALID, "too many points");
+    if ((n_src > 0 && !src) || (n_tgt > 0 && !tgt && tgt != src))
+        return fail(FMM_E_INVALID, "null point array");
+    if (!(eps > 0.0 && eps < 0.5)) return fail(FMM_E_INVALID, "eps must lie in (0, 0.5)");
+    if (o.leaf_size < 1) return fail(FMM_E_INVALID, "leaf_size must be >= 1");
+    if (o.p > kMaxP) return fail(FMM_E_INVALID, "p above the supported maximum (60)");
+    if (o.lmax > kMaxL) return fail(FMM_E_INVALID, "lmax above the supported maximum (16)");
+    if (o.precision < 0 || o.precision > 2) return fail(FMM_E_INVALID, "bad precision");
+    PlanImpl *P = new PlanImpl();
+    P->device_pointers = o.device_pointers != 0;
+    P->n_src = n_src;
+    P->n_tgt = n_tgt;
+    P->same = (tgt == src) && (n_tgt == n_src);
+    P->leaf_size = o.leaf_size;
+    int prec = o.precision;
+    if (prec == FMM_PREC_AUTO) prec = eps >= 1e-6 ? FMM_PREC_MIXED : FMM_PREC_FP64;
+    P->precision = prec;
+    hipGetDevice(&P->device);
+    if (o.device_pointers && o.stream) {
+        P->stream = (hipStream_t)o.stream;
+    } else {
+        if (hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete P;
+            return fail(FMM_E_DEVICE, "hipStreamCreate failed");
+        }
+        P->own_stream = true;
+    }
+    for (auto &e : P->ev) {
+        if (hipEventCreate(&e) != hipSuccess) {
+            release(P);
+            delete P;
+            return fail(FMM_E_DEVICE, "hipEventCreate failed");
+        }
+    }
+    fmm_status st = build_plan(P, (int)tiling, src, n_src, tgt, n_tgt, eps, o);
+    if (st != FMM_OK) {
+        std::string msg = g_err;
+        release(P);
+        delete P;
+        g_err = msg;
+        return st;
+    }
+    *out = (fmm_plan_t)(Plan *)P;
+    return FMM_OK;
+}
+
+fmm_status fmm_eval(fmm_plan_t plan, const double *u, double *phi)
+{
+    g_err.clear();
+    if (!plan) return fail(FMM_E_INVALID, "null plan");
+    PlanImpl *P = (PlanImpl *)(Plan *)plan;
+    if ((P->n_src > 0 && !u) || (P->n_tgt > 0 && !phi)) return fail(FMM_E_INVALID, "null array");
+    hipStream_t s = P->stream;
+    const int L = P->geo.L;
+    if (P->n_tgt == 0) return FMM_OK;
+    double *dphi = P->device_pointers ? phi : P->io_phi;
+    const double *du = P->device_pointers ? u : P->io_u;
+    if (!P->device_pointers && P->n_src)
+        FMM_HIP_CHECK(hipMemcpyAsync(P->io_u, u, sizeof(double) * P->n_src, hipMemcpyHostToDevice, s));
+    FMM_HIP_CHECK(hipEventRecord(P->ev[2], s));
+    if (P->n_src == 0) {
+        FMM_HIP_CHECK(hipMemsetAsync(dphi, 0, sizeof(double) * 2 * P->n_tgt, s));
+        FMM_HIP_CHECK(hipEventRecord(P->ev[3], s));
+        FMM_HIP_CHECK(hipEventRecord(P->ev[4], s));
+        FMM_HIP_CHECK(hipEventRecord(P->ev[5], s));
+        FMM_HIP_CHECK(hipEventRecord(P->ev[6], s));
+    } else {
+        const bool mixed = P->precision == FMM_PREC_MIXED;
+        launch_gather_u(du, P->sperm, P->n_src, P->su, mixed ? P->suf : nullptr, s);
+        launch_p2m(*P, s);
+        for (int l = L - 1; l >= 1; --l) launch_m2m(*P, l, s);
+        FMM_HIP_CHECK(hipEventRecord(P->ev[3], s));
+        if (mixed)
+            launch_m2l_mixed(*P, s);
+        else
+            launch_m2l_fp64(*P, s);
+        FMM_HIP_CHECK(hipEventRecord(P->ev[4], s));
+        for (int l = 2; l <= L; ++l) launch_l2l(*P, l, s);
+        FMM_HIP_CHECK(hipEventRecord(P->ev[5], s));
+        if (mixed)
+            launch_near_mixed(*P, dphi, s);
+        else
+            launch_near_fp64(*P, nullptr, dphi, s);
+        FMM_HIP_CHECK(hipEventRecord(P->ev[6], s));
+    }
+    FMM_HIP_CHECK(hipGetLastError());
+    if (!P->device_pointers) {
+        FMM_HIP_CHECK(hipMemcpyAsync(phi, P->io_phi, sizeof(double) * 2 * P->n_tgt,
+                                     hipMemcpyDeviceToHost, s));
+        FMM_HIP_CHECK(hipStreamSynchronize(s));
+    }
+    return FMM_OK;
+}
+
+fmm_status fmm_plan_info_get(fmm_plan_t plan, fmm_plan_info *info)
+{
+    if (!plan || !info) return fail(FMM_E_INVALID, "null argument");
+    PlanImpl *P = (PlanImpl *)(Plan *)plan;
+    memset(info, 0, sizeof(*info));
+    info->tiling = P->geo.tiling;
+    info->lmax = P->geo.L;
+    info->p = P->p;
+    info->precision = P->precision;
+    info->geometry[0] = P->geo.ox;
+    info->geometry[1] = P->geo.oy;
+    info->geometry[2] = P->geo.size;
+    info->n_src = P->n_src;
+    info->n_tgt = P->n_tgt;
+    info->targets_are_sources = P->same;
+    info->e4_width = P->tables.e4_width;
+    for (int l = 0; l <= P->geo.L && l < 32; ++l) info->n_cells[l] = P->lev[l].n;
+    info->n_m2l_pairs = P->n_m2l_pairs;
+    info->n_near_pairs = P->n_near_pairs;
+    info->device_bytes = P->device_bytes;
+    info->plan_ms = P->plan_ms;
+    if (hipEventQuery(P->ev[6]) == hipSuccess && P->n_tgt > 0) {
+        info->eval_ms = elapsed(P->ev[2], P->ev[6]);
+        info->stage_ms[0] = elapsed(P->ev[2], P->ev[3]);
+        info->stage_ms[1] = elapsed(P->ev[3], P->ev[4]);
+        info->stage_ms[2] = elapsed(P->ev[4], P->ev[5]);
+        info->stage_ms[3] = elapsed(P->ev[5], P->ev[6]);
+    }
+    (void)hipGetLastError();
+    return FMM_OK;
+}
+
+fmm_status fmm_plan_export_points(fmm_plan_t plan, int64_t *src_keys, int64_t *tgt_keys,
+                                  int64_t *src_perm, int64_t *tgt_perm)
+{
+    if (!plan) return fail(FMM_E_INVALID, "null plan");
+    PlanImpl *P = (PlanImpl *)(Plan *)plan;
+    FMM_HIP_CHECK(hipStreamSynchronize(P->stream));
+    auto one = [&](const uint32_t *dk, const int32_t *dp, int64_t n, int64_t *keys,
+                   int64_t *perm) -> fmm_status {
+        if (n <= 0) return FMM_OK;
+        std::vector<uint32_t> k(n);
+        std::vector<int32_t> p(n);
+        FMM_HIP_CHECK(hipMemcpy(k.data(), dk, 4 * n, hipMemcpyDeviceToHost));
+        FMM_HIP_CHECK(hipMemcpy(p.data(), dp, 4 * n, hipMemcpyDeviceToHost));
+        for (int64_t j = 0; j < n; ++j) {
+            if (keys) keys[p[j]] = k[j];
+            if (perm) perm[j] = p[j];
+        }
+        return FMM_OK;
+    };
+    fmm_status st = one(P->skey, P->sperm, P->n_src, src_keys, src_perm);
+    if (st) return st;
+    return one(P->tkey, P->tperm, P->n_tgt, tgt_keys, tgt_perm);
+}
+
+fmm_status fmm_plan_export_level(fmm_plan_t plan, int32_t level, int64_t *keys, int32_t *occupancy,
+                                 int64_t *src_range, int64_t *tgt_range, int64_t *e4, int64_t *near)
+{
+    if (!plan) return fail(FMM_E_INVALID, "null plan");
+    PlanImpl *P = (PlanImpl *)(Plan *)plan;
+    if (level < 0 || level > P->geo.L) return fail(FMM_E_INVALID, "level out of range");
+    FMM_HIP_CHECK(hipStreamSynchronize(P->stream));
+    const int64_t n = P->lev[level].n, off = P->lev[level].cell_off, C = P->n_cells;
+    if (n == 0) return FMM_OK;
+    std::vector<uint32_t> ck(C);
+    FMM_HIP_CHECK(hipMemcpy(ck.data(), P->cell_key, 4 * C, hipMemcpyDeviceToHost));
+    if (keys)
+        for (int64_t i = 0; i < n; ++i) keys[i] = ck[off + i];
+    if (occupancy) {
+        std::vector<uint8_t> oc(n);
+        FMM_HIP_CHECK(hipMemcpy(oc.data(), P->cell_occ + off, n, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) occupancy[i] = oc[i];
+    }
+    auto ranges = [&](const int32_t *b, const int32_t *e, int64_t *out) -> fmm_status {
+        std::vector<int32_t> hb(n), he(n);
+        FMM_HIP_CHECK(hipMemcpy(hb.data(), b + off, 4 * n, hipMemcpyDeviceToHost));
+        FMM_HIP_CHECK(hipMemcpy(he.data(), e + off, 4 * n, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) {
+            out[2 * i] = hb[i];
+            out[2 * i + 1] = he[i];
+        }
+        return FMM_OK;
+    };
+    if (src_range && ranges(P->sb, P->se, src_range)) return FMM_E_DEVICE;
+    if (tgt_range && ranges(P->tb, P->te, tgt_range)) return FMM_E_DEVICE;
+    auto lists = [&](const int32_t *d, int64_t row0, int w, int64_t *out) -> fmm_status {
+        std::vector<int32_t> h(n * w);
+        FMM_HIP_CHECK(hipMemcpy(h.data(), d + row0 * w, 4 * n * w, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i) {
+            std::vector<int64_t> v;
+            for (int k = 0; k < w; ++k)
+                if (h[i * w + k] >= 0) v.push_back(ck[h[i * w + k]]);
+            std::sort(v.begin(), v.end());
+            for (int k = 0; k < w; ++k) out[i * w + k] = k < (int)v.size() ? v[k] : -1;
+        }
+        return FMM_OK;
+    };
+    if (e4 && lists(P->e4, off, P->tables.e4_width, e4)) return FMM_E_DEVICE;
+    if (near && level == P->geo.L) {
+        std::vector<int64_t> tmp(n * P->tables.near_width);
+        if (lists(P->near, 0, P->tables.near_width, tmp.data())) return FMM_E_DEVICE;
+        for (int64_t i = 0; i < n; ++i)
+            for (int k = 0; k < kNearSlots; ++k)
+                near[i * kNearSlots + k] = k < P->tables.near_width ? tmp[i * P->tables.near_width + k] : -1;
+    }
+    return FMM_OK;
+}
+
+void fmm_plan_destroy(fmm_plan_t plan)
+{
+    if (!plan) return;
+    PlanImpl *P = (PlanImpl *)(Plan *)plan;
+    release(P);
+    delete P;
+}
+
+const char *fmm_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,237 @@
+// sort.hip -- device-wide exclusive scan and stable LSD radix sort.
+//
+// The radix sort orders (key, index) pairs by key, keeping equal keys in
+// index order, so the sorted permutation is unique.  Each pass handles 8
+// bits: per-tile digit histograms, one exclusive scan over the
+// [digit][tile] table, and a scatter in which every element's rank among
+// equal digits of its tile is found with wave64 ballots (a match mask per
+// lane) and per-wave counters in LDS.  Tiles are read in striped order, so
+// ranks follow the original order and the pass is stable.
+#include "fmm_internal.h"
+
+namespace fmm {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+// ------------------------------------------------------------------ scan
+__device__ __forceinline__ int32_t wave_incl_scan(int32_t v)
+{
+    int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+
+// Block-wide exclusive scan of one value per thread; returns the prefix and
+// writes the block total to *total.
+__device__ int32_t block_excl_scan(int32_t v, int32_t *total)
+{
+    __shared__ int32_t wsum[16];
+    __shared__ int32_t wtot;
+    int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    int32_t inc = wave_incl_scan(v);
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t acc = 0;
+        for (int k = 0; k < nw; ++k) {
+            int32_t t = wsum[k];
+            wsum[k] = acc;
+            acc += t;
+        }
+        wtot = acc;
+    }
+    __syncthreads();
+    int32_t res = inc - v + wsum[w];
+    *total = wtot;
+    __syncthreads();
+    return res;
+}
+
+__global__ void k_scan_tile_sums(const int32_t *__restrict__ in, int64_t n, int32_t *__restrict__ sums)
+{
+    int64_t base = (int64_t)blockIdx.x * kScanTile;
+    int32_t acc = 0;
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + (int64_t)k * kScanThreads + threadIdx.x;
+        if (i < n) acc += in[i];
+    }
+    int32_t tot;
+    block_excl_scan(acc, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Single-block exclusive scan of the tile sums (in place); total -> *total.
+__global__ void k_scan_sums(int32_t *__restrict__ sums, int64_t n, int32_t *__restrict__ total)
+{
+    int64_t per = (n + blockDim.x - 1) / blockDim.x;
+    int64_t b = per * threadIdx.x, e = b + per < n ? b + per : n;
+    int32_t acc = 0;
+    for (int64_t i = b; i < e; ++i) acc += sums[i];
+    int32_t tot;
+    int32_t off = block_excl_scan(acc, &tot);
+    for (int64_t i = b; i < e; ++i) {
+        int32_t t = sums[i];
+        sums[i] = off;
+        off += t;
+    }
+    if (threadIdx.x == 0 && total) *total = tot;
+}
+
+__global__ void k_scan_apply(const int32_t *__restrict__ in, int32_t *__restrict__ out, int64_t n,
+                             const int32_t *__restrict__ sums)
+{
+    // Blocked layout: thread t owns kScanItems consecutive elements.
+    int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    int32_t v[kScanItems];
+    int32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        v[k] = i < n ? in[i] : 0;
+        acc += v[k];
+    }
+    int32_t tot;
+    int32_t off = block_excl_scan(acc, &tot) + sums[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        int64_t i = base + k;
+        if (i < n) out[i] = off;
+        off += v[k];
+    }
+}
+
+size_t scan_tmp_bytes(int64_t n)
+{
+    int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    return (size_t)(tiles + 1) * sizeof(int32_t) + 256;
+}
+
+// out may alias in.  *total (device) receives the sum when non-null.
+void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *total, void *tmp,
+                    hipStream_t s)
+{
+    int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    if (tiles == 0) tiles = 1;
+    int32_t *sums = (int32_t *)tmp;
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, n,
+                       sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, sums, tiles, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, out, n,
+                       sums);
+}
+
+// ------------------------------------------------------------------ radix
+constexpr int kRadixThreads = 256;
+constexpr int kRadixItems = 8;
+constexpr int kRadixTile = kRadixThreads * kRadixItems;   // striped rounds of 256
+
+__global__ void k_radix_count(const uint32_t *__restrict__ keys, int64_t n, int shift,
+                              int32_t *__restrict__ counts, int ntiles)
+{
+    __shared__ int32_t hist[256];
+    hist[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    for (int k = 0; k < kRadixItems; ++k) {
+        int64_t i = base + (int64_t)k * kRadixThreads + threadIdx.x;
+        if (i < n) atomicAdd(&hist[(keys[i] >> shift) & 255u], 1);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
+}
+
+__global__ void k_radix_scatter(const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin,
+                                uint32_t *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
+                                int shift, const int32_t *__restrict__ offs, int ntiles)
+{
+    __shared__ int32_t run[256];        // elements of each digit already placed
+    __shared__ int32_t wcnt[4][256];    // per-wave digit counts of this round
+    __shared__ int32_t goff[256];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    goff[t] = offs[(int64_t)t * ntiles + blockIdx.x];
+    run[t] = 0;
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    for (int k = 0; k < kRadixItems; ++k) {
+        for (int q = 0; q < 4; ++q) wcnt[q][t] = 0;
+        __syncthreads();
+        int64_t i = base + (int64_t)k * kRadixThreads + t;
+        bool valid = i < n;
+        uint32_t key = valid ? kin[i] : 0u;
+        int32_t val = valid ? vin[i] : 0;
+        uint32_t d = (key >> shift) & 255u;
+        uint64_t active = __ballot(valid);
+        uint64_t match = active;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t bal = __ballot((d >> b) & 1u);
+            match &= ((d >> b) & 1u) ? bal : ~bal;
+        }
+        int rank_w = __popcll(match & lt_mask);
+        if (valid && rank_w == 0) wcnt[w][d] = __popcll(match);
+        __syncthreads();
+        if (valid) {
+            int32_t before = 0;
+            for (int q = 0; q < w; ++q) before += wcnt[q][d];
+            int64_t pos = (int64_t)goff[d] + run[d] + before + rank_w;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+    }
+}
+
+size_t radix_tmp_bytes(int64_t n)
+{
+    int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
+    if (ntiles == 0) ntiles = 1;
+    size_t counts = (size_t)256 * ntiles * sizeof(int32_t);
+    size_t bufs = (size_t)n * (sizeof(uint32_t) + sizeof(int32_t));
+    return counts + scan_tmp_bytes(256 * ntiles) + bufs + 1024;
+}
+
+static char *align256(char *p) { return (char *)(((uintptr_t)p + 255) & ~(uintptr_t)255); }
+
+void radix_sort(uint32_t *keys, int32_t *vals, int64_t n, int bits, void *tmp, hipStream_t s)
+{
+    if (n <= 1 || bits <= 0) return;
+    int ntiles = (int)((n + kRadixTile - 1) / kRadixTile);
+    char *p = align256((char *)tmp);
+    int32_t *counts = (int32_t *)p;
+    p = align256(p + (size_t)256 * ntiles * sizeof(int32_t));
+    void *stmp = p;
+    p = align256(p + scan_tmp_bytes(256 * (int64_t)ntiles));
+    uint32_t *k2 = (uint32_t *)p;
+    p = align256(p + (size_t)n * sizeof(uint32_t));
+    int32_t *v2 = (int32_t *)p;
+    uint32_t *ka = keys, *kb = k2;
+    int32_t *va = vals, *vb = v2;
+    int passes = (bits + 7) / 8;
+    for (int ps = 0; ps < passes; ++ps) {
+        int shift = 8 * ps;
+        hipLaunchKernelGGL(k_radix_count, dim3(ntiles), dim3(kRadixThreads), 0, s, ka, n, shift,
+                           counts, ntiles);
+        scan_exclusive(counts, counts, (int64_t)256 * ntiles, nullptr, stmp, s);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kRadixThreads), 0, s, ka, va, kb, vb,
+                           n, shift, counts, ntiles);
+        uint32_t *tk = ka;
+        ka = kb;
+        kb = tk;
+        int32_t *tv = va;
+        va = vb;
+        vb = tv;
+    }
+    if (ka != keys) {
+        hipMemcpyAsync(keys, ka, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);
+        hipMemcpyAsync(vals, va, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s);
+    }
+}
+
+}  // namespace fmm
