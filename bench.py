@@ -1,0 +1,207 @@
+#!/usr/bin/env python
+"""Benchmark: targets/sec of full FMM solves (plan + eval) at eps = 1e-6.
+
+Workload: N = M = 2^20 sources = targets uniform in the unit square, strengths
+U[-1,1] (seed 2), one solve per tiling (quadtree, septree, triangle-quadtree)
+per step, leaf size 64, p from eps and each tiling's separation ratio.  A step
+is plan + eval for all three tilings with the points already resident in HBM.
+
+Prints one JSON line.  `value` = 3 * M * steps / wall time of the timed
+steps.  `roofline` covers the dominant kernel (the fused L2P + P2P near
+field), timed with HIP events on the stream it runs on.  `cpu_baseline` is
+the CPU oracle timed on this host on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU lane-operations per second of one MI355X: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz (FP64 and non-packed FP32 issue at the same rate).
+LANE_OPS = 256 * 4 * 16 * 2.4e9
+# VALU instructions per source-target pair in the near-field inner loop of our
+# gfx950 build (counted from the kernels' AMD assembly; see the design notes).
+VALU_PER_PAIR = {"fp64": 98.0, "mixed": 40.0}
+HBM_PEAK = 8.0e12
+MFMA_BF16_PEAK = 2.5e15
+FP64_PEAK = 78.6e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--eps", type=float, default=1e-6)
+    ap.add_argument("--precision", default="auto", choices=["auto", "fp64", "mixed"])
+    ap.add_argument("--tilings", default="quad,sept,tri")
+    ap.add_argument("--leaf", type=int, default=64)
+    ap.add_argument("--check", type=int, default=2048, help="targets sampled for the error check")
+    ap.add_argument("--cpu-sample", type=int, default=2048)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="also time the plain FP64 form (reported under extra)")
+    return ap.parse_args()
+
+
+def run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs):
+    infos = {t: [] for t in tilings}
+    for _ in range(steps):
+        for t in tilings:
+            plan = F.Plan(t, src=pts, tgt=pts, eps=eps, precision=prec, leaf_size=leaf)
+            plan.eval(u, out=outs[t])
+            infos[t].append(plan.info())
+            plan.close()
+    return infos
+
+
+def timed(F, torch, pts, u, tilings, eps, prec, leaf, steps, warmup, outs):
+    run_steps(F, torch, pts, u, tilings, eps, prec, leaf, warmup, outs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return t1 - t0, infos
+
+
+def error_check(orc, w, outs, infos, tilings, nsample):
+    from paper_1204_3105_amd import inputs
+    idx = inputs.subsample(w.n_tgt, nsample, seed=99)
+    res = {}
+    for t in tilings:
+        inf = infos[t][-1]
+        g = orc.geom(t, inf["lmax"], *inf["geometry"])
+        ref = orc.fmm(g, inf["p"], w.xs, w.ys, w.u, w.xt[idx], w.yt[idx])
+        d1 = orc.direct_principal(w.xs, w.ys, w.u, w.xt[idx], w.yt[idx])
+        got = outs[t].cpu().numpy()[idx]
+        res[t] = {
+            "rel_l2_vs_oracle": float(np.linalg.norm(got - ref) / np.linalg.norm(ref)),
+            "rel_l2_re_vs_direct": float(np.linalg.norm(got.real - d1.real) / np.linalg.norm(d1.real)),
+            "max_abs_re_vs_direct": float(np.max(np.abs(got.real - d1.real))),
+            "sample": int(len(idx)),
+        }
+    return res
+
+
+def cpu_baseline(orc, w, infos, tilings, sample):
+    """The oracle on all sources and a seeded sample of targets, per tiling;
+    scaled to whole-job throughput: keys + tree + upward pass are counted
+    once, the per-target work (M2L chain, L2L, L2P, P2P) is scaled from the
+    sample to all M targets."""
+    from paper_1204_3105_amd import inputs
+    idx = inputs.subsample(w.n_tgt, sample, seed=7)
+    threads = orc.max_threads()
+    total = 0.0
+    detail = {}
+    for t in tilings:
+        inf = infos[t][-1]
+        g = orc.geom(t, inf["lmax"], *inf["geometry"])
+        times = [0.0] * 6
+        t0 = time.perf_counter()
+        orc.fmm(g, inf["p"], w.xs, w.ys, w.u, w.xt[idx], w.yt[idx], nthreads=threads, times=times)
+        wall = time.perf_counter() - t0
+        fixed = times[0] + times[1]
+        per_target = (wall - fixed) / len(idx)
+        est = fixed + per_target * w.n_tgt
+        detail[t] = {"sample_wall_s": wall, "fixed_s": fixed, "projected_s": est}
+        total += est
+    value = len(tilings) * w.n_tgt / total
+    return {"value": value, "unit": "targets/s", "cores": int(threads), "kind": "oracle",
+            "sample": "oracle FMM (FP64, same trees and p) on all %d sources and %d seeded "
+                      "targets per tiling; keys+tree+upward pass counted once, per-target "
+                      "work scaled to %d targets" % (w.n_src, len(idx), w.n_tgt),
+            "detail": detail}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print("bench.py runs on one GPU: this build has no multi-GPU path "
+              "(requested --gpus %d)" % a.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import oracle
+    from paper_1204_3105_amd import fmm as F
+    from paper_1204_3105_amd import inputs
+
+    F.lib()
+    dev = torch.device("cuda:0")
+    tilings = a.tilings.split(",")
+    w = inputs.uniform_square(a.n, seed=2)
+    pts = torch.tensor(w.xs + 1j * w.ys, dtype=torch.complex128, device=dev)
+    u = torch.tensor(w.u, dtype=torch.float64, device=dev)
+    outs = {t: torch.empty(a.n, dtype=torch.complex128, device=dev) for t in tilings}
+    print("bench: n=%d tilings=%s precision=%s steps=%d warmup=%d" %
+          (a.n, tilings, a.precision, a.steps, a.warmup), file=sys.stderr, flush=True)
+
+    wall, infos = timed(F, torch, pts, u, tilings, a.eps, a.precision, a.leaf, a.steps, a.warmup, outs)
+    value = len(tilings) * a.n * a.steps / wall
+    prec_used = infos[tilings[0]][-1]["precision"]
+    print("bench: timed %.3f s -> %.4g targets/s (%s)" % (wall, value, prec_used), file=sys.stderr,
+          flush=True)
+
+    # Dominant kernel: the fused L2P + P2P near-field launch.
+    near_ms = np.mean([i["stage_ms"][3] for t in tilings for i in infos[t]])
+    pairs = np.mean([i["n_near_pairs"] for t in tilings for i in infos[t]])
+    ach = pairs / (near_ms * 1e-3)
+    peak = LANE_OPS / VALU_PER_PAIR[prec_used]
+    roofline = {"bound": "alu", "kernel": "near field (L2P + P2P)", "achieved": ach / 1e9,
+                "peak": peak / 1e9, "unit": "Gpair/s", "frac": ach / peak, "traffic": None,
+                "avg_launch_ms": float(near_ms), "pairs_per_launch": float(pairs)}
+
+    per_tiling = {}
+    for t in tilings:
+        inf = infos[t]
+        per_tiling[t] = {
+            "p": inf[-1]["p"], "lmax": inf[-1]["lmax"], "precision": inf[-1]["precision"],
+            "plan_ms": float(np.mean([i["plan_ms"] for i in inf])),
+            "eval_ms": float(np.mean([i["eval_ms"] for i in inf])),
+            "stage_ms": [float(np.mean([i["stage_ms"][k] for i in inf])) for k in range(4)],
+            "n_m2l_pairs": inf[-1]["n_m2l_pairs"], "n_near_pairs": inf[-1]["n_near_pairs"],
+            "cells": int(sum(inf[-1]["n_cells"])),
+            "targets_per_s_eval_only": a.n / (np.mean([i["eval_ms"] for i in inf]) * 1e-3),
+        }
+    extra = {"per_tiling": per_tiling}
+    errs = error_check(oracle, w, outs, infos, tilings, a.check)
+    extra["errors"] = errs
+
+    if a.compare_fp64 and prec_used != "fp64":
+        wall64, infos64 = timed(F, torch, pts, u, tilings, a.eps, "fp64", a.leaf, a.steps, 1, outs)
+        extra["fp64_form"] = {"value": len(tilings) * a.n * a.steps / wall64,
+                              "ms_per_step": wall64 / a.steps * 1e3}
+
+    cpu = None
+    if not a.no_cpu_baseline:
+        print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(oracle, w, infos, tilings, a.cpu_sample)
+
+    dtype = {"fp64": "f64", "mixed": "f64/f32/bf16x3"}[prec_used]
+    line = {
+        "metric": "targets/sec at rel err 1e-6, N=1M per tiling; p50/p99 solve latency",
+        "value": value, "unit": "targets/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": wall / a.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": "N=M=2^20 uniform unit square, sources=targets, u~U[-1,1], "
+                               "eps=%g, leaf %d, one plan+eval per tiling (%s) per step" %
+                               (a.eps, a.leaf, "+".join(tilings)),
+                   "precision": prec_used, "n": a.n},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

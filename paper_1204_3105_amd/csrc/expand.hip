@@ -10,6 +10,10 @@
 // so every stored coefficient is O(1) and the translation formulas carry
 // only the dimensionless offsets.  Rows are 2(p+1) doubles, (re, im)
 // interleaved, one row per cell.
+#include <map>
+#include <mutex>
+#include <vector>
+
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -28,21 +32,32 @@ __device__ __forceinline__ cd cinv(cd a)
 
 constexpr int kBinomN = 2 * kMaxP + 2;   // table C(n, k) for n, k < kBinomN
 
-__global__ void k_binom(double *__restrict__ t)
+// Pascal's triangle C(n, k), n, k < kBinomN, built once per device on the
+// host (exact integers below 2^53, correctly rounded sums above).
+const double *device_binom(int *err)
 {
-    // one thread builds Pascal's triangle (exact integers up to 2^53, then
-    // correctly rounded sums)
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    static std::mutex mu;
+    static std::map<int, double *> tabs;
+    int dev = 0;
+    hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = tabs.find(dev);
+    if (it != tabs.end()) return it->second;
+    std::vector<double> t((size_t)kBinomN * kBinomN, 0.0);
     for (int n = 0; n < kBinomN; ++n) {
-        t[n * kBinomN] = 1.0;
-        for (int k = 1; k < kBinomN; ++k)
-            t[n * kBinomN + k] = (k > n) ? 0.0 : t[(n - 1) * kBinomN + k - 1] + (k <= n - 1 ? t[(n - 1) * kBinomN + k] : 0.0);
+        t[(size_t)n * kBinomN] = 1.0;
+        for (int k = 1; k <= n; ++k)
+            t[(size_t)n * kBinomN + k] = t[(size_t)(n - 1) * kBinomN + k - 1] + t[(size_t)(n - 1) * kBinomN + k];
     }
-}
-
-void launch_binom(double *binom, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_binom, dim3(1), dim3(64), 0, s, binom);
+    double *d = nullptr;
+    if (hipMalloc(&d, t.size() * sizeof(double)) != hipSuccess ||
+        hipMemcpy(d, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        if (err) *err = 1;
+        return nullptr;
+    }
+    tabs[dev] = d;
+    return d;
 }
 
 struct ExpParams {

@@ -18,6 +18,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/fmm2d.h"
 
@@ -115,14 +116,20 @@ struct Plan {
 
     // expansions
     double *mp = nullptr, *lc = nullptr;
-    double *binom = nullptr;       // C(n, k), n, k <= 2 kMaxP + 1
+    const double *binom = nullptr; // C(n, k), n, k <= 2 kMaxP + 1 (per device)
+
+    // M2L offset tables (lane kernel): (-1/delta)^k and Log(c_T - c_S)
+    double *m2l_pw = nullptr, *m2l_lg = nullptr;
+    int m2l_pm = 0;
 
     // mixed precision M2L operands
     void *mixed = nullptr;
+    int mixed_tiles = 0;
 
     // timing
     hipEvent_t ev[12]{};
     double plan_ms = 0, eval_ms = 0, stage_ms[8]{};
+    bool evaluated = false;
 
     // scratch for staging host inputs / outputs
     double *io_u = nullptr;
@@ -184,7 +191,12 @@ void launch_p2m(const Plan &P, hipStream_t s);
 void launch_m2m(const Plan &P, int level, hipStream_t s);
 void launch_m2l_fp64(const Plan &P, hipStream_t s);
 void launch_l2l(const Plan &P, int level, hipStream_t s);
-void launch_binom(double *binom, hipStream_t s);
+const double *device_binom(int *err);
+
+// m2l.hip
+int m2l_pm_for(int p);
+void m2l_tables(const Plan &P, int pm, std::vector<double> &pw, std::vector<double> &lg);
+void launch_m2l_lanes(const Plan &P, const double *pwt, const double *lgt, hipStream_t s);
 
 // near.hip
 void launch_near_fp64(const Plan &P, const double *dummy, double *phi, hipStream_t s);

@@ -1,0 +1,226 @@
+// m2l.hip -- multipole-to-local translation, FP64, one target cell per lane.
+//
+// Greengard & Rokhlin (1987) Lemma 2.4 in radius-scaled form.  For a source
+// cell S and target cell T on level l with delta = (c_S - c_T)/ell_l and
+// g_k = a~_k (-1/delta)^k (k = 1..p):
+//     b~_0 += a_0 Log(c_T - c_S) + sum_k g_k
+//     b~_m += delta^(-m) [ -a_0/m + sum_k C(m+k-1, k-1) g_k ],  m = 1..p.
+// The matrix C(m+k-1, k-1) is the same for every offset, so it is read from
+// uniform (scalar) memory, and the offset enters only through the powers
+// (-1/delta)^k and the log term.  Those depend on (level, target group,
+// slot) alone -- the E4 list of every cell of one group is the same set of
+// relative positions -- and are tabulated once per plan.  Each lane keeps
+// its target's p+1 local coefficients and the scaled source vector in
+// registers; the order is a compile-time bound PM >= p.
+#include <math.h>
+
+#include <vector>
+
+#include "fmm_internal.h"
+
+namespace fmm {
+
+constexpr int kBinomN = 2 * kMaxP + 2;
+
+struct M2LLaneParams {
+    int p, L, G, S, pm;
+    int64_t first, n_cells;
+    int64_t cell_off[kMaxL + 2];
+};
+
+int m2l_pm_for(int p)
+{
+    const int pms[] = {8, 16, 24, 32, 40, 48};
+    for (int v : pms)
+        if (p <= v) return v;
+    return 0;
+}
+
+// Offset of slot s of group g on level l in Cartesian units, c_S - c_T.
+static void slot_offset(const Plan &P, int l, int g, int s, double &dx, double &dy)
+{
+    const GeoParams &G = P.geo;
+    int da = P.tables.e4[g][s][0], db = P.tables.e4[g][s][1];
+    if (G.tiling == kQuad) {
+        dx = da * P.scale[l];
+        dy = db * P.scale[l];
+    } else if (G.tiling == kSept) {
+        int64_t a = da, b = db;
+        for (int k = 0; k < G.L - l; ++k) {   // times beta = 1 + 2w
+            int64_t na = a - 2 * b, nb = 2 * a + 3 * b;
+            a = na;
+            b = nb;
+        }
+        const double r = G.size;
+        dx = (3.0 * r * (double)a) / 2.0;
+        dy = (r * G.s3 * (2.0 * (double)b + (double)a)) / 2.0;
+    } else {
+        const double r = G.size;
+        int64_t R = (int64_t)1 << (G.L - l);
+        dx = (double)(da * R) * ((G.s3 * r) / 2.0);
+        dy = (double)(db * R) * (r / 2.0);
+    }
+}
+
+// Tables: pw[((l*G + g)*S + s)*(PM+1) + k] = (-1/delta)^k (complex, zero
+// beyond p), lg[(l*G + g)*S + s] = Log(c_T - c_S).
+void m2l_tables(const Plan &P, int pm, std::vector<double> &pw, std::vector<double> &lg)
+{
+    const int L = P.geo.L, G = P.tables.n_groups, S = P.tables.e4_width;
+    pw.assign((size_t)(L + 1) * G * S * (pm + 1) * 2, 0.0);
+    lg.assign((size_t)(L + 1) * G * S * 2, 0.0);
+    for (int l = 1; l <= L; ++l)
+        for (int g = 0; g < G; ++g)
+            for (int s = 0; s < P.tables.e4_count[g]; ++s) {
+                double dx, dy;
+                slot_offset(P, l, g, s, dx, dy);
+                size_t idx = ((size_t)l * G + g) * S + s;
+                double lx = -dx, ly = -dy + 0.0;
+                lg[2 * idx] = log(hypot(lx, ly));
+                lg[2 * idx + 1] = atan2(ly, lx);
+                double ex = dx / P.scale[l], ey = dy / P.scale[l];
+                double d2 = ex * ex + ey * ey;
+                double qx = -ex / d2, qy = ey / d2;   // -1/delta
+                double cr = 1.0, ci = 0.0;
+                for (int k = 0; k <= P.p; ++k) {
+                    pw[2 * (idx * (pm + 1) + k)] = cr;
+                    pw[2 * (idx * (pm + 1) + k) + 1] = ci;
+                    double nr = cr * qx - ci * qy, ni = cr * qy + ci * qx;
+                    cr = nr;
+                    ci = ni;
+                }
+            }
+}
+
+template <int PM>
+__global__ __launch_bounds__(64) void k_m2l_lanes(M2LLaneParams q, const uint8_t *__restrict__ occ,
+                                                  const uint8_t *__restrict__ group,
+                                                  const int32_t *__restrict__ e4,
+                                                  const double *__restrict__ pwt,
+                                                  const double *__restrict__ lgt,
+                                                  const double *__restrict__ binom,
+                                                  const double *__restrict__ mp,
+                                                  double *__restrict__ lc)
+{
+    constexpr int CH = 8;   // outputs per pass over the slots
+    __shared__ double H[PM * PM];   // H[(m-1)*PM + (k-1)] = C(m+k-1, k-1)
+    __shared__ double invm[PM + 1];
+    for (int i = threadIdx.x; i < PM * PM; i += 64) {
+        int m = i / PM + 1, k = i % PM + 1;
+        H[i] = binom[(m + k - 1) * kBinomN + (k - 1)];
+    }
+    for (int i = threadIdx.x; i <= PM; i += 64) invm[i] = i ? 1.0 / (double)i : 0.0;
+    __syncthreads();
+    const int64_t gid = q.first + (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (gid >= q.n_cells) return;
+    const int p = q.p, P1 = p + 1;
+    double *out = lc + gid * 2 * P1;
+    if (!(occ[gid] & 2)) {
+        for (int m = 0; m <= p; ++m) out[2 * m] = out[2 * m + 1] = 0.0;
+        return;
+    }
+    int l = 1;
+    while (l < q.L && gid >= q.cell_off[l + 1]) ++l;
+    const int g = group[gid];
+    const int32_t *row_e4 = e4 + gid * (int64_t)q.S;
+    const size_t tab0 = ((size_t)l * q.G + g) * q.S;
+    const int nch = (p + CH - 1) / CH;
+    for (int c = 0; c < nch; ++c) {
+        double ar[CH], ai[CH];
+        double b0r = 0.0, b0i = 0.0;
+#pragma unroll
+        for (int j = 0; j < CH; ++j) ar[j] = ai[j] = 0.0;
+        for (int s = 0; s < q.S; ++s) {
+            const int32_t src = row_e4[s];
+            if (src < 0) continue;
+            const double *tb = pwt + 2 * (tab0 + s) * (PM + 1);
+            const double *a = mp + (int64_t)src * 2 * P1;
+            const double a0 = a[0];
+            double gr[PM + 1], gi[PM + 1];
+#pragma unroll
+            for (int k = 1; k <= PM; ++k) {
+                double xr = 0.0, xi = 0.0;
+                if (k <= p) {
+                    xr = a[2 * k];
+                    xi = a[2 * k + 1];
+                }
+                const double tr = tb[2 * k], ti = tb[2 * k + 1];
+                gr[k] = xr * tr - xi * ti;
+                gi[k] = xr * ti + xi * tr;
+            }
+            if (c == 0) {
+                double s0r = a0 * lgt[2 * (tab0 + s)], s0i = a0 * lgt[2 * (tab0 + s) + 1];
+#pragma unroll
+                for (int k = 1; k <= PM; ++k) {
+                    s0r += gr[k];
+                    s0i += gi[k];
+                }
+                b0r += s0r;
+                b0i += s0i;
+            }
+            // An opaque zero keeps the LDS reads of H inside the slot loop.
+            int hoff = (c * CH) * PM;
+            asm volatile("" : "+v"(hoff));
+#pragma unroll
+            for (int j = 0; j < CH; ++j) {
+                const int m = c * CH + 1 + j;
+                double hr = -a0 * invm[m < PM ? m : PM], hi = 0.0;
+                const double *Hr = H + hoff + j * PM;
+#pragma unroll
+                for (int k = 1; k <= PM; ++k) {
+                    const double cf = Hr[k - 1];
+                    hr += cf * gr[k];
+                    hi += cf * gi[k];
+                }
+                double dr = tb[2 * m], di = tb[2 * m + 1];
+                if (m & 1) {
+                    dr = -dr;
+                    di = -di;
+                }
+                ar[j] += hr * dr - hi * di;
+                ai[j] += hr * di + hi * dr;
+            }
+        }
+        if (c == 0) {
+            out[0] = b0r;
+            out[1] = b0i;
+        }
+#pragma unroll
+        for (int j = 0; j < CH; ++j) {
+            const int m = c * CH + 1 + j;
+            if (m <= p) {
+                out[2 * m] = ar[j];
+                out[2 * m + 1] = ai[j];
+            }
+        }
+    }
+}
+
+void launch_m2l_lanes(const Plan &P, const double *pwt, const double *lgt, hipStream_t s)
+{
+    if (P.geo.L < 1) return;
+    M2LLaneParams q;
+    q.p = P.p;
+    q.L = P.geo.L;
+    q.G = P.tables.n_groups;
+    q.S = P.tables.e4_width;
+    q.pm = m2l_pm_for(P.p);
+    q.first = P.lev[1].cell_off;
+    q.n_cells = P.n_cells;
+    for (int l = 0; l <= P.geo.L; ++l) q.cell_off[l] = P.lev[l].cell_off;
+    q.cell_off[P.geo.L + 1] = P.n_cells;
+    int64_t n = P.n_cells - q.first;
+    if (n <= 0) return;
+    dim3 grid((unsigned)((n + 63) / 64));
+    switch (q.pm) {
+    case 8: hipLaunchKernelGGL(k_m2l_lanes<8>, grid, dim3(64), 0, s, q, P.cell_occ, P.group, P.e4, pwt, lgt, P.binom, P.mp, P.lc); break;
+    case 16: hipLaunchKernelGGL(k_m2l_lanes<16>, grid, dim3(64), 0, s, q, P.cell_occ, P.group, P.e4, pwt, lgt, P.binom, P.mp, P.lc); break;
+    case 24: hipLaunchKernelGGL(k_m2l_lanes<24>, grid, dim3(64), 0, s, q, P.cell_occ, P.group, P.e4, pwt, lgt, P.binom, P.mp, P.lc); break;
+    case 32: hipLaunchKernelGGL(k_m2l_lanes<32>, grid, dim3(64), 0, s, q, P.cell_occ, P.group, P.e4, pwt, lgt, P.binom, P.mp, P.lc); break;
+    case 40: hipLaunchKernelGGL(k_m2l_lanes<40>, grid, dim3(64), 0, s, q, P.cell_occ, P.group, P.e4, pwt, lgt, P.binom, P.mp, P.lc); break;
+    case 48: hipLaunchKernelGGL(k_m2l_lanes<48>, grid, dim3(64), 0, s, q, P.cell_occ, P.group, P.e4, pwt, lgt, P.binom, P.mp, P.lc); break;
+    default: break;
+    }
+}
+
+}  // namespace fmm

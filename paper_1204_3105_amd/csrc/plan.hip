@@ -400,7 +400,7 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     P->near = take<int32_t>(P, NL * nw, &err);
     P->mp = take<double>(P, C * 2 * (P->p + 1), &err);
     P->lc = take<double>(P, C * 2 * (P->p + 1), &err);
-    P->binom = take<double>(P, (2 * kMaxP + 2) * (2 * kMaxP + 2), &err);
+    P->binom = device_binom(&err);
     P->su = take<double>(P, N, &err);
     int32_t *ncount = take<int32_t>(P, NL + 1, &err);
     int64_t items_cap = (M + kChunk - 1) / kChunk + NL + 1;
@@ -427,8 +427,17 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     FMM_HIP_CHECK(hipMemsetAsync(pairs, 0, 2 * sizeof(unsigned long long), s));
     launch_count_pairs(P->lev, g.L, ew, nw, P->e4, P->near, P->cell_occ, P->sb, P->se, P->tb,
                        P->te, pairs, s);
-    launch_binom(P->binom, s);
     FMM_HIP_CHECK(hipMemsetAsync(P->lc, 0, sizeof(double) * 2 * (P->p + 1) * C, s));
+    P->m2l_pm = m2l_pm_for(P->p);
+    if (P->m2l_pm > 0 && g.L >= 1) {
+        std::vector<double> pw, lg;
+        m2l_tables(*P, P->m2l_pm, pw, lg);
+        P->m2l_pw = take<double>(P, (int64_t)pw.size(), &err);
+        P->m2l_lg = take<double>(P, (int64_t)lg.size(), &err);
+        if (err) return fail(FMM_E_NOMEM, "device allocation failed (M2L tables)");
+        FMM_HIP_CHECK(hipMemcpy(P->m2l_pw, pw.data(), pw.size() * sizeof(double), hipMemcpyHostToDevice));
+        FMM_HIP_CHECK(hipMemcpy(P->m2l_lg, lg.data(), lg.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
     if (P->precision == FMM_PREC_MIXED) {
         P->sxl = take<float>(P, N, &err);
         P->syl = take<float>(P, N, &err);
@@ -577,6 +586,8 @@ fmm_status fmm_eval(fmm_plan_t plan, const double *u, double *phi)
         FMM_HIP_CHECK(hipEventRecord(P->ev[3], s));
         if (mixed)
             launch_m2l_mixed(*P, s);
+        else if (P->m2l_pw)
+            launch_m2l_lanes(*P, P->m2l_pw, P->m2l_lg, s);
         else
             launch_m2l_fp64(*P, s);
         FMM_HIP_CHECK(hipEventRecord(P->ev[4], s));
@@ -589,6 +600,7 @@ fmm_status fmm_eval(fmm_plan_t plan, const double *u, double *phi)
         FMM_HIP_CHECK(hipEventRecord(P->ev[6], s));
     }
     FMM_HIP_CHECK(hipGetLastError());
+    P->evaluated = true;
     if (!P->device_pointers) {
         FMM_HIP_CHECK(hipMemcpyAsync(phi, P->io_phi, sizeof(double) * 2 * P->n_tgt,
                                      hipMemcpyDeviceToHost, s));
@@ -618,7 +630,7 @@ fmm_status fmm_plan_info_get(fmm_plan_t plan, fmm_plan_info *info)
     info->n_near_pairs = P->n_near_pairs;
     info->device_bytes = P->device_bytes;
     info->plan_ms = P->plan_ms;
-    if (hipEventQuery(P->ev[6]) == hipSuccess && P->n_tgt > 0) {
+    if (P->evaluated && hipEventSynchronize(P->ev[6]) == hipSuccess && P->n_tgt > 0) {
         info->eval_ms = elapsed(P->ev[2], P->ev[6]);
         info->stage_ms[0] = elapsed(P->ev[2], P->ev[3]);
         info->stage_ms[1] = elapsed(P->ev[3], P->ev[4]);
