@@ -20,7 +20,7 @@ LIB = os.path.join(HERE, "libfmm2d.so")
 BUILD = os.path.join(HERE, "_build")
 
 SOURCES = ["keys.hip", "sort.hip", "tree.hip", "expand.hip", "m2l.hip", "near.hip", "near_mixed.hip", "m2l_mixed.hip",
-           "plan.hip", "server.hip"]
+           "eval.hip", "plan.hip", "server.hip"]
 NO_CONTRACT = {"keys.hip", "tree.hip"}
 
 

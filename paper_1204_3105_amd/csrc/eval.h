@@ -1,0 +1,96 @@
+// eval.h -- per-plan evaluation descriptors and batched launches.
+//
+// Every evaluation kernel takes a device array of EvalJob descriptors (one
+// per plan) and a BatchMap passed by value that lists, for the phase being
+// launched, which jobs take part and where each job's work items start in
+// the global item range.  A kernel's workgroups walk that range with a
+// fixed-size, grid-stride (persistent) loop, so one launch serves any mix of
+// requests; a single fmm_eval is a batch of one.  An item's arithmetic
+// depends only on its own job's data, so a result is bitwise the same alone
+// and in a batch.
+#pragma once
+
+#include "fmm_internal.h"
+
+namespace fmm {
+
+constexpr int kMaxBatch = 64;
+constexpr int kBinomStride = 2 * kMaxP + 2;
+
+struct EvalJob {
+    int p, L, tiling, base, prec;
+    int nw, ew, G, pm, MT, KB, sept;
+    int64_t n_src, n_tgt, n_cells, leaf_off, n_leaf, m2l_first;
+    double scale[kMaxL + 1];
+    int64_t cell_off[kMaxL + 2];
+    int64_t dense_off[kMaxL + 1];
+    const double *sx, *sy;
+    double *su;
+    float *suf;
+    const float *sxl, *syl, *txl, *tyl;
+    const double *tx, *ty;
+    const int32_t *sperm, *tperm;
+    const int32_t *sb, *se, *tb, *te, *dense, *parent, *e4, *near, *work_near;
+    const uint32_t *cell_key;
+    const uint8_t *occ, *group;
+    const double *cx, *cy;
+    double *mp, *lc;
+    const double *m2l_pw, *m2l_lg, *binom;
+    const __bf16 *mix_tab;
+    const int32_t *mix_tiles, *mix_list;
+    double *phi;   // output, caller's target order, 2 n_tgt doubles
+};
+
+struct BatchMap {
+    int n;                        // participating entries
+    int64_t pre[kMaxBatch + 1];   // item prefix per entry
+    int16_t job[kMaxBatch];       // job index of each entry
+    int8_t aux[kMaxBatch];        // phase argument (level) of each entry
+    double *phi_override;         // single-job output redirect (or null)
+};
+
+__device__ __forceinline__ int batch_entry(const BatchMap &m, int64_t item)
+{
+    int e = 0;
+    while (e + 1 < m.n && item >= m.pre[e + 1]) ++e;
+    return e;
+}
+
+__device__ __forceinline__ int level_of(const EvalJob &J, int64_t gid)
+{
+    int l = 0;
+    while (l < J.L && gid >= J.cell_off[l + 1]) ++l;
+    return l;
+}
+
+// Persistent-grid size for a phase with `items` work items.
+inline unsigned persistent_grid(int64_t items, int per_cu)
+{
+    int64_t cap = (int64_t)256 * per_cu;
+    return (unsigned)(items < cap ? (items > 0 ? items : 1) : cap);
+}
+
+// Launchers (items are counted on the host from plan sizes).
+void batch_gather_u(const EvalJob *jobs_d, const EvalJob &J, const double *u, hipStream_t s);
+void batch_p2m(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
+void batch_m2m(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
+void batch_l2l(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
+void batch_m2l_block(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
+void batch_m2l_lanes(const EvalJob *jobs, const BatchMap &m, int pm, hipStream_t s);
+void batch_m2l_mixed(const EvalJob *jobs, const BatchMap &m, int MT, int KB, hipStream_t s);
+bool mixed_shape_supported(int MT, int KB);
+void batch_near_fp64(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
+void batch_near_mixed(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
+
+// Host view of one plan for batching: its descriptor (host copy) and the
+// device copy.
+EvalJob make_job(const Plan &P);
+
+// Run the evaluation phases for a batch of plans on stream s.  jobs_dev
+// holds the descriptors in device memory (jobs_dev[i] describes plans[i]).
+// phi_single, when not null and the batch has one plan, receives the output
+// instead of the plan's own buffer.
+void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_single, hipStream_t s,
+               hipEvent_t *stage_events);
+
+}  // namespace fmm

@@ -1,0 +1,209 @@
+// eval.hip -- evaluation phases over a batch of plans.
+//
+// Phase order (Greengard-Rokhlin sweep; paper Sec. 2 cites it):
+//   P2M at the leaves, M2M from level L-1 up to 1, M2L on every level >= 1
+//   (the E4 lists), L2L from level 2 down to L, then L2P + P2P per target
+//   leaf.  Strengths are gathered into sorted order by the caller.
+// Each phase is one launch (per kernel variant) covering every plan of the
+// batch that has work in it; level-wise phases pair plans by their distance
+// from the leaves (M2M) or from the top (L2L), so plans of different depth
+// share launches.
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "eval.h"
+
+namespace fmm {
+
+void mixed_pointers(const Plan &P, const __bf16 **tab, const int32_t **tiles, const int32_t **list,
+                    int *MT, int *KB);
+
+EvalJob make_job(const Plan &P)
+{
+    EvalJob J;
+    memset(&J, 0, sizeof(J));
+    J.p = P.p;
+    J.L = P.geo.L;
+    J.tiling = P.geo.tiling;
+    J.base = base_of(P.geo.tiling);
+    J.prec = P.precision;
+    J.nw = P.tables.near_width;
+    J.ew = P.tables.e4_width;
+    J.G = P.tables.n_groups;
+    J.pm = P.m2l_pm;
+    J.sept = P.geo.tiling == kSept;
+    J.n_src = P.n_src;
+    J.n_tgt = P.n_tgt;
+    J.n_cells = P.n_cells;
+    J.leaf_off = P.lev[P.geo.L].cell_off;
+    J.n_leaf = P.lev[P.geo.L].n;
+    J.m2l_first = P.geo.L >= 1 ? P.lev[1].cell_off : P.n_cells;
+    for (int l = 0; l <= kMaxL; ++l) {
+        J.scale[l] = l <= P.geo.L ? P.scale[l] : 0.0;
+        J.dense_off[l] = l <= P.geo.L ? P.lev[l].dense_off : 0;
+    }
+    for (int l = 0; l < kMaxL + 2; ++l) J.cell_off[l] = P.n_cells;
+    for (int l = 0; l <= P.geo.L; ++l) J.cell_off[l] = P.lev[l].cell_off;
+    J.sx = P.sx;
+    J.sy = P.sy;
+    J.su = P.su;
+    J.suf = P.suf;
+    J.sxl = P.sxl;
+    J.syl = P.syl;
+    J.txl = P.txl;
+    J.tyl = P.tyl;
+    J.tx = P.tx;
+    J.ty = P.ty;
+    J.sperm = P.sperm;
+    J.tperm = P.tperm;
+    J.sb = P.sb;
+    J.se = P.se;
+    J.tb = P.tb;
+    J.te = P.te;
+    J.dense = P.dense;
+    J.parent = P.parent;
+    J.e4 = P.e4;
+    J.near = P.near;
+    J.work_near = P.work_near;
+    J.cell_key = P.cell_key;
+    J.occ = P.cell_occ;
+    J.group = P.group;
+    J.cx = P.cx;
+    J.cy = P.cy;
+    J.mp = P.mp;
+    J.lc = P.lc;
+    J.m2l_pw = P.m2l_pw;
+    J.m2l_lg = P.m2l_lg;
+    J.binom = P.binom;
+    J.phi = P.phi_int;
+    if (P.precision == FMM_PREC_MIXED && P.mixed) {
+        int MT, KB;
+        mixed_pointers(P, &J.mix_tab, &J.mix_tiles, &J.mix_list, &MT, &KB);
+        J.MT = MT;
+        J.KB = KB;
+    }
+    return J;
+}
+
+namespace {
+
+// Collects (job, aux, items) entries and launches when 64 are pending.
+struct Launcher {
+    const EvalJob *jobs;
+    hipStream_t s;
+    double *phi_single;
+    BatchMap m;
+    template <typename F>
+    void add(int job, int aux, int64_t items, F &&flush)
+    {
+        if (items <= 0) return;
+        if (m.n == kMaxBatch) {
+            flush(m);
+            reset();
+        }
+        m.job[m.n] = (int16_t)job;
+        m.aux[m.n] = (int8_t)aux;
+        m.pre[m.n + 1] = m.pre[m.n] + items;
+        m.n++;
+    }
+    void reset()
+    {
+        m.n = 0;
+        m.pre[0] = 0;
+        m.phi_override = phi_single;
+    }
+};
+
+}  // namespace
+
+void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_single, hipStream_t s,
+               hipEvent_t *ev)
+{
+    Launcher Lc{jobs_dev, s, n == 1 ? phi_single : nullptr, {}};
+    Lc.reset();
+    auto go = [&](auto &&launch) {
+        if (Lc.m.n > 0) launch(Lc.m);
+        Lc.reset();
+    };
+    int maxL = 0;
+    for (int i = 0; i < n; ++i) maxL = std::max(maxL, plans[i]->geo.L);
+
+    // P2M
+    {
+        auto f = [&](const BatchMap &m) { batch_p2m(jobs_dev, m, s); };
+        for (int i = 0; i < n; ++i) Lc.add(i, 0, plans[i]->lev[plans[i]->geo.L].n, f);
+        go(f);
+    }
+    // M2M, step k: level L_i - 1 - k.
+    for (int k = 0; k < maxL; ++k) {
+        auto f = [&](const BatchMap &m) { batch_m2m(jobs_dev, m, s); };
+        for (int i = 0; i < n; ++i) {
+            const int l = plans[i]->geo.L - 1 - k;
+            if (l >= 1) Lc.add(i, l, plans[i]->lev[l].n, f);
+        }
+        go(f);
+    }
+    if (ev) hipEventRecord(ev[0], s);
+
+    // M2L, one launch per kernel variant present in the batch.
+    {
+        const int pms[] = {8, 16, 24, 32, 40, 48};
+        for (int pm : pms) {
+            auto f = [&](const BatchMap &m) { batch_m2l_lanes(jobs_dev, m, pm, s); };
+            for (int i = 0; i < n; ++i) {
+                const Plan &P = *plans[i];
+                const bool mixed_ok = P.precision == FMM_PREC_MIXED && P.mixed_tiles > 0;
+                if (P.geo.L < 1 || P.m2l_pm != pm || mixed_ok) continue;
+                const int64_t cells = P.n_cells - P.lev[1].cell_off;
+                Lc.add(i, 0, (cells + 63) / 64, f);
+            }
+            go(f);
+        }
+        auto fb = [&](const BatchMap &m) { batch_m2l_block(jobs_dev, m, s); };
+        for (int i = 0; i < n; ++i) {
+            const Plan &P = *plans[i];
+            if (P.geo.L < 1 || P.m2l_pm != 0) continue;
+            Lc.add(i, 0, P.n_cells - P.lev[1].cell_off, fb);
+        }
+        go(fb);
+        for (int mt = 1; mt <= 7; ++mt)
+            for (int kb = 1; kb <= 3; ++kb) {
+                if (!mixed_shape_supported(mt, kb)) continue;
+                auto f = [&](const BatchMap &m) { batch_m2l_mixed(jobs_dev, m, mt, kb, s); };
+                for (int i = 0; i < n; ++i) {
+                    const Plan &P = *plans[i];
+                    if (P.precision != FMM_PREC_MIXED || P.mixed_tiles == 0) continue;
+                    if ((2 * (P.p + 1) + 15) / 16 != mt || (2 * P.p + 31) / 32 != kb) continue;
+                    Lc.add(i, 0, P.mixed_tiles, f);
+                }
+                go(f);
+            }
+    }
+    if (ev) hipEventRecord(ev[1], s);
+
+    // L2L, step k: level 2 + k.
+    for (int l = 2; l <= maxL; ++l) {
+        auto f = [&](const BatchMap &m) { batch_l2l(jobs_dev, m, s); };
+        for (int i = 0; i < n; ++i)
+            if (plans[i]->geo.L >= l) Lc.add(i, l, plans[i]->lev[l].n, f);
+        go(f);
+    }
+    if (ev) hipEventRecord(ev[2], s);
+
+    // L2P + P2P
+    {
+        auto f = [&](const BatchMap &m) { batch_near_fp64(jobs_dev, m, s); };
+        for (int i = 0; i < n; ++i)
+            if (plans[i]->precision != FMM_PREC_MIXED) Lc.add(i, 0, plans[i]->n_work_near, f);
+        go(f);
+        auto g = [&](const BatchMap &m) { batch_near_mixed(jobs_dev, m, s); };
+        for (int i = 0; i < n; ++i)
+            if (plans[i]->precision == FMM_PREC_MIXED) Lc.add(i, 0, plans[i]->n_work_near, g);
+        go(g);
+    }
+    if (ev) hipEventRecord(ev[3], s);
+}
+
+}  // namespace fmm

@@ -131,6 +131,11 @@ struct Plan {
     double plan_ms = 0, eval_ms = 0, stage_ms[8]{};
     bool evaluated = false;
 
+    // evaluation descriptor (device copy) and the output buffer used by
+    // batched evaluation (caller's target order)
+    void *job_dev = nullptr;
+    double *phi_int = nullptr;
+
     // scratch for staging host inputs / outputs
     double *io_u = nullptr;
     double *io_phi = nullptr;
@@ -185,27 +190,15 @@ void launch_count_pairs(const LevelInfo *lev, int L, int e4w, int nw, const int3
 ListTables build_tables(int tiling);
 
 // expand.hip
-void launch_gather_u(const double *u, const int32_t *perm, int64_t n, double *su, float *suf,
-                     hipStream_t s);
-void launch_p2m(const Plan &P, hipStream_t s);
-void launch_m2m(const Plan &P, int level, hipStream_t s);
-void launch_m2l_fp64(const Plan &P, hipStream_t s);
-void launch_l2l(const Plan &P, int level, hipStream_t s);
 const double *device_binom(int *err);
 
 // m2l.hip
 int m2l_pm_for(int p);
 void m2l_tables(const Plan &P, int pm, std::vector<double> &pw, std::vector<double> &lg);
-void launch_m2l_lanes(const Plan &P, const double *pwt, const double *lgt, hipStream_t s);
-
-// near.hip
-void launch_near_fp64(const Plan &P, const double *dummy, double *phi, hipStream_t s);
-void launch_near_mixed(const Plan &P, double *phi, hipStream_t s);
 
 // m2l_mixed.hip
 size_t mixed_bytes(const Plan &P);
 int mixed_setup(Plan &P);
-void launch_m2l_mixed(const Plan &P, hipStream_t s);
 
 // errors
 void set_error(const std::string &msg);

@@ -16,17 +16,9 @@
 
 #include <vector>
 
-#include "fmm_internal.h"
+#include "eval.h"
 
 namespace fmm {
-
-constexpr int kBinomN = 2 * kMaxP + 2;
-
-struct M2LLaneParams {
-    int p, L, G, S, pm;
-    int64_t first, n_cells;
-    int64_t cell_off[kMaxL + 2];
-};
 
 int m2l_pm_for(int p)
 {
@@ -93,132 +85,121 @@ void m2l_tables(const Plan &P, int pm, std::vector<double> &pw, std::vector<doub
 }
 
 template <int PM>
-__global__ __launch_bounds__(64) void k_m2l_lanes(M2LLaneParams q, const uint8_t *__restrict__ occ,
-                                                  const uint8_t *__restrict__ group,
-                                                  const int32_t *__restrict__ e4,
-                                                  const double *__restrict__ pwt,
-                                                  const double *__restrict__ lgt,
-                                                  const double *__restrict__ binom,
-                                                  const double *__restrict__ mp,
-                                                  double *__restrict__ lc)
+__global__ __launch_bounds__(64) void k_m2l_lanes(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
     constexpr int CH = 8;   // outputs per pass over the slots
     __shared__ double H[PM * PM];   // H[(m-1)*PM + (k-1)] = C(m+k-1, k-1)
     __shared__ double invm[PM + 1];
-    for (int i = threadIdx.x; i < PM * PM; i += 64) {
-        int m = i / PM + 1, k = i % PM + 1;
-        H[i] = binom[(m + k - 1) * kBinomN + (k - 1)];
+    {
+        const double *binom = jobs[bm.job[0]].binom;
+        for (int i = threadIdx.x; i < PM * PM; i += 64) {
+            int m = i / PM + 1, k = i % PM + 1;
+            H[i] = binom[(m + k - 1) * kBinomStride + (k - 1)];
+        }
+        for (int i = threadIdx.x; i <= PM; i += 64) invm[i] = i ? 1.0 / (double)i : 0.0;
     }
-    for (int i = threadIdx.x; i <= PM; i += 64) invm[i] = i ? 1.0 / (double)i : 0.0;
     __syncthreads();
-    const int64_t gid = q.first + (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (gid >= q.n_cells) return;
-    const int p = q.p, P1 = p + 1;
-    double *out = lc + gid * 2 * P1;
-    if (!(occ[gid] & 2)) {
-        for (int m = 0; m <= p; ++m) out[2 * m] = out[2 * m + 1] = 0.0;
-        return;
-    }
-    int l = 1;
-    while (l < q.L && gid >= q.cell_off[l + 1]) ++l;
-    const int g = group[gid];
-    const int32_t *row_e4 = e4 + gid * (int64_t)q.S;
-    const size_t tab0 = ((size_t)l * q.G + g) * q.S;
-    const int nch = (p + CH - 1) / CH;
-    for (int c = 0; c < nch; ++c) {
-        double ar[CH], ai[CH];
-        double b0r = 0.0, b0i = 0.0;
+    // One item = 64 consecutive cells of levels >= 1 (one per lane).
+    for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
+        const int e = batch_entry(bm, item);
+        const EvalJob &J = jobs[bm.job[e]];
+        const int64_t gid = J.m2l_first + (item - bm.pre[e]) * 64 + threadIdx.x;
+        if (gid >= J.n_cells) continue;
+        const int p = J.p, P1 = p + 1;
+        double *out = J.lc + gid * 2 * P1;
+        if (!(J.occ[gid] & 2)) {
+            for (int m = 0; m <= p; ++m) out[2 * m] = out[2 * m + 1] = 0.0;
+            continue;
+        }
+        const int l = level_of(J, gid);
+        const int g = J.group[gid];
+        const int32_t *row_e4 = J.e4 + gid * (int64_t)J.ew;
+        const size_t tab0 = ((size_t)l * J.G + g) * J.ew;
+        const double *pwt = J.m2l_pw, *lgt = J.m2l_lg, *mp = J.mp;
+        const int nch = (p + CH - 1) / CH;
+        for (int c = 0; c < nch; ++c) {
+            double ar[CH], ai[CH];
+            double b0r = 0.0, b0i = 0.0;
 #pragma unroll
-        for (int j = 0; j < CH; ++j) ar[j] = ai[j] = 0.0;
-        for (int s = 0; s < q.S; ++s) {
-            const int32_t src = row_e4[s];
-            if (src < 0) continue;
-            const double *tb = pwt + 2 * (tab0 + s) * (PM + 1);
-            const double *a = mp + (int64_t)src * 2 * P1;
-            const double a0 = a[0];
-            double gr[PM + 1], gi[PM + 1];
-#pragma unroll
-            for (int k = 1; k <= PM; ++k) {
-                double xr = 0.0, xi = 0.0;
-                if (k <= p) {
-                    xr = a[2 * k];
-                    xi = a[2 * k + 1];
-                }
-                const double tr = tb[2 * k], ti = tb[2 * k + 1];
-                gr[k] = xr * tr - xi * ti;
-                gi[k] = xr * ti + xi * tr;
-            }
-            if (c == 0) {
-                double s0r = a0 * lgt[2 * (tab0 + s)], s0i = a0 * lgt[2 * (tab0 + s) + 1];
+            for (int j = 0; j < CH; ++j) ar[j] = ai[j] = 0.0;
+            for (int s = 0; s < J.ew; ++s) {
+                const int32_t src = row_e4[s];
+                if (src < 0) continue;
+                const double *tb = pwt + 2 * (tab0 + s) * (PM + 1);
+                const double *a = mp + (int64_t)src * 2 * P1;
+                const double a0 = a[0];
+                double gr[PM + 1], gi[PM + 1];
 #pragma unroll
                 for (int k = 1; k <= PM; ++k) {
-                    s0r += gr[k];
-                    s0i += gi[k];
+                    double xr = 0.0, xi = 0.0;
+                    if (k <= p) {
+                        xr = a[2 * k];
+                        xi = a[2 * k + 1];
+                    }
+                    const double tr = tb[2 * k], ti = tb[2 * k + 1];
+                    gr[k] = xr * tr - xi * ti;
+                    gi[k] = xr * ti + xi * tr;
                 }
-                b0r += s0r;
-                b0i += s0i;
+                if (c == 0) {
+                    double s0r = a0 * lgt[2 * (tab0 + s)], s0i = a0 * lgt[2 * (tab0 + s) + 1];
+#pragma unroll
+                    for (int k = 1; k <= PM; ++k) {
+                        s0r += gr[k];
+                        s0i += gi[k];
+                    }
+                    b0r += s0r;
+                    b0i += s0i;
+                }
+                // An opaque zero keeps the LDS reads of H inside the slot loop.
+                int hoff = (c * CH) * PM;
+                asm volatile("" : "+v"(hoff));
+#pragma unroll
+                for (int j = 0; j < CH; ++j) {
+                    const int m = c * CH + 1 + j;
+                    double hr = -a0 * invm[m < PM ? m : PM], hi = 0.0;
+                    const double *Hr = H + hoff + j * PM;
+#pragma unroll
+                    for (int k = 1; k <= PM; ++k) {
+                        const double cf = Hr[k - 1];
+                        hr += cf * gr[k];
+                        hi += cf * gi[k];
+                    }
+                    double dr = tb[2 * m], di = tb[2 * m + 1];
+                    if (m & 1) {
+                        dr = -dr;
+                        di = -di;
+                    }
+                    ar[j] += hr * dr - hi * di;
+                    ai[j] += hr * di + hi * dr;
+                }
             }
-            // An opaque zero keeps the LDS reads of H inside the slot loop.
-            int hoff = (c * CH) * PM;
-            asm volatile("" : "+v"(hoff));
+            if (c == 0) {
+                out[0] = b0r;
+                out[1] = b0i;
+            }
 #pragma unroll
             for (int j = 0; j < CH; ++j) {
                 const int m = c * CH + 1 + j;
-                double hr = -a0 * invm[m < PM ? m : PM], hi = 0.0;
-                const double *Hr = H + hoff + j * PM;
-#pragma unroll
-                for (int k = 1; k <= PM; ++k) {
-                    const double cf = Hr[k - 1];
-                    hr += cf * gr[k];
-                    hi += cf * gi[k];
+                if (m <= p) {
+                    out[2 * m] = ar[j];
+                    out[2 * m + 1] = ai[j];
                 }
-                double dr = tb[2 * m], di = tb[2 * m + 1];
-                if (m & 1) {
-                    dr = -dr;
-                    di = -di;
-                }
-                ar[j] += hr * dr - hi * di;
-                ai[j] += hr * di + hi * dr;
-            }
-        }
-        if (c == 0) {
-            out[0] = b0r;
-            out[1] = b0i;
-        }
-#pragma unroll
-        for (int j = 0; j < CH; ++j) {
-            const int m = c * CH + 1 + j;
-            if (m <= p) {
-                out[2 * m] = ar[j];
-                out[2 * m + 1] = ai[j];
             }
         }
     }
 }
 
-void launch_m2l_lanes(const Plan &P, const double *pwt, const double *lgt, hipStream_t s)
+void batch_m2l_lanes(const EvalJob *jobs, const BatchMap &m, int pm, hipStream_t s)
 {
-    if (P.geo.L < 1) return;
-    M2LLaneParams q;
-    q.p = P.p;
-    q.L = P.geo.L;
-    q.G = P.tables.n_groups;
-    q.S = P.tables.e4_width;
-    q.pm = m2l_pm_for(P.p);
-    q.first = P.lev[1].cell_off;
-    q.n_cells = P.n_cells;
-    for (int l = 0; l <= P.geo.L; ++l) q.cell_off[l] = P.lev[l].cell_off;
-    q.cell_off[P.geo.L + 1] = P.n_cells;
-    int64_t n = P.n_cells - q.first;
-    if (n <= 0) return;
-    dim3 grid((unsigned)((n + 63) / 64));
-    switch (q.pm) {
-    case 8: hipLaunchKernelGGL(k_m2l_lanes<8>, grid, dim3(64), 0, s, q, P.cell_occ, P.group, P.e4, pwt, lgt, P.binom, P.mp, P.lc); break;
-    case 16: hipLaunchKernelGGL(k_m2l_lanes<16>, grid, dim3(64), 0, s, q, P.cell_occ, P.group, P.e4, pwt, lgt, P.binom, P.mp, P.lc); break;
-    case 24: hipLaunchKernelGGL(k_m2l_lanes<24>, grid, dim3(64), 0, s, q, P.cell_occ, P.group, P.e4, pwt, lgt, P.binom, P.mp, P.lc); break;
-    case 32: hipLaunchKernelGGL(k_m2l_lanes<32>, grid, dim3(64), 0, s, q, P.cell_occ, P.group, P.e4, pwt, lgt, P.binom, P.mp, P.lc); break;
-    case 40: hipLaunchKernelGGL(k_m2l_lanes<40>, grid, dim3(64), 0, s, q, P.cell_occ, P.group, P.e4, pwt, lgt, P.binom, P.mp, P.lc); break;
-    case 48: hipLaunchKernelGGL(k_m2l_lanes<48>, grid, dim3(64), 0, s, q, P.cell_occ, P.group, P.e4, pwt, lgt, P.binom, P.mp, P.lc); break;
+    if (m.n <= 0 || m.pre[m.n] <= 0) return;
+    const dim3 grid(persistent_grid(m.pre[m.n], 32));
+    switch (pm) {
+    case 8: hipLaunchKernelGGL(k_m2l_lanes<8>, grid, dim3(64), 0, s, jobs, m); break;
+    case 16: hipLaunchKernelGGL(k_m2l_lanes<16>, grid, dim3(64), 0, s, jobs, m); break;
+    case 24: hipLaunchKernelGGL(k_m2l_lanes<24>, grid, dim3(64), 0, s, jobs, m); break;
+    case 32: hipLaunchKernelGGL(k_m2l_lanes<32>, grid, dim3(64), 0, s, jobs, m); break;
+    case 40: hipLaunchKernelGGL(k_m2l_lanes<40>, grid, dim3(64), 0, s, jobs, m); break;
+    case 48: hipLaunchKernelGGL(k_m2l_lanes<48>, grid, dim3(64), 0, s, jobs, m); break;
     default: break;
     }
 }

@@ -22,14 +22,13 @@
 //   C[i = 4(l/16)+j][n = l%16].
 #include <vector>
 
-#include "fmm_internal.h"
+#include "eval.h"
 
 namespace fmm {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBinomN = 2 * kMaxP + 2;
 constexpr int kTileT = 64;   // targets per workgroup (4 waves x 16 columns)
 
 struct MixedLayout {
@@ -128,7 +127,7 @@ __global__ __launch_bounds__(64) void k_build_mixed_tables(int p, int MT, int KB
                     dr = -dr;
                     di = -di;
                 }
-                const double c = binom[(m + k - 1) * kBinomN + (k - 1)];
+                const double c = binom[(m + k - 1) * kBinomStride + (k - 1)];
                 const double nr = (tr * dr - ti * di) * c, ni = (tr * di + ti * dr) * c;
                 tr = nr;
                 ti = ni;
@@ -221,136 +220,133 @@ int mixed_setup(Plan &P)
 }
 
 template <int MT, int KB>
-__global__ __launch_bounds__(256) void k_m2l_bf16x3(int p, int G, int S, int pm, int sept,
-                                                    const int32_t *__restrict__ tiles,
-                                                    const int32_t *__restrict__ list,
-                                                    const int32_t *__restrict__ e4,
-                                                    const int *__restrict__ e4_count_unused,
-                                                    const __bf16 *__restrict__ tab,
-                                                    const double *__restrict__ pwt,
-                                                    const double *__restrict__ lgt,
-                                                    const double *__restrict__ mp,
-                                                    double *__restrict__ lc)
+__global__ __launch_bounds__(256) void k_m2l_bf16x3(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
-    (void)e4_count_unused;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int key = tiles[4 * blockIdx.x], start = tiles[4 * blockIdx.x + 1],
-              count = tiles[4 * blockIdx.x + 2];
-    const int l = key / G, g = key % G;
     const int n = lane % 16, q = lane / 16;
-    const int col = 16 * w + n;
-    const bool valid = col < count;
-    const int32_t gid = valid ? list[start + col] : -1;
-    const int P1 = p + 1, twoP = 2 * p;
-    const int tl = sept ? l : 0;
-    double acc[MT][4];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0;
-    const size_t tab_elems = (size_t)MT * KB * 3 * 512;
-    for (int s = 0; s < S; ++s) {
-        const int32_t src = valid ? e4[(int64_t)gid * S + s] : -1;
-        // Wave-uniform skip when no lane has a source in this slot.
-        if (__ballot(src >= 0) == 0ull) continue;
-        const double *a = src >= 0 ? mp + (int64_t)src * 2 * P1 : nullptr;
-        bf16x8 bh[KB], bm[KB], bl[KB];
-#pragma unroll
-        for (int kb = 0; kb < KB; ++kb) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const int idx = 32 * kb + 8 * q + j;
-                float x = 0.0f;
-                if (a && idx < twoP) x = (float)a[2 + idx];
-                __bf16 h, m, lo;
-                split3(x, h, m, lo);
-                bh[kb][j] = h;
-                bm[kb][j] = m;
-                bl[kb][j] = lo;
-            }
-        }
-        const bf16x8 *T = (const bf16x8 *)(tab + (((size_t)tl * G + g) * S + s) * tab_elems);
-        const size_t pidx = ((size_t)l * G + g) * S + s;
-        const double *pw = pwt + 2 * pidx * (pm + 1);
-        const double a0 = a ? a[0] : 0.0;
-        const double lgr = lgt[2 * pidx], lgi = lgt[2 * pidx + 1];
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) {
-            floatx4 c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb) {
-                const bf16x8 *t3 = T + (size_t)((mt * KB + kb) * 3) * 64;
-                const bf16x8 ah = t3[lane], am = t3[64 + lane], al = t3[128 + lane];
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[kb], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bm[kb], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[kb], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[kb], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[kb], c, 0, 0, 0);
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bm[kb], c, 0, 0, 0);
-            }
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int row = 16 * mt + 4 * q + j;
-                const int m = row >> 1;
-                double t0 = 0.0;
-                if (a && m <= p) {
-                    if (m == 0) {
-                        t0 = a0 * ((row & 1) ? lgi : lgr);
-                    } else {
-                        // -a0/m delta^-m, delta^-m = (-1)^m (-1/delta)^m
-                        double d = pw[2 * m + (row & 1)];
-                        if (m & 1) d = -d;
-                        t0 = -a0 / (double)m * d;
-                    }
-                }
-                acc[mt][j] += (double)c[j] + t0;
-            }
-        }
-    }
-    if (valid) {
-        double *out = lc + (int64_t)gid * 2 * P1;
+    for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
+        const int e = batch_entry(bm, item);
+        const EvalJob &J = jobs[bm.job[e]];
+        const int32_t *tile = J.mix_tiles + 4 * (item - bm.pre[e]);
+        const int key = tile[0], start = tile[1], count = tile[2];
+        const int G = J.G, S = J.ew, p = J.p, pm = J.pm;
+        const int l = key / G, g = key % G;
+        const int col = 16 * w + n;
+        const bool valid = col < count;
+        const int32_t gid = valid ? J.mix_list[start + col] : -1;
+        const int P1 = p + 1, twoP = 2 * p;
+        const int tl = J.sept ? l : 0;
+        double acc[MT][4];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int row = 16 * mt + 4 * q + j;
-                if (row < 2 * P1) out[row] = acc[mt][j];
+            for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0;
+        const size_t tab_elems = (size_t)MT * KB * 3 * 512;
+        for (int s = 0; s < S; ++s) {
+            const int32_t src = valid ? J.e4[(int64_t)gid * S + s] : -1;
+            // Wave-uniform skip when no lane has a source in this slot.
+            if (__ballot(src >= 0) == 0ull) continue;
+            const double *a = src >= 0 ? J.mp + (int64_t)src * 2 * P1 : nullptr;
+            bf16x8 bh[KB], bmd[KB], bl[KB];
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int idx = 32 * kb + 8 * q + j;
+                    float x = 0.0f;
+                    if (a && idx < twoP) x = (float)a[2 + idx];
+                    __bf16 h, m, lo;
+                    split3(x, h, m, lo);
+                    bh[kb][j] = h;
+                    bmd[kb][j] = m;
+                    bl[kb][j] = lo;
+                }
             }
+            const bf16x8 *T = (const bf16x8 *)(J.mix_tab + (((size_t)tl * G + g) * S + s) * tab_elems);
+            const size_t pidx = ((size_t)l * G + g) * S + s;
+            const double *pw = J.m2l_pw + 2 * pidx * (pm + 1);
+            const double a0 = a ? a[0] : 0.0;
+            const double lgr = J.m2l_lg[2 * pidx], lgi = J.m2l_lg[2 * pidx + 1];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                floatx4 c = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < KB; ++kb) {
+                    const bf16x8 *t3 = T + (size_t)((mt * KB + kb) * 3) * 64;
+                    const bf16x8 ah = t3[lane], am = t3[64 + lane], al = t3[128 + lane];
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[kb], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bmd[kb], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[kb], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[kb], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[kb], c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bmd[kb], c, 0, 0, 0);
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int row = 16 * mt + 4 * q + j;
+                    const int m = row >> 1;
+                    double t0 = 0.0;
+                    if (a && m <= p) {
+                        if (m == 0) {
+                            t0 = a0 * ((row & 1) ? lgi : lgr);
+                        } else {
+                            // -a0/m delta^-m, delta^-m = (-1)^m (-1/delta)^m
+                            double d = pw[2 * m + (row & 1)];
+                            if (m & 1) d = -d;
+                            t0 = -a0 / (double)m * d;
+                        }
+                    }
+                    acc[mt][j] += (double)c[j] + t0;
+                }
+            }
+        }
+        if (valid) {
+            double *out = J.lc + (int64_t)gid * 2 * P1;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int row = 16 * mt + 4 * q + j;
+                    if (row < 2 * P1) out[row] = acc[mt][j];
+                }
+        }
     }
 }
 
-template <int MT, int KB>
-static void launch_mt_kb(const Plan &P, const MixedLayout &m, hipStream_t s)
+void mixed_pointers(const Plan &P, const __bf16 **tab, const int32_t **tiles, const int32_t **list,
+                    int *MT, int *KB)
 {
-    char *base = (char *)P.mixed;
-    hipLaunchKernelGGL((k_m2l_bf16x3<MT, KB>), dim3(P.mixed_tiles), dim3(256), 0, s, P.p, m.G, m.S,
-                       m.pm, P.geo.tiling == kSept ? 1 : 0, (const int32_t *)(base + m.off_tiles),
-                       (const int32_t *)(base + m.off_list), P.e4, nullptr,
-                       (const __bf16 *)(base + m.off_tab), P.m2l_pw, P.m2l_lg, P.mp, P.lc);
-}
-
-void launch_m2l_mixed(const Plan &P, hipStream_t s)
-{
-    if (P.geo.L < 1) return;
-    if (P.m2l_pm == 0 || P.mixed_tiles == 0) {
-        if (P.m2l_pm) launch_m2l_lanes(P, P.m2l_pw, P.m2l_lg, s);
-        return;
-    }
-    // Cells of levels >= 1 that hold no targets keep a zero local expansion
-    // (set when the plan was built); target cells are fully overwritten.
     MixedLayout m = layout_of(P);
-    const int key = m.MT * 10 + m.KB;
-    switch (key) {
-    case 11: launch_mt_kb<1, 1>(P, m, s); break;
-    case 21: launch_mt_kb<2, 1>(P, m, s); break;
-    case 31: launch_mt_kb<3, 1>(P, m, s); break;
-    case 32: launch_mt_kb<3, 2>(P, m, s); break;
-    case 42: launch_mt_kb<4, 2>(P, m, s); break;
-    case 52: launch_mt_kb<5, 2>(P, m, s); break;
-    case 53: launch_mt_kb<5, 3>(P, m, s); break;
-    case 63: launch_mt_kb<6, 3>(P, m, s); break;
-    case 73: launch_mt_kb<7, 3>(P, m, s); break;
-    default: launch_m2l_lanes(P, P.m2l_pw, P.m2l_lg, s); break;
+    const char *base = (const char *)P.mixed;
+    *tab = base ? (const __bf16 *)(base + m.off_tab) : nullptr;
+    *tiles = base ? (const int32_t *)(base + m.off_tiles) : nullptr;
+    *list = base ? (const int32_t *)(base + m.off_list) : nullptr;
+    *MT = m.MT;
+    *KB = m.KB;
+}
+
+bool mixed_shape_supported(int MT, int KB)
+{
+    const int key = MT * 10 + KB;
+    return key == 11 || key == 21 || key == 31 || key == 32 || key == 42 || key == 52 ||
+           key == 53 || key == 63 || key == 73;
+}
+
+void batch_m2l_mixed(const EvalJob *jobs, const BatchMap &m, int MT, int KB, hipStream_t s)
+{
+    if (m.n <= 0 || m.pre[m.n] <= 0) return;
+    const dim3 grid(persistent_grid(m.pre[m.n], 16)), block(256);
+    switch (MT * 10 + KB) {
+    case 11: hipLaunchKernelGGL((k_m2l_bf16x3<1, 1>), grid, block, 0, s, jobs, m); break;
+    case 21: hipLaunchKernelGGL((k_m2l_bf16x3<2, 1>), grid, block, 0, s, jobs, m); break;
+    case 31: hipLaunchKernelGGL((k_m2l_bf16x3<3, 1>), grid, block, 0, s, jobs, m); break;
+    case 32: hipLaunchKernelGGL((k_m2l_bf16x3<3, 2>), grid, block, 0, s, jobs, m); break;
+    case 42: hipLaunchKernelGGL((k_m2l_bf16x3<4, 2>), grid, block, 0, s, jobs, m); break;
+    case 52: hipLaunchKernelGGL((k_m2l_bf16x3<5, 2>), grid, block, 0, s, jobs, m); break;
+    case 53: hipLaunchKernelGGL((k_m2l_bf16x3<5, 3>), grid, block, 0, s, jobs, m); break;
+    case 63: hipLaunchKernelGGL((k_m2l_bf16x3<6, 3>), grid, block, 0, s, jobs, m); break;
+    case 73: hipLaunchKernelGGL((k_m2l_bf16x3<7, 3>), grid, block, 0, s, jobs, m); break;
+    default: break;
     }
 }
 

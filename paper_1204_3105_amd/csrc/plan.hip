@@ -24,7 +24,7 @@
 #include <string>
 #include <vector>
 
-#include "fmm_internal.h"
+#include "eval.h"
 #include "fmm_tables.h"
 
 namespace fmm {
@@ -475,6 +475,11 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
         P->io_phi = take<double>(P, 2 * std::max<int64_t>(M, 1), &err);
         if (err) return fail(FMM_E_NOMEM, "device allocation failed (io)");
     }
+    P->phi_int = take<double>(P, 2 * std::max<int64_t>(M, 1), &err);
+    P->job_dev = take<EvalJob>(P, 1, &err);
+    if (err) return fail(FMM_E_NOMEM, "device allocation failed (descriptor)");
+    EvalJob J = make_job(*P);
+    FMM_HIP_CHECK(hipMemcpy(P->job_dev, &J, sizeof(J), hipMemcpyHostToDevice));
     return FMM_OK;
 }
 
@@ -579,25 +584,10 @@ fmm_status fmm_eval(fmm_plan_t plan, const double *u, double *phi)
         FMM_HIP_CHECK(hipEventRecord(P->ev[5], s));
         FMM_HIP_CHECK(hipEventRecord(P->ev[6], s));
     } else {
-        const bool mixed = P->precision == FMM_PREC_MIXED;
-        launch_gather_u(du, P->sperm, P->n_src, P->su, mixed ? P->suf : nullptr, s);
-        launch_p2m(*P, s);
-        for (int l = L - 1; l >= 1; --l) launch_m2m(*P, l, s);
-        FMM_HIP_CHECK(hipEventRecord(P->ev[3], s));
-        if (mixed)
-            launch_m2l_mixed(*P, s);
-        else if (P->m2l_pw)
-            launch_m2l_lanes(*P, P->m2l_pw, P->m2l_lg, s);
-        else
-            launch_m2l_fp64(*P, s);
-        FMM_HIP_CHECK(hipEventRecord(P->ev[4], s));
-        for (int l = 2; l <= L; ++l) launch_l2l(*P, l, s);
-        FMM_HIP_CHECK(hipEventRecord(P->ev[5], s));
-        if (mixed)
-            launch_near_mixed(*P, dphi, s);
-        else
-            launch_near_fp64(*P, nullptr, dphi, s);
-        FMM_HIP_CHECK(hipEventRecord(P->ev[6], s));
+        EvalJob J = make_job(*P);
+        batch_gather_u((const EvalJob *)P->job_dev, J, du, s);
+        Plan *one = P;
+        run_batch(&one, 1, (const EvalJob *)P->job_dev, dphi, s, &P->ev[3]);
     }
     FMM_HIP_CHECK(hipGetLastError());
     P->evaluated = true;

@@ -294,3 +294,75 @@ def solve(tiling, xs, ys, u, xt=None, yt=None, eps=1e-6, **kw):
     """One-shot host solve: plan + eval + destroy."""
     with Plan(tiling, xs, ys, xt, yt, eps, **kw) as p:
         return p.eval(u)
+
+
+class Server:
+    """Continuous-batching solve server (fmm_server_* in the C ABI).
+
+    submit() copies the inputs and returns a ticket; poll() returns None while
+    the request is queued or running, else (phi, result) where result holds
+    the status, p, lmax and the submit / admit / start / end timestamps
+    (seconds, steady clock)."""
+
+    def __init__(self, hbm_budget_bytes: int = 8 << 30, max_inflight: int = 64, leaf_size: int = 64):
+        L = lib()
+        o = ServerOptions()
+        o.struct_size = C.sizeof(ServerOptions)
+        o.hbm_budget_bytes = int(hbm_budget_bytes)
+        o.max_inflight = int(max_inflight)
+        o.leaf_size = int(leaf_size)
+        self._s = C.c_void_p()
+        _check(L.fmm_server_create(C.byref(o), C.byref(self._s)))
+        self._n = {}
+
+    def submit(self, tiling, xs, ys, u, eps=1e-6, precision="auto", xt=None, yt=None) -> int:
+        src = _points_host(xs, ys)
+        tgt = None if xt is None else _points_host(xt, yt)
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        r = Request()
+        r.tiling = _tiling(tiling)
+        r.precision = PREC[precision] if isinstance(precision, str) else int(precision)
+        r.eps = float(eps)
+        r.n_src = len(src) // 2
+        r.n_tgt = r.n_src if tgt is None else len(tgt) // 2
+        r.src = src.ctypes.data if r.n_src else None
+        r.tgt = None if tgt is None else (tgt.ctypes.data if r.n_tgt else None)
+        r.u = u.ctypes.data if r.n_src else None
+        t = C.c_uint64()
+        _check(lib().fmm_submit(self._s, C.byref(r), C.byref(t)))
+        self._n[t.value] = r.n_tgt
+        return t.value
+
+    def poll(self, ticket: int):
+        n = self._n[ticket]
+        phi = np.empty(n, dtype=np.complex128)
+        res = Result()
+        st = lib().fmm_poll(self._s, C.c_uint64(ticket),
+                            phi.ctypes.data_as(C.POINTER(C.c_double)) if n else None, C.byref(res))
+        if st == 5:
+            return None
+        del self._n[ticket]
+        out = {"status": STATUS.get(res.status, res.status), "p": res.p, "lmax": res.lmax,
+               "t_submit": res.t_submit, "t_admit": res.t_admit, "t_start": res.t_start,
+               "t_end": res.t_end}
+        return (phi if st == 0 else None), out
+
+    def drain(self):
+        _check(lib().fmm_server_drain(self._s))
+
+    def close(self):
+        if getattr(self, "_s", None) and self._s.value:
+            lib().fmm_server_destroy(self._s)
+            self._s = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
