@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 LANE_OPS = 256 * 4 * 16 * 2.4e9
 # VALU instructions per source-target pair in the near-field inner loop of our
 # gfx950 build (counted from the kernels' AMD assembly; see the design notes).
-VALU_PER_PAIR = {"fp64": 98.0, "mixed": 40.0}
+VALU_PER_PAIR = {"fp64": 181.0, "mixed": 41.0}
 HBM_PEAK = 8.0e12
 MFMA_BF16_PEAK = 2.5e15
 FP64_PEAK = 78.6e12
@@ -50,6 +50,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--compare-fp64", action="store_true",
                     help="also time the plain FP64 form (reported under extra)")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests in the serving stream (0 = skip the serving leg)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one plain 512 MiB device copy first (HBM counter calibration)")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="Poisson arrival rate as a fraction of the saturated request rate")
     return ap.parse_args()
 
 
@@ -123,6 +129,61 @@ def cpu_baseline(orc, w, infos, tilings, sample):
             "detail": detail}
 
 
+def serve_bench(F, nreq, load, leaf):
+    """cfg5-shaped stream: N log-uniform in [1e3, 2e6], uniform or 4-Gaussian
+    sources (50/50), tiling uniform over three, eps in {1e-4, 1e-8}.  First
+    all requests at once (saturated throughput), then Poisson arrivals at
+    `load` times the saturated request rate; latency = end - submit."""
+    from paper_1204_3105_amd import inputs
+    reqs = inputs.serving_stream(nreq, seed=5, rate=1.0)
+    total_targets = sum(r.work.n_tgt for r in reqs)
+
+    def run(arrivals):
+        with F.Server(hbm_budget_bytes=64 << 30, max_inflight=64, leaf_size=leaf) as srv:
+            t0 = time.perf_counter()
+            pending = {}
+            lat = []
+            done = 0
+            k = 0
+            while done < len(reqs):
+                now = time.perf_counter() - t0
+                while k < len(reqs) and (arrivals is None or arrivals[k] <= now):
+                    r = reqs[k]
+                    w = r.work
+                    pending[srv.submit(r.tiling, w.xs, w.ys, w.u, eps=r.eps)] = k
+                    k += 1
+                    now = time.perf_counter() - t0
+                for t in list(pending):
+                    res = srv.poll(t)
+                    if res is not None:
+                        assert res[1]["status"] == "OK", res[1]
+                        lat.append(res[1]["t_end"] - res[1]["t_submit"])
+                        del pending[t]
+                        done += 1
+                if k < len(reqs) and arrivals is not None and not pending:
+                    time.sleep(max(0.0, min(0.002, arrivals[k] - (time.perf_counter() - t0))))
+                else:
+                    time.sleep(0.0002)
+            wall = time.perf_counter() - t0
+        return wall, np.array(lat)
+
+    wall_sat, lat_sat = run(None)
+    sat_rate = len(reqs) / wall_sat
+    rate = load * sat_rate
+    gaps = inputs.rng(55).exponential(1.0 / rate, len(reqs))
+    arrivals = np.cumsum(gaps)
+    wall, lat = run(arrivals)
+    return {
+        "requests": len(reqs), "total_targets": int(total_targets),
+        "saturated_requests_per_s": sat_rate, "saturated_targets_per_s": total_targets / wall_sat,
+        "poisson_rate_requests_per_s": rate, "load": load,
+        "targets_per_s": total_targets / wall,
+        "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+        "saturated_p50_ms": float(np.percentile(lat_sat, 50) * 1e3),
+        "saturated_p99_ms": float(np.percentile(lat_sat, 99) * 1e3),
+    }
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -142,6 +203,12 @@ def main():
     pts = torch.tensor(w.xs + 1j * w.ys, dtype=torch.complex128, device=dev)
     u = torch.tensor(w.u, dtype=torch.float64, device=dev)
     outs = {t: torch.empty(a.n, dtype=torch.complex128, device=dev) for t in tilings}
+    if a.calibrate_copy:
+        src = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print("bench: n=%d tilings=%s precision=%s steps=%d warmup=%d" %
           (a.n, tilings, a.precision, a.steps, a.warmup), file=sys.stderr, flush=True)
 
@@ -180,6 +247,13 @@ def main():
         wall64, infos64 = timed(F, torch, pts, u, tilings, a.eps, "fp64", a.leaf, a.steps, 1, outs)
         extra["fp64_form"] = {"value": len(tilings) * a.n * a.steps / wall64,
                               "ms_per_step": wall64 / a.steps * 1e3}
+
+    if a.serve_requests > 0:
+        print("bench: serving stream (%d requests) ..." % a.serve_requests, file=sys.stderr, flush=True)
+        extra["serving"] = serve_bench(F, a.serve_requests, a.serve_load, a.leaf)
+        print("bench: serving p50 %.2f ms p99 %.2f ms" % (extra["serving"]["p50_ms"],
+                                                          extra["serving"]["p99_ms"]),
+              file=sys.stderr, flush=True)
 
     cpu = None
     if not a.no_cpu_baseline:

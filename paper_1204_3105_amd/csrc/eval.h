@@ -35,9 +35,10 @@ struct EvalJob {
     const uint8_t *occ, *group;
     const double *cx, *cy;
     double *mp, *lc;
-    const double *m2l_pw, *m2l_lg, *binom;
+    const double *m2l_pw, *m2l_lg, *m2l_a0, *binom;
     const __bf16 *mix_tab;
     const int32_t *mix_tiles, *mix_list;
+    __bf16 *mix_b;   // split multipoles (mixed M2L B operands)
     double *phi;   // output, caller's target order, 2 n_tgt doubles
 };
 
@@ -72,13 +73,14 @@ inline unsigned persistent_grid(int64_t items, int per_cu)
 
 // Launchers (items are counted on the host from plan sizes).
 void batch_gather_u(const EvalJob *jobs_d, const EvalJob &J, const double *u, hipStream_t s);
-void batch_p2m(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
+void batch_p2m(const EvalJob *jobs, const BatchMap &m, int pmax, hipStream_t s);
 void batch_m2m(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_l2l(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_m2l_block(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_m2l_lanes(const EvalJob *jobs, const BatchMap &m, int pm, hipStream_t s);
 void batch_m2l_mixed(const EvalJob *jobs, const BatchMap &m, int MT, int KB, hipStream_t s);
 bool mixed_shape_supported(int MT, int KB);
+void batch_split_mp(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_near_fp64(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_near_mixed(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 

@@ -18,7 +18,7 @@
 namespace fmm {
 
 void mixed_pointers(const Plan &P, const __bf16 **tab, const int32_t **tiles, const int32_t **list,
-                    int *MT, int *KB);
+                    __bf16 **bsplit, int *MT, int *KB);
 
 EvalJob make_job(const Plan &P)
 {
@@ -76,11 +76,12 @@ EvalJob make_job(const Plan &P)
     J.lc = P.lc;
     J.m2l_pw = P.m2l_pw;
     J.m2l_lg = P.m2l_lg;
+    J.m2l_a0 = P.m2l_a0;
     J.binom = P.binom;
     J.phi = P.phi_int;
     if (P.precision == FMM_PREC_MIXED && P.mixed) {
         int MT, KB;
-        mixed_pointers(P, &J.mix_tab, &J.mix_tiles, &J.mix_list, &MT, &KB);
+        mixed_pointers(P, &J.mix_tab, &J.mix_tiles, &J.mix_list, &J.mix_b, &MT, &KB);
         J.MT = MT;
         J.KB = KB;
     }
@@ -130,9 +131,11 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
     int maxL = 0;
     for (int i = 0; i < n; ++i) maxL = std::max(maxL, plans[i]->geo.L);
 
+    int pmax = 1;
+    for (int i = 0; i < n; ++i) pmax = std::max(pmax, plans[i]->p);
     // P2M
     {
-        auto f = [&](const BatchMap &m) { batch_p2m(jobs_dev, m, s); };
+        auto f = [&](const BatchMap &m) { batch_p2m(jobs_dev, m, pmax, s); };
         for (int i = 0; i < n; ++i) Lc.add(i, 0, plans[i]->lev[plans[i]->geo.L].n, f);
         go(f);
     }
@@ -142,6 +145,16 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
         for (int i = 0; i < n; ++i) {
             const int l = plans[i]->geo.L - 1 - k;
             if (l >= 1) Lc.add(i, l, plans[i]->lev[l].n, f);
+        }
+        go(f);
+    }
+    // Split multipoles for the BF16x3 M2L.
+    {
+        auto f = [&](const BatchMap &m) { batch_split_mp(jobs_dev, m, s); };
+        for (int i = 0; i < n; ++i) {
+            const Plan &P = *plans[i];
+            if (P.precision != FMM_PREC_MIXED || P.mixed_tiles == 0) continue;
+            Lc.add(i, 0, (P.n_cells - P.lev[1].cell_off) * 4 * ((2 * P.p + 31) / 32), f);
         }
         go(f);
     }

@@ -81,55 +81,70 @@ void batch_gather_u(const EvalJob *jobs_d, const EvalJob &J, const double *u, hi
 }
 
 // ------------------------------------------------------------------ P2M
-// One wave per leaf: lane i holds one source, builds w^k incrementally and
-// the wave reduces each term; lane k keeps coefficient k.
+// One wave per leaf.  Each lane takes one source of a 64-source chunk and
+// writes its terms -u w^k / k (k = 1..p) to LDS; then lanes sum the rows of
+// that table (lane r owns row r: Re/Im of one coefficient), so every
+// coefficient is a plain sum over the chunk in source order.
 __global__ __launch_bounds__(64) void k_p2m(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
+    constexpr int kChunkS = 32;
+    constexpr int kStride = kChunkS + 1;   // odd stride: conflict-free row reads
+    extern __shared__ double tab[];          // 2 (pmax + 1) rows of kStride
     const int lane = threadIdx.x;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
         const int e = batch_entry(bm, item);
         const EvalJob &J = jobs[bm.job[e]];
         const int64_t gid = J.leaf_off + (item - bm.pre[e]);
         const int32_t b = J.sb[gid], en = J.se[gid];
-        const int P1 = J.p + 1;
+        const int P1 = J.p + 1, R = 2 * P1;
         double *row = J.mp + gid * 2 * P1;
-        double acc_re = 0.0, acc_im = 0.0;
         const double inv = 1.0 / J.scale[J.L];
         const double c0 = J.cx[gid], c1 = J.cy[gid];
-        for (int32_t base = b; base < en; base += 64) {
-            const int32_t i = base + lane;
+        double acc = 0.0, acc2 = 0.0;   // rows lane and lane + 64
+        for (int32_t base = b; base < en; base += kChunkS) {
+            // lanes 0..31 each take a source; lanes 32..63 take the odd
+            // coefficients of the same source (halves the serial chain)
+            const int src_lane = lane & (kChunkS - 1), half = lane / kChunkS;
+            const int32_t i = base + src_lane;
             const bool ok = i < en;
             const double u = ok ? J.su[i] : 0.0;
             const cd w = ok ? cd{(J.sx[i] - c0) * inv, (J.sy[i] - c1) * inv} : cd{0.0, 0.0};
-            double s0 = u;
-            for (int o = 32; o > 0; o >>= 1) s0 += __shfl_xor(s0, o);
-            if (lane == 0) acc_re += s0;
-            cd pw = {1.0, 0.0};
-            for (int k = 1; k <= J.p; ++k) {
-                pw = cmul(pw, w);
+            const cd w2 = cmul(w, w);
+            __syncthreads();
+            if (half == 0) {
+                tab[0 * kStride + src_lane] = u;
+                tab[1 * kStride + src_lane] = 0.0;
+            }
+            cd pw = half ? w : cmul(w, w);   // w^1 or w^2
+            for (int k = 1 + (half ? 0 : 1); k <= J.p; k += 2) {
                 const double f = -u / (double)k;
-                double tr = pw.x * f, ti = pw.y * f;
-                for (int o = 32; o > 0; o >>= 1) {
-                    tr += __shfl_xor(tr, o);
-                    ti += __shfl_xor(ti, o);
-                }
-                if (lane == k) {
-                    acc_re += tr;
-                    acc_im += ti;
-                }
+                tab[(2 * k) * kStride + src_lane] = pw.x * f;
+                tab[(2 * k + 1) * kStride + src_lane] = pw.y * f;
+                pw = cmul(pw, w2);
+            }
+            __syncthreads();
+            const int n = en - base < kChunkS ? en - base : kChunkS;
+            if (lane < R) {
+                double s = 0.0;
+                for (int j = 0; j < n; ++j) s += tab[lane * kStride + j];
+                acc += s;
+            }
+            if (lane + 64 < R) {
+                double s = 0.0;
+                for (int j = 0; j < n; ++j) s += tab[(lane + 64) * kStride + j];
+                acc2 += s;
             }
         }
-        if (lane < P1) {
-            row[2 * lane] = acc_re;
-            row[2 * lane + 1] = acc_im;
-        }
+        if (lane < R) row[lane] = acc;
+        if (lane + 64 < R) row[lane + 64] = acc2;
     }
 }
 
-void batch_p2m(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
+void batch_p2m(const EvalJob *jobs, const BatchMap &m, int pmax, hipStream_t s)
 {
     if (m.n <= 0 || m.pre[m.n] <= 0) return;
-    hipLaunchKernelGGL(k_p2m, dim3(persistent_grid(m.pre[m.n], 64)), dim3(64), 0, s, jobs, m);
+    const size_t lds = (size_t)2 * (pmax + 1) * 33 * sizeof(double);
+    hipLaunchKernelGGL(k_p2m, dim3(persistent_grid(m.pre[m.n], 64)), dim3(64), lds, s, jobs, m);
 }
 
 // ------------------------------------------------------------------ M2M

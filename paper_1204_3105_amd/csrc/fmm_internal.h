@@ -119,7 +119,7 @@ struct Plan {
     const double *binom = nullptr; // C(n, k), n, k <= 2 kMaxP + 1 (per device)
 
     // M2L offset tables (lane kernel): (-1/delta)^k and Log(c_T - c_S)
-    double *m2l_pw = nullptr, *m2l_lg = nullptr;
+    double *m2l_pw = nullptr, *m2l_lg = nullptr, *m2l_a0 = nullptr;
     int m2l_pm = 0;
 
     // mixed precision M2L operands
@@ -194,7 +194,8 @@ const double *device_binom(int *err);
 
 // m2l.hip
 int m2l_pm_for(int p);
-void m2l_tables(const Plan &P, int pm, std::vector<double> &pw, std::vector<double> &lg);
+void m2l_tables(const Plan &P, int pm, std::vector<double> &pw, std::vector<double> &lg,
+                std::vector<double> &a0);
 
 // m2l_mixed.hip
 size_t mixed_bytes(const Plan &P);

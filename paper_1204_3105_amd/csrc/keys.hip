@@ -65,21 +65,47 @@ __global__ void k_bbox(const double *__restrict__ pts, int64_t n, double *__rest
 
 __global__ void k_bbox_final(const double *__restrict__ partial, int nparts, double *__restrict__ out)
 {
-    if (threadIdx.x != 0) return;
+    // One block of 256 threads reduces up to 256 partial boxes.
     double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY, bad = 0.0;
-    for (int k = 0; k < nparts; ++k) {
+    for (int k = threadIdx.x; k < nparts; k += blockDim.x) {
         mnx = fmin(mnx, partial[5 * k]);
         mxx = fmax(mxx, partial[5 * k + 1]);
         mny = fmin(mny, partial[5 * k + 2]);
         mxy = fmax(mxy, partial[5 * k + 3]);
         bad += partial[5 * k + 4];
     }
-    // Accumulate into out[0..4] (callers run this once per point set).
-    out[0] = fmin(out[0], mnx);
-    out[1] = fmax(out[1], mxx);
-    out[2] = fmin(out[2], mny);
-    out[3] = fmax(out[3], mxy);
-    out[4] += bad;
+    for (int o = 32; o > 0; o >>= 1) {
+        mnx = fmin(mnx, __shfl_xor(mnx, o));
+        mxx = fmax(mxx, __shfl_xor(mxx, o));
+        mny = fmin(mny, __shfl_xor(mny, o));
+        mxy = fmax(mxy, __shfl_xor(mxy, o));
+        bad += __shfl_xor(bad, o);
+    }
+    __shared__ double sh[5][4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][w] = mnx;
+        sh[1][w] = mxx;
+        sh[2][w] = mny;
+        sh[3][w] = mxy;
+        sh[4][w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+            sh[0][0] = fmin(sh[0][0], sh[0][k]);
+            sh[1][0] = fmax(sh[1][0], sh[1][k]);
+            sh[2][0] = fmin(sh[2][0], sh[2][k]);
+            sh[3][0] = fmax(sh[3][0], sh[3][k]);
+            sh[4][0] += sh[4][k];
+        }
+        // Accumulate into out[0..4] (callers run this once per point set).
+        out[0] = fmin(out[0], sh[0][0]);
+        out[1] = fmax(out[1], sh[1][0]);
+        out[2] = fmin(out[2], sh[2][0]);
+        out[3] = fmax(out[3], sh[3][0]);
+        out[4] += sh[4][0];
+    }
 }
 
 void launch_bbox(const double *pts, int64_t n, double *partial, int nblocks, hipStream_t s)
@@ -89,7 +115,7 @@ void launch_bbox(const double *pts, int64_t n, double *partial, int nblocks, hip
 
 void launch_bbox_final(const double *partial, int nparts, double *out4, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(64), 0, s, partial, nparts, out4);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, partial, nparts, out4);
 }
 
 // ------------------------------------------------------------------ keys

@@ -56,11 +56,13 @@ static void slot_offset(const Plan &P, int l, int g, int s, double &dx, double &
 
 // Tables: pw[((l*G + g)*S + s)*(PM+1) + k] = (-1/delta)^k (complex, zero
 // beyond p), lg[(l*G + g)*S + s] = Log(c_T - c_S).
-void m2l_tables(const Plan &P, int pm, std::vector<double> &pw, std::vector<double> &lg)
+void m2l_tables(const Plan &P, int pm, std::vector<double> &pw, std::vector<double> &lg,
+                std::vector<double> &a0)
 {
     const int L = P.geo.L, G = P.tables.n_groups, S = P.tables.e4_width;
     pw.assign((size_t)(L + 1) * G * S * (pm + 1) * 2, 0.0);
     lg.assign((size_t)(L + 1) * G * S * 2, 0.0);
+    a0.assign((size_t)(L + 1) * G * S * (pm + 1) * 2, 0.0);
     for (int l = 1; l <= L; ++l)
         for (int g = 0; g < G; ++g)
             for (int s = 0; s < P.tables.e4_count[g]; ++s) {
@@ -77,6 +79,16 @@ void m2l_tables(const Plan &P, int pm, std::vector<double> &pw, std::vector<doub
                 for (int k = 0; k <= P.p; ++k) {
                     pw[2 * (idx * (pm + 1) + k)] = cr;
                     pw[2 * (idx * (pm + 1) + k) + 1] = ci;
+                    // monopole coefficient of row k: Log(c_T - c_S) for k = 0,
+                    // -delta^-k / k = -(-1)^k (-1/delta)^k / k otherwise
+                    if (k == 0) {
+                        a0[2 * (idx * (pm + 1))] = lg[2 * idx];
+                        a0[2 * (idx * (pm + 1)) + 1] = lg[2 * idx + 1];
+                    } else {
+                        const double sg = (k & 1) ? 1.0 : -1.0;
+                        a0[2 * (idx * (pm + 1) + k)] = sg * cr / (double)k;
+                        a0[2 * (idx * (pm + 1) + k) + 1] = sg * ci / (double)k;
+                    }
                     double nr = cr * qx - ci * qy, ni = cr * qy + ci * qx;
                     cr = nr;
                     ci = ni;

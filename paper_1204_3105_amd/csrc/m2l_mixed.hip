@@ -37,7 +37,7 @@ struct MixedLayout {
     int G, S, pm;
     size_t tab_elems;    // bf16 elements per (level, group, slot) table
     int n_tiles;
-    size_t off_tab, off_tiles, off_list, off_cnt;   // byte offsets in P.mixed
+    size_t off_tab, off_tiles, off_list, off_cnt, off_b;   // byte offsets in P.mixed
 };
 
 static MixedLayout layout_of(const Plan &P)
@@ -63,7 +63,9 @@ static MixedLayout layout_of(const Plan &P)
     o = (o + 255) & ~(size_t)255;
     m.off_list = o;
     o += (size_t)(ncell + 1) * sizeof(int32_t);
-    m.tab_elems = m.tab_elems;
+    o = (o + 255) & ~(size_t)255;
+    m.off_b = o;   // split multipoles: [cell][kb][split][q] bf16x8
+    o += (size_t)ncell * m.KB * 12 * 16;
     return m;
 }
 
@@ -71,7 +73,7 @@ size_t mixed_bytes(const Plan &P)
 {
     if (P.m2l_pm == 0) return 256;
     MixedLayout m = layout_of(P);
-    return m.off_list + (size_t)(P.n_cells + 1) * sizeof(int32_t) + 256;
+    return m.off_b + (size_t)P.n_cells * m.KB * 12 * 16 + 256;
 }
 
 struct CellOffsets {
@@ -143,16 +145,23 @@ __global__ __launch_bounds__(64) void k_build_mixed_tables(int p, int MT, int KB
     }
 }
 
-// Group target cells of levels >= 1 by (level, group).
+// Group target cells of levels >= 1 by (level, group): per-block LDS
+// histograms, one global atomic per (block, key).
 __global__ void k_group_count(int64_t first, int64_t n_cells, int L, int G, CellOffsets cell_off,
                               const uint8_t *__restrict__ occ,
                               const uint8_t *__restrict__ group, int32_t *__restrict__ cnt)
 {
+    __shared__ int32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t gid = first + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (gid >= n_cells || !(occ[gid] & 2)) return;
-    int l = 1;
-    while (l < L && gid >= cell_off.v[l + 1]) ++l;
-    atomicAdd(&cnt[l * G + group[gid]], 1);
+    if (gid < n_cells && (occ[gid] & 2)) {
+        int l = 1;
+        while (l < L && gid >= cell_off.v[l + 1]) ++l;
+        atomicAdd(&h[l * G + group[gid]], 1);
+    }
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd(&cnt[threadIdx.x], h[threadIdx.x]);
 }
 
 __global__ void k_group_scatter(int64_t first, int64_t n_cells, int L, int G, CellOffsets cell_off,
@@ -160,12 +169,21 @@ __global__ void k_group_scatter(int64_t first, int64_t n_cells, int L, int G, Ce
                                 const uint8_t *__restrict__ group, const int32_t *__restrict__ off,
                                 int32_t *__restrict__ cursor, int32_t *__restrict__ list)
 {
+    __shared__ int32_t h[256], base[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t gid = first + blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (gid >= n_cells || !(occ[gid] & 2)) return;
-    int l = 1;
-    while (l < L && gid >= cell_off.v[l + 1]) ++l;
-    const int key = l * G + group[gid];
-    list[off[key] + atomicAdd(&cursor[key], 1)] = (int32_t)gid;
+    int key = -1, rank = 0;
+    if (gid < n_cells && (occ[gid] & 2)) {
+        int l = 1;
+        while (l < L && gid >= cell_off.v[l + 1]) ++l;
+        key = l * G + group[gid];
+        rank = atomicAdd(&h[key], 1);
+    }
+    __syncthreads();
+    if (h[threadIdx.x]) base[threadIdx.x] = atomicAdd(&cursor[threadIdx.x], h[threadIdx.x]);
+    __syncthreads();
+    if (key >= 0) list[off[key] + base[key] + rank] = (int32_t)gid;
 }
 
 int mixed_setup(Plan &P)
@@ -222,9 +240,17 @@ int mixed_setup(Plan &P)
 template <int MT, int KB>
 __global__ __launch_bounds__(256) void k_m2l_bf16x3(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
+    constexpr int NA = MT * KB * 3 * 64;   // bf16x8 vectors of one slot's matrix
+    __shared__ bf16x8 Ash[NA];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int n = lane % 16, q = lane / 16;
-    for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
+    // XCD-aware order: the 8 XCDs each take a contiguous eighth of the tiles
+    // (workgroups are dealt to XCDs round-robin), so the tiles of one
+    // (level, group) -- which share translation matrices -- stay on one L2.
+    const int64_t total = bm.pre[bm.n];
+    const int xcd = blockIdx.x % 8, lb = blockIdx.x / 8, nb = gridDim.x / 8;
+    const int64_t t_beg = total * xcd / 8, t_end = total * (xcd + 1) / 8;
+    for (int64_t item = t_beg + lb; item < t_end; item += nb) {
         const int e = batch_entry(bm, item);
         const EvalJob &J = jobs[bm.job[e]];
         const int32_t *tile = J.mix_tiles + 4 * (item - bm.pre[e]);
@@ -234,45 +260,42 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const EvalJob *__restrict__ 
         const int col = 16 * w + n;
         const bool valid = col < count;
         const int32_t gid = valid ? J.mix_list[start + col] : -1;
-        const int P1 = p + 1, twoP = 2 * p;
+        const int P1 = p + 1;
         const int tl = J.sept ? l : 0;
         double acc[MT][4];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0;
-        const size_t tab_elems = (size_t)MT * KB * 3 * 512;
         for (int s = 0; s < S; ++s) {
             const int32_t src = valid ? J.e4[(int64_t)gid * S + s] : -1;
-            // Wave-uniform skip when no lane has a source in this slot.
-            if (__ballot(src >= 0) == 0ull) continue;
+            // Block-uniform skip when no target of the tile has this slot.
+            if (!__syncthreads_or(src >= 0)) continue;
+            const bf16x8 *T = (const bf16x8 *)(J.mix_tab + (((size_t)tl * G + g) * S + s) * (size_t)(NA * 8));
+            for (int i = threadIdx.x; i < NA; i += 256) Ash[i] = T[i];
             const double *a = src >= 0 ? J.mp + (int64_t)src * 2 * P1 : nullptr;
             bf16x8 bh[KB], bmd[KB], bl[KB];
+            const bf16x8 *Bs = (const bf16x8 *)J.mix_b + ((int64_t)(src >= 0 ? src : 0) * KB * 3) * 4 + q;
 #pragma unroll
             for (int kb = 0; kb < KB; ++kb) {
+                if (src >= 0) {
+                    bh[kb] = Bs[(kb * 3 + 0) * 4];
+                    bmd[kb] = Bs[(kb * 3 + 1) * 4];
+                    bl[kb] = Bs[(kb * 3 + 2) * 4];
+                } else {
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int idx = 32 * kb + 8 * q + j;
-                    float x = 0.0f;
-                    if (a && idx < twoP) x = (float)a[2 + idx];
-                    __bf16 h, m, lo;
-                    split3(x, h, m, lo);
-                    bh[kb][j] = h;
-                    bmd[kb][j] = m;
-                    bl[kb][j] = lo;
+                    for (int j = 0; j < 8; ++j) bh[kb][j] = bmd[kb][j] = bl[kb][j] = (__bf16)0.0f;
                 }
             }
-            const bf16x8 *T = (const bf16x8 *)(J.mix_tab + (((size_t)tl * G + g) * S + s) * tab_elems);
-            const size_t pidx = ((size_t)l * G + g) * S + s;
-            const double *pw = J.m2l_pw + 2 * pidx * (pm + 1);
             const double a0 = a ? a[0] : 0.0;
-            const double lgr = J.m2l_lg[2 * pidx], lgi = J.m2l_lg[2 * pidx + 1];
+            const double *A0 = J.m2l_a0 + 2 * (((size_t)l * G + g) * S + s) * (pm + 1);
+            __syncthreads();
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
                 floatx4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int kb = 0; kb < KB; ++kb) {
-                    const bf16x8 *t3 = T + (size_t)((mt * KB + kb) * 3) * 64;
+                    const bf16x8 *t3 = Ash + (mt * KB + kb) * 3 * 64;
                     const bf16x8 ah = t3[lane], am = t3[64 + lane], al = t3[128 + lane];
                     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[kb], c, 0, 0, 0);
                     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bmd[kb], c, 0, 0, 0);
@@ -284,21 +307,12 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const EvalJob *__restrict__ 
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int row = 16 * mt + 4 * q + j;
-                    const int m = row >> 1;
-                    double t0 = 0.0;
-                    if (a && m <= p) {
-                        if (m == 0) {
-                            t0 = a0 * ((row & 1) ? lgi : lgr);
-                        } else {
-                            // -a0/m delta^-m, delta^-m = (-1)^m (-1/delta)^m
-                            double d = pw[2 * m + (row & 1)];
-                            if (m & 1) d = -d;
-                            t0 = -a0 / (double)m * d;
-                        }
-                    }
+                    // monopole terms in FP64: a0 Log(c_T - c_S), -a0 delta^-m / m
+                    const double t0 = (a && row < 2 * P1) ? a0 * A0[row] : 0.0;
                     acc[mt][j] += (double)c[j] + t0;
                 }
             }
+            __syncthreads();
         }
         if (valid) {
             double *out = J.lc + (int64_t)gid * 2 * P1;
@@ -314,15 +328,55 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const EvalJob *__restrict__ 
 }
 
 void mixed_pointers(const Plan &P, const __bf16 **tab, const int32_t **tiles, const int32_t **list,
-                    int *MT, int *KB)
+                    __bf16 **bsplit, int *MT, int *KB)
 {
     MixedLayout m = layout_of(P);
-    const char *base = (const char *)P.mixed;
+    char *base = (char *)P.mixed;
+    *bsplit = base ? (__bf16 *)(base + m.off_b) : nullptr;
     *tab = base ? (const __bf16 *)(base + m.off_tab) : nullptr;
     *tiles = base ? (const int32_t *)(base + m.off_tiles) : nullptr;
     *list = base ? (const int32_t *)(base + m.off_list) : nullptr;
     *MT = m.MT;
     *KB = m.KB;
+}
+
+// Split every multipole of levels >= 1 into three bfloat16 parts in the
+// MFMA B-operand layout: thread per (cell, k-block, lane group q).
+__global__ __launch_bounds__(256) void k_split_mp(const EvalJob *__restrict__ jobs, BatchMap bm)
+{
+    for (int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; item < bm.pre[bm.n];
+         item += (int64_t)gridDim.x * blockDim.x) {
+        const int e = batch_entry(bm, item);
+        const EvalJob &J = jobs[bm.job[e]];
+        const int64_t it = item - bm.pre[e];
+        const int q = (int)(it % 4), kb = (int)((it / 4) % J.KB);
+        const int64_t cell = J.m2l_first + it / (4 * J.KB);
+        const double *a = J.mp + cell * 2 * (J.p + 1);
+        const bool src = (J.occ[cell] & 1) != 0;
+        bf16x8 h, m, l;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int idx = 32 * kb + 8 * q + j;
+            const float x = (src && idx < 2 * J.p) ? (float)a[2 + idx] : 0.0f;
+            __bf16 hh, mm, ll;
+            split3(x, hh, mm, ll);
+            h[j] = hh;
+            m[j] = mm;
+            l[j] = ll;
+        }
+        bf16x8 *out = (bf16x8 *)J.mix_b + ((cell * J.KB + kb) * 3) * 4 + q;
+        out[0] = h;
+        out[4] = m;
+        out[8] = l;
+    }
+}
+
+void batch_split_mp(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
+{
+    if (m.n <= 0 || m.pre[m.n] <= 0) return;
+    const int64_t threads = m.pre[m.n];
+    const unsigned grid = (unsigned)std::min<int64_t>((threads + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_split_mp, dim3(grid), dim3(256), 0, s, jobs, m);
 }
 
 bool mixed_shape_supported(int MT, int KB)
@@ -335,7 +389,7 @@ bool mixed_shape_supported(int MT, int KB)
 void batch_m2l_mixed(const EvalJob *jobs, const BatchMap &m, int MT, int KB, hipStream_t s)
 {
     if (m.n <= 0 || m.pre[m.n] <= 0) return;
-    const dim3 grid(persistent_grid(m.pre[m.n], 16)), block(256);
+    const dim3 grid((persistent_grid(m.pre[m.n], 16) + 7) / 8 * 8), block(256);
     switch (MT * 10 + KB) {
     case 11: hipLaunchKernelGGL((k_m2l_bf16x3<1, 1>), grid, block, 0, s, jobs, m); break;
     case 21: hipLaunchKernelGGL((k_m2l_bf16x3<2, 1>), grid, block, 0, s, jobs, m); break;

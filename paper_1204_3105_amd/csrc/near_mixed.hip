@@ -7,7 +7,8 @@
 // absolute FP32 coordinates would suffer.  Per pair:
 //   Re += u * ln|y - x|  = (u ln2 / 2) * log2(dx^2 + dy^2)   (hardware log2)
 //   Im += u * atan2(dy, dx)                                   (own atan2)
-// Both sums are Kahan-compensated in FP32 and added to the FP64 far field.
+// Both sums are compensated in FP32 (Kahan steps on blocks of four plainly
+// summed pairs) and added to the FP64 far field.
 // A pair with a zero separation is skipped (bitwise-equal points).
 #include "eval.h"
 
@@ -81,12 +82,27 @@ __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ j
         }
 
         float rs = 0.0f, rc = 0.0f, is = 0.0f, ic = 0.0f;
+        // Kahan step for both sums.
+        auto acc = [&](float vr, float vi) {
+            const float yr = vr - rc;
+            const float tr = rs + yr;
+            rc = (tr - rs) - yr;
+            rs = tr;
+            const float yi = vi - ic;
+            const float ti = is + yi;
+            ic = (ti - is) - yi;
+            is = ti;
+        };
         for (int k = 0; k < J.nw; ++k) {
-            const int32_t c = J.near[li * J.nw + k];
+            // Slot 0 is the target leaf itself: only there can a source have
+            // the target's exact coordinates (equal points share a leaf key).
+            const int32_t c = __builtin_amdgcn_readfirstlane(J.near[li * J.nw + k]);
             if (c < 0) continue;
+            const bool self = c == gid;
             const float ax = tlx - (float)(J.cx[c] - tcx);
             const float ay = tly - (float)(J.cy[c] - tcy);
-            const int32_t b0 = J.sb[c], e0 = J.se[c];
+            const int32_t b0 = __builtin_amdgcn_readfirstlane(J.sb[c]);
+            const int32_t e0 = __builtin_amdgcn_readfirstlane(J.se[c]);
             for (int32_t base = b0; base < e0; base += 64) {
                 __syncthreads();
                 const int32_t i = base + lane;
@@ -96,24 +112,39 @@ __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ j
                 }
                 __syncthreads();
                 const int nsrc = e0 - base < 64 ? e0 - base : 64;
-                for (int j = 0; j < nsrc; ++j) {
-                    const float4 sv = sh[j];
-                    const float dx = ax - sv.x, dy = ay - sv.y;
-                    const float r2 = fmaf(dx, dx, dy * dy);
-                    const bool live = r2 > 0.0f;
-                    const float lg = __log2f(live ? r2 : 1.0f);
-                    const float at = atan2_f32(dy, dx);
-                    const float vr = live ? sv.z * lg : 0.0f;
-                    const float vi = live ? sv.w * at : 0.0f;
-                    // Kahan steps
-                    const float yr = vr - rc;
-                    const float tr = rs + yr;
-                    rc = (tr - rs) - yr;
-                    rs = tr;
-                    const float yi = vi - ic;
-                    const float ti = is + yi;
-                    ic = (ti - is) - yi;
-                    is = ti;
+                if (self) {
+                    for (int j = 0; j < nsrc; ++j) {
+                        const float4 sv = sh[j];
+                        const float dx = ax - sv.x, dy = ay - sv.y;
+                        const float r2 = fmaf(dx, dx, dy * dy);
+                        const bool live = r2 > 0.0f;
+                        const float lg = __log2f(live ? r2 : 1.0f);
+                        const float at = atan2_f32(dy, dx);
+                        acc(live ? sv.z * lg : 0.0f, live ? sv.w * at : 0.0f);
+                    }
+                } else {
+                    // Distinct leaves: separations are nonzero; the floor
+                    // only keeps a pair closer than FP32 resolution finite.
+                    // Four pairs are summed plainly, then Kahan-added.
+                    int j = 0;
+                    for (; j + 4 <= nsrc; j += 4) {
+                        float pr = 0.0f, pi = 0.0f;
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) {
+                            const float4 sv = sh[j + jj];
+                            const float dx = ax - sv.x, dy = ay - sv.y;
+                            const float r2 = fmaxf(fmaf(dx, dx, dy * dy), 1e-37f);
+                            pr = fmaf(sv.z, __log2f(r2), pr);
+                            pi = fmaf(sv.w, atan2_f32(dy, dx), pi);
+                        }
+                        acc(pr, pi);
+                    }
+                    for (; j < nsrc; ++j) {
+                        const float4 sv = sh[j];
+                        const float dx = ax - sv.x, dy = ay - sv.y;
+                        const float r2 = fmaxf(fmaf(dx, dx, dy * dy), 1e-37f);
+                        acc(sv.z * __log2f(r2), sv.w * atan2_f32(dy, dx));
+                    }
                 }
             }
         }

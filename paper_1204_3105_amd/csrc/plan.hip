@@ -430,13 +430,17 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     FMM_HIP_CHECK(hipMemsetAsync(P->lc, 0, sizeof(double) * 2 * (P->p + 1) * C, s));
     P->m2l_pm = m2l_pm_for(P->p);
     if (P->m2l_pm > 0 && g.L >= 1) {
-        std::vector<double> pw, lg;
-        m2l_tables(*P, P->m2l_pm, pw, lg);
-        P->m2l_pw = take<double>(P, (int64_t)pw.size(), &err);
-        P->m2l_lg = take<double>(P, (int64_t)lg.size(), &err);
+        std::vector<double> pw, lg, a0;
+        m2l_tables(*P, P->m2l_pm, pw, lg, a0);
+        std::vector<double> all(pw.size() + lg.size() + a0.size());
+        std::copy(pw.begin(), pw.end(), all.begin());
+        std::copy(lg.begin(), lg.end(), all.begin() + pw.size());
+        std::copy(a0.begin(), a0.end(), all.begin() + pw.size() + lg.size());
+        P->m2l_pw = take<double>(P, (int64_t)all.size(), &err);
         if (err) return fail(FMM_E_NOMEM, "device allocation failed (M2L tables)");
-        FMM_HIP_CHECK(hipMemcpy(P->m2l_pw, pw.data(), pw.size() * sizeof(double), hipMemcpyHostToDevice));
-        FMM_HIP_CHECK(hipMemcpy(P->m2l_lg, lg.data(), lg.size() * sizeof(double), hipMemcpyHostToDevice));
+        P->m2l_lg = P->m2l_pw + pw.size();
+        P->m2l_a0 = P->m2l_lg + lg.size();
+        FMM_HIP_CHECK(hipMemcpy(P->m2l_pw, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice));
     }
     if (P->precision == FMM_PREC_MIXED) {
         P->sxl = take<float>(P, N, &err);
