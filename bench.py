@@ -60,23 +60,32 @@ def parse():
 
 
 def run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs):
-    infos = {t: [] for t in tilings}
-    for _ in range(steps):
+    """`steps` passes of plan + evaluate per tiling, all on torch's current
+    stream.  Plans are released without a host wait; the last pass's plans
+    are returned open so their event timings can be read after the clock."""
+    kept = {}
+    for step in range(steps):
         for t in tilings:
             plan = F.Plan(t, src=pts, tgt=pts, eps=eps, precision=prec, leaf_size=leaf)
             plan.eval(u, out=outs[t])
-            infos[t].append(plan.info())
-            plan.close()
-    return infos
+            if step == steps - 1:
+                kept[t] = plan
+            else:
+                plan.close()
+    return kept
 
 
 def timed(F, torch, pts, u, tilings, eps, prec, leaf, steps, warmup, outs):
-    run_steps(F, torch, pts, u, tilings, eps, prec, leaf, warmup, outs)
+    for plan in run_steps(F, torch, pts, u, tilings, eps, prec, leaf, warmup, outs).values():
+        plan.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    infos = run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs)
+    kept = run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    infos = {t: [plan.info()] for t, plan in kept.items()}
+    for plan in kept.values():
+        plan.close()
     return t1 - t0, infos
 
 

@@ -28,8 +28,11 @@
  *    return.  A plan owns all of its device memory until fmm_plan_destroy.
  *  - Pointers are host pointers unless options.device_pointers is set, in
  *    which case they are device pointers on the current HIP device and the
- *    work is ordered on options.stream (hipStream_t; NULL = a stream the
- *    plan creates).  With host pointers every call is synchronous.
+ *    work is ordered on options.stream (hipStream_t; NULL = the null
+ *    stream): inputs are read and outputs written in that stream's order,
+ *    and fmm_plan_destroy returns without waiting (the plan's memory is
+ *    reused only behind its last work).  With host pointers every call is
+ *    synchronous.
  *  - Errors are status codes, never exceptions; fmm_last_error() returns a
  *    thread-local message for the last non-OK status.
  *  - Plans are independent; one plan must not be evaluated concurrently

@@ -39,6 +39,9 @@ struct EvalJob {
     const __bf16 *mix_tab;
     const int32_t *mix_tiles, *mix_list;
     __bf16 *mix_b;   // split multipoles (mixed M2L B operands)
+    // Device counts written at plan time: [0] near-field items, [1] mixed M2L
+    // tiles.  Launches are sized by host upper bounds; kernels stop here.
+    const int32_t *counts;
     double *phi;   // output, caller's target order, 2 n_tgt doubles
 };
 
@@ -71,11 +74,14 @@ inline unsigned persistent_grid(int64_t items, int per_cu)
     return (unsigned)(items < cap ? (items > 0 ? items : 1) : cap);
 }
 
-// Launchers (items are counted on the host from plan sizes).
+// Launchers (items are counted on the host from plan sizes, or bounded
+// there when only the device knows the count).
 void batch_gather_u(const EvalJob *jobs_d, const EvalJob &J, const double *u, hipStream_t s);
 void batch_p2m(const EvalJob *jobs, const BatchMap &m, int pmax, hipStream_t s);
 void batch_m2m(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_l2l(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
+void batch_m2m_lanes(const EvalJob *jobs, const BatchMap &m, int pm, int gs, hipStream_t s);
+void batch_l2l_lanes(const EvalJob *jobs, const BatchMap &m, int pm, hipStream_t s);
 void batch_m2l_block(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_m2l_lanes(const EvalJob *jobs, const BatchMap &m, int pm, hipStream_t s);
 void batch_m2l_mixed(const EvalJob *jobs, const BatchMap &m, int MT, int KB, hipStream_t s);

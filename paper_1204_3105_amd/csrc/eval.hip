@@ -74,6 +74,7 @@ EvalJob make_job(const Plan &P)
     J.cy = P.cy;
     J.mp = P.mp;
     J.lc = P.lc;
+    J.counts = P.counts;
     J.m2l_pw = P.m2l_pw;
     J.m2l_lg = P.m2l_lg;
     J.m2l_a0 = P.m2l_a0;
@@ -139,15 +140,26 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
         for (int i = 0; i < n; ++i) Lc.add(i, 0, plans[i]->lev[plans[i]->geo.L].n, f);
         go(f);
     }
-    // M2M, step k: level L_i - 1 - k.
-    for (int k = 0; k < maxL; ++k) {
-        auto f = [&](const BatchMap &m) { batch_m2m(jobs_dev, m, s); };
-        for (int i = 0; i < n; ++i) {
-            const int l = plans[i]->geo.L - 1 - k;
-            if (l >= 1) Lc.add(i, l, plans[i]->lev[l].n, f);
-        }
-        go(f);
-    }
+    // Translation kernel variants: lane form for orders up to 48 (register
+    // arrays of PM + 1 coefficients), block form beyond.
+    const int pms[] = {0, 8, 16, 24, 32, 40, 48};
+    // M2M, step k: level L_i - 1 - k; lane groups of 4 (base 4) or 8 (base 7).
+    for (int k = 0; k < maxL; ++k)
+        for (int pm : pms)
+            for (int gs : {4, 8}) {
+                if (pm == 0 && gs == 8) continue;
+                auto f = [&](const BatchMap &m) {
+                    if (pm == 0) batch_m2m(jobs_dev, m, s);
+                    else batch_m2m_lanes(jobs_dev, m, pm, gs, s);
+                };
+                for (int i = 0; i < n; ++i) {
+                    const Plan &P = *plans[i];
+                    const int l = P.geo.L - 1 - k;
+                    if (l < 1 || P.m2l_pm != pm || (pm && (base_of(P.geo.tiling) > 4 ? 8 : 4) != gs)) continue;
+                    Lc.add(i, l, P.lev[l].n, f);
+                }
+                go(f);
+            }
     // Split multipoles for the BF16x3 M2L.
     {
         auto f = [&](const BatchMap &m) { batch_split_mp(jobs_dev, m, s); };
@@ -162,8 +174,8 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
 
     // M2L, one launch per kernel variant present in the batch.
     {
-        const int pms[] = {8, 16, 24, 32, 40, 48};
         for (int pm : pms) {
+            if (pm == 0) continue;
             auto f = [&](const BatchMap &m) { batch_m2l_lanes(jobs_dev, m, pm, s); };
             for (int i = 0; i < n; ++i) {
                 const Plan &P = *plans[i];
@@ -197,12 +209,16 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
     if (ev) hipEventRecord(ev[1], s);
 
     // L2L, step k: level 2 + k.
-    for (int l = 2; l <= maxL; ++l) {
-        auto f = [&](const BatchMap &m) { batch_l2l(jobs_dev, m, s); };
-        for (int i = 0; i < n; ++i)
-            if (plans[i]->geo.L >= l) Lc.add(i, l, plans[i]->lev[l].n, f);
-        go(f);
-    }
+    for (int l = 2; l <= maxL; ++l)
+        for (int pm : pms) {
+            auto f = [&](const BatchMap &m) {
+                if (pm == 0) batch_l2l(jobs_dev, m, s);
+                else batch_l2l_lanes(jobs_dev, m, pm, s);
+            };
+            for (int i = 0; i < n; ++i)
+                if (plans[i]->geo.L >= l && plans[i]->m2l_pm == pm) Lc.add(i, l, plans[i]->lev[l].n, f);
+            go(f);
+        }
     if (ev) hipEventRecord(ev[2], s);
 
     // L2P + P2P

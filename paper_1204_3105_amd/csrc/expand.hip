@@ -272,6 +272,169 @@ void batch_l2l(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
     hipLaunchKernelGGL(k_l2l, dim3(persistent_grid(m.pre[m.n], 64)), dim3(64), 0, s, jobs, m);
 }
 
+// ------------------------------------------------------------------ M2M / L2L, lane form
+// The same translations with one lane per (parent, child) pair (M2M) or per
+// child (L2L), coefficients in registers (orders padded to PM with zeros),
+// and the binomial sums done as Horner-style triangles with no division:
+//   M2M: x_k = a~_k rho^k; passes j = 1..PM-1 of x_k += w x_(k-1)
+//        (k = PM down to j+1) leave x_m = sum_k C(m-1, k-1) w^(m-k) x_k;
+//        then b~_m = x_m - a_0 w^m / m and b~_0 = a_0.
+//   L2L: passes j = 0..PM-1 of y_k += w y_(k+1) (k = PM-1 down to j) leave
+//        y_m = sum_(k>=m) C(k, m) w^(k-m) b~_k; then b~'_m += y_m rho^m.
+// The children of one parent occupy GS consecutive lanes (GS >= base) and
+// are summed by an xor butterfly, which leaves the same sum in every lane.
+template <int PM, int GS>
+__global__ __launch_bounds__(256) void k_m2m_lanes(const EvalJob *__restrict__ jobs, BatchMap bm)
+{
+    const int64_t total = bm.pre[bm.n] * GS;
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t item = t / GS;
+        const int d = (int)(t % GS);
+        const int e = batch_entry(bm, item);
+        const EvalJob &J = jobs[bm.job[e]];
+        const int l = bm.aux[e];
+        const int64_t gid = J.cell_off[l] + (item - bm.pre[e]);
+        const int p = J.p, P1 = p + 1;
+        double xr[PM + 1], xi[PM + 1];
+#pragma unroll
+        for (int k = 0; k <= PM; ++k) xr[k] = xi[k] = 0.0;
+        int32_t c = -1;
+        if ((J.occ[gid] & 1) && d < J.base) {
+            c = J.dense[J.dense_off[l + 1] + (int64_t)J.cell_key[gid] * J.base + d];
+            if (c >= 0 && !(J.occ[c] & 1)) c = -1;
+        }
+        if (c >= 0) {
+            const double inv = 1.0 / J.scale[l];
+            const double rho = J.scale[l + 1] * inv;
+            const double wr = (J.cx[c] - J.cx[gid]) * inv, wi = (J.cy[c] - J.cy[gid]) * inv;
+            const double *a = J.mp + (int64_t)c * 2 * P1;
+            double r = rho;
+#pragma unroll
+            for (int k = 1; k <= PM; ++k) {
+                if (k <= p) {
+                    xr[k] = a[2 * k] * r;
+                    xi[k] = a[2 * k + 1] * r;
+                }
+                r *= rho;
+            }
+#pragma unroll
+            for (int j = 1; j < PM; ++j)
+#pragma unroll
+                for (int k = PM; k > j; --k) {
+                    xr[k] += wr * xr[k - 1] - wi * xi[k - 1];
+                    xi[k] += wr * xi[k - 1] + wi * xr[k - 1];
+                }
+            const double a0 = a[0];
+            double pr = 1.0, pi = 0.0;
+#pragma unroll
+            for (int m = 1; m <= PM; ++m) {
+                const double nr = pr * wr - pi * wi, ni = pr * wi + pi * wr;
+                pr = nr;
+                pi = ni;
+                const double f = -a0 / (double)m;
+                xr[m] += f * pr;
+                xi[m] += f * pi;
+            }
+            xr[0] = a[0];
+            xi[0] = a[1];
+        }
+#pragma unroll
+        for (int o = 1; o < GS; o <<= 1)
+#pragma unroll
+            for (int k = 0; k <= PM; ++k) {
+                xr[k] += __shfl_xor(xr[k], o);
+                xi[k] += __shfl_xor(xi[k], o);
+            }
+        double *row = J.mp + gid * 2 * P1;
+#pragma unroll
+        for (int m = 0; m <= PM; ++m)
+            if (m <= p && m % GS == d) {
+                row[2 * m] = xr[m];
+                row[2 * m + 1] = xi[m];
+            }
+    }
+}
+
+template <int PM>
+__global__ __launch_bounds__(256) void k_l2l_lanes(const EvalJob *__restrict__ jobs, BatchMap bm)
+{
+    for (int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; item < bm.pre[bm.n];
+         item += (int64_t)gridDim.x * blockDim.x) {
+        const int e = batch_entry(bm, item);
+        const EvalJob &J = jobs[bm.job[e]];
+        const int l = bm.aux[e];
+        const int64_t gid = J.cell_off[l] + (item - bm.pre[e]);
+        if (!(J.occ[gid] & 2)) continue;
+        const int p = J.p, P1 = p + 1;
+        const int32_t par = J.parent[gid];
+        const double inv = 1.0 / J.scale[l - 1];
+        const double rho = J.scale[l] * inv;
+        const double wr = (J.cx[gid] - J.cx[par]) * inv, wi = (J.cy[gid] - J.cy[par]) * inv;
+        const double *b = J.lc + (int64_t)par * 2 * P1;
+        double yr[PM + 1], yi[PM + 1];
+#pragma unroll
+        for (int k = 0; k <= PM; ++k) {
+            yr[k] = k <= p ? b[2 * k] : 0.0;
+            yi[k] = k <= p ? b[2 * k + 1] : 0.0;
+        }
+#pragma unroll
+        for (int j = 0; j < PM; ++j)
+#pragma unroll
+            for (int k = PM - 1; k >= j; --k) {
+                yr[k] += wr * yr[k + 1] - wi * yi[k + 1];
+                yi[k] += wr * yi[k + 1] + wi * yr[k + 1];
+            }
+        double *row = J.lc + gid * 2 * P1;
+        double r = 1.0;
+#pragma unroll
+        for (int m = 0; m <= PM; ++m) {
+            if (m <= p) {
+                row[2 * m] += yr[m] * r;
+                row[2 * m + 1] += yi[m] * r;
+            }
+            r *= rho;
+        }
+    }
+}
+
+template <int PM>
+static void launch_m2m_lanes(const EvalJob *jobs, const BatchMap &m, int gs, hipStream_t s)
+{
+    const unsigned grid = persistent_grid((m.pre[m.n] * gs + 255) / 256, 16);
+    if (gs == 4) hipLaunchKernelGGL((k_m2m_lanes<PM, 4>), dim3(grid), dim3(256), 0, s, jobs, m);
+    else hipLaunchKernelGGL((k_m2m_lanes<PM, 8>), dim3(grid), dim3(256), 0, s, jobs, m);
+}
+
+void batch_m2m_lanes(const EvalJob *jobs, const BatchMap &m, int pm, int gs, hipStream_t s)
+{
+    if (m.n <= 0 || m.pre[m.n] <= 0) return;
+    switch (pm) {
+    case 8: launch_m2m_lanes<8>(jobs, m, gs, s); break;
+    case 16: launch_m2m_lanes<16>(jobs, m, gs, s); break;
+    case 24: launch_m2m_lanes<24>(jobs, m, gs, s); break;
+    case 32: launch_m2m_lanes<32>(jobs, m, gs, s); break;
+    case 40: launch_m2m_lanes<40>(jobs, m, gs, s); break;
+    case 48: launch_m2m_lanes<48>(jobs, m, gs, s); break;
+    default: break;
+    }
+}
+
+void batch_l2l_lanes(const EvalJob *jobs, const BatchMap &m, int pm, hipStream_t s)
+{
+    if (m.n <= 0 || m.pre[m.n] <= 0) return;
+    const dim3 grid(persistent_grid((m.pre[m.n] + 255) / 256, 16)), block(256);
+    switch (pm) {
+    case 8: hipLaunchKernelGGL((k_l2l_lanes<8>), grid, block, 0, s, jobs, m); break;
+    case 16: hipLaunchKernelGGL((k_l2l_lanes<16>), grid, block, 0, s, jobs, m); break;
+    case 24: hipLaunchKernelGGL((k_l2l_lanes<24>), grid, block, 0, s, jobs, m); break;
+    case 32: hipLaunchKernelGGL((k_l2l_lanes<32>), grid, block, 0, s, jobs, m); break;
+    case 40: hipLaunchKernelGGL((k_l2l_lanes<40>), grid, block, 0, s, jobs, m); break;
+    case 48: hipLaunchKernelGGL((k_l2l_lanes<48>), grid, block, 0, s, jobs, m); break;
+    default: break;
+    }
+}
+
 // ------------------------------------------------------------------ M2L
 // General-order fallback (any p): block per target cell at levels >= 1,
 // thread m.  For a source cell with delta = (c_S - c_T)/ell and

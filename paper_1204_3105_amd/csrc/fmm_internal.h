@@ -64,7 +64,8 @@ struct LevelInfo {
 };
 
 // Arena of device memory with a caching pool behind it.
-void *dev_alloc(size_t bytes, int *err);
+void *dev_alloc(size_t bytes, int *err, std::vector<uint64_t> *waited = nullptr,
+                hipStream_t stream = nullptr);
 void dev_free(void *p, size_t bytes);
 
 struct Plan {
@@ -111,7 +112,8 @@ struct Plan {
     int32_t *e4 = nullptr;         // [n_cells][e4_width]
     int32_t *near = nullptr;       // [n_leaf][near_width]
     int32_t *work_near = nullptr;  // near-field items: (leaf id, start)
-    int64_t n_work_near = 0;
+    int64_t n_work_near = 0;        // upper bound of near-field items
+    int32_t *counts = nullptr;      // device: [0] near items, [1] mixed M2L tiles
     int64_t n_m2l_pairs = 0, n_near_pairs = 0;
 
     // expansions
@@ -165,7 +167,9 @@ void launch_mark_cells(const GeoParams &g, const LevelInfo *lev, const uint32_t 
 void launch_flags_to_ids(int32_t *flags, int64_t n, hipStream_t s);
 void launch_compact(const GeoParams &g, const LevelInfo *lev, int64_t dense_total,
                     const int32_t *flags, const int32_t *ids, int32_t *dense, uint32_t *cell_key,
-                    uint8_t *occ, hipStream_t s);
+                    uint8_t *occ, int32_t *sb, int32_t *se, int32_t *tb, int32_t *te, hipStream_t s);
+void launch_gather_bounds(const LevelInfo *lev, int L, const int32_t *ids, const int32_t *total,
+                          const int32_t *bad, int32_t *out, hipStream_t s);
 void launch_cell_ranges(const GeoParams &g, const LevelInfo *lev, const uint32_t *key, int64_t n,
                         const int32_t *dense, int32_t *b, int32_t *e, hipStream_t s);
 void launch_cell_geometry(const GeoParams &g, const LevelInfo *lev, int64_t n_cells,
@@ -194,8 +198,8 @@ const double *device_binom(int *err);
 
 // m2l.hip
 int m2l_pm_for(int p);
-void m2l_tables(const Plan &P, int pm, std::vector<double> &pw, std::vector<double> &lg,
-                std::vector<double> &a0);
+size_t m2l_table_doubles(const Plan &P, int pm);
+void launch_m2l_tables(Plan &P, int pm, double *base, hipStream_t s);
 
 // m2l_mixed.hip
 size_t mixed_bytes(const Plan &P);

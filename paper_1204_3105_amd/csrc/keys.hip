@@ -65,7 +65,7 @@ __global__ void k_bbox(const double *__restrict__ pts, int64_t n, double *__rest
 
 __global__ void k_bbox_final(const double *__restrict__ partial, int nparts, double *__restrict__ out)
 {
-    // One block of 256 threads reduces up to 256 partial boxes.
+    // One block of 256 threads reduces the partial boxes.
     double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY, bad = 0.0;
     for (int k = threadIdx.x; k < nparts; k += blockDim.x) {
         mnx = fmin(mnx, partial[5 * k]);
@@ -99,17 +99,13 @@ __global__ void k_bbox_final(const double *__restrict__ partial, int nparts, dou
             sh[3][0] = fmax(sh[3][0], sh[3][k]);
             sh[4][0] += sh[4][k];
         }
-        // Accumulate into out[0..4] (callers run this once per point set).
-        out[0] = fmin(out[0], sh[0][0]);
-        out[1] = fmax(out[1], sh[1][0]);
-        out[2] = fmin(out[2], sh[2][0]);
-        out[3] = fmax(out[3], sh[3][0]);
-        out[4] += sh[4][0];
+        for (int k = 0; k < 5; ++k) out[k] = sh[k][0];
     }
 }
 
 void launch_bbox(const double *pts, int64_t n, double *partial, int nblocks, hipStream_t s)
 {
+    // n = 0 writes empty boxes, so the final reduction can always read them.
     hipLaunchKernelGGL(k_bbox, dim3(nblocks), dim3(256), 0, s, pts, n, partial);
 }
 

@@ -14,8 +14,6 @@
 // registers; the order is a compile-time bound PM >= p.
 #include <math.h>
 
-#include <vector>
-
 #include "eval.h"
 
 namespace fmm {
@@ -28,18 +26,23 @@ int m2l_pm_for(int p)
     return 0;
 }
 
+struct SlotTable {
+    int off[kMaxGroups][kMaxSlots][2];   // E4 offsets per group, lattice units
+    int count[kMaxGroups];
+};
+
 // Offset of slot s of group g on level l in Cartesian units, c_S - c_T.
-static void slot_offset(const Plan &P, int l, int g, int s, double &dx, double &dy)
+__device__ void slot_offset(const GeoParams &G, const SlotTable &T, int l, int g, int s, double scale,
+                            double &dx, double &dy)
 {
-    const GeoParams &G = P.geo;
-    int da = P.tables.e4[g][s][0], db = P.tables.e4[g][s][1];
+    const int da = T.off[g][s][0], db = T.off[g][s][1];
     if (G.tiling == kQuad) {
-        dx = da * P.scale[l];
-        dy = db * P.scale[l];
+        dx = da * scale;
+        dy = db * scale;
     } else if (G.tiling == kSept) {
         int64_t a = da, b = db;
         for (int k = 0; k < G.L - l; ++k) {   // times beta = 1 + 2w
-            int64_t na = a - 2 * b, nb = 2 * a + 3 * b;
+            const int64_t na = a - 2 * b, nb = 2 * a + 3 * b;
             a = na;
             b = nb;
         }
@@ -48,52 +51,87 @@ static void slot_offset(const Plan &P, int l, int g, int s, double &dx, double &
         dy = (r * G.s3 * (2.0 * (double)b + (double)a)) / 2.0;
     } else {
         const double r = G.size;
-        int64_t R = (int64_t)1 << (G.L - l);
+        const int64_t R = (int64_t)1 << (G.L - l);
         dx = (double)(da * R) * ((G.s3 * r) / 2.0);
         dy = (double)(db * R) * (r / 2.0);
     }
 }
 
-// Tables: pw[((l*G + g)*S + s)*(PM+1) + k] = (-1/delta)^k (complex, zero
-// beyond p), lg[(l*G + g)*S + s] = Log(c_T - c_S).
-void m2l_tables(const Plan &P, int pm, std::vector<double> &pw, std::vector<double> &lg,
-                std::vector<double> &a0)
+struct LevelScales {
+    double v[kMaxL + 1];
+};
+
+// Thread per (level, group, slot) entry idx = (l G + g) S + s:
+//   pw[idx (PM+1) + k] = (-1/delta)^k for k <= p (zero beyond p and for
+//   unused entries), lg[idx] = Log(c_T - c_S), and the monopole row
+//   a0[idx (PM+1) + k] = Log(c_T - c_S) for k = 0, -delta^-k / k =
+//   (-1)^(k+1) (-1/delta)^k / k otherwise.
+__global__ void k_m2l_tables(GeoParams geo, SlotTable T, LevelScales sc, int G, int S, int p, int pm,
+                             double *__restrict__ pw, double *__restrict__ lg,
+                             double *__restrict__ a0)
 {
-    const int L = P.geo.L, G = P.tables.n_groups, S = P.tables.e4_width;
-    pw.assign((size_t)(L + 1) * G * S * (pm + 1) * 2, 0.0);
-    lg.assign((size_t)(L + 1) * G * S * 2, 0.0);
-    a0.assign((size_t)(L + 1) * G * S * (pm + 1) * 2, 0.0);
-    for (int l = 1; l <= L; ++l)
-        for (int g = 0; g < G; ++g)
-            for (int s = 0; s < P.tables.e4_count[g]; ++s) {
-                double dx, dy;
-                slot_offset(P, l, g, s, dx, dy);
-                size_t idx = ((size_t)l * G + g) * S + s;
-                double lx = -dx, ly = -dy + 0.0;
-                lg[2 * idx] = log(hypot(lx, ly));
-                lg[2 * idx + 1] = atan2(ly, lx);
-                double ex = dx / P.scale[l], ey = dy / P.scale[l];
-                double d2 = ex * ex + ey * ey;
-                double qx = -ex / d2, qy = ey / d2;   // -1/delta
-                double cr = 1.0, ci = 0.0;
-                for (int k = 0; k <= P.p; ++k) {
-                    pw[2 * (idx * (pm + 1) + k)] = cr;
-                    pw[2 * (idx * (pm + 1) + k) + 1] = ci;
-                    // monopole coefficient of row k: Log(c_T - c_S) for k = 0,
-                    // -delta^-k / k = -(-1)^k (-1/delta)^k / k otherwise
-                    if (k == 0) {
-                        a0[2 * (idx * (pm + 1))] = lg[2 * idx];
-                        a0[2 * (idx * (pm + 1)) + 1] = lg[2 * idx + 1];
-                    } else {
-                        const double sg = (k & 1) ? 1.0 : -1.0;
-                        a0[2 * (idx * (pm + 1) + k)] = sg * cr / (double)k;
-                        a0[2 * (idx * (pm + 1) + k) + 1] = sg * ci / (double)k;
-                    }
-                    double nr = cr * qx - ci * qy, ni = cr * qy + ci * qx;
-                    cr = nr;
-                    ci = ni;
-                }
-            }
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (geo.L + 1) * G * S) return;
+    const int s = idx % S, g = (idx / S) % G, l = idx / (S * G);
+    double *pr = pw + 2 * (size_t)idx * (pm + 1), *ar = a0 + 2 * (size_t)idx * (pm + 1);
+    if (l < 1 || s >= T.count[g]) {
+        for (int k = 0; k <= pm; ++k) pr[2 * k] = pr[2 * k + 1] = ar[2 * k] = ar[2 * k + 1] = 0.0;
+        lg[2 * idx] = lg[2 * idx + 1] = 0.0;
+        return;
+    }
+    double dx, dy;
+    slot_offset(geo, T, l, g, s, sc.v[l], dx, dy);
+    const double lx = -dx, ly = -dy + 0.0;   // a -0 imaginary part counts as +0
+    const double lr = log(hypot(lx, ly)), li = atan2(ly, lx);
+    lg[2 * idx] = lr;
+    lg[2 * idx + 1] = li;
+    const double ex = dx / sc.v[l], ey = dy / sc.v[l];
+    const double d2 = ex * ex + ey * ey;
+    const double qx = -ex / d2, qy = ey / d2;   // -1/delta
+    double cr = 1.0, ci = 0.0;
+    for (int k = 0; k <= pm; ++k) {
+        const bool in = k <= p;
+        pr[2 * k] = in ? cr : 0.0;
+        pr[2 * k + 1] = in ? ci : 0.0;
+        if (k == 0) {
+            ar[0] = lr;
+            ar[1] = li;
+        } else {
+            const double sg = (k & 1) ? 1.0 : -1.0;
+            ar[2 * k] = in ? sg * cr / (double)k : 0.0;
+            ar[2 * k + 1] = in ? sg * ci / (double)k : 0.0;
+        }
+        const double nr = cr * qx - ci * qy, ni = cr * qy + ci * qx;
+        cr = nr;
+        ci = ni;
+    }
+}
+
+size_t m2l_table_doubles(const Plan &P, int pm)
+{
+    const size_t n = (size_t)(P.geo.L + 1) * P.tables.n_groups * P.tables.e4_width;
+    return n * (pm + 1) * 2 * 2 + n * 2;
+}
+
+void launch_m2l_tables(Plan &P, int pm, double *base, hipStream_t s)
+{
+    const int G = P.tables.n_groups, S = P.tables.e4_width;
+    const size_t n = (size_t)(P.geo.L + 1) * G * S;
+    P.m2l_pw = base;
+    P.m2l_lg = base + n * (pm + 1) * 2;
+    P.m2l_a0 = P.m2l_lg + n * 2;
+    SlotTable T;
+    for (int g = 0; g < kMaxGroups; ++g) {
+        T.count[g] = g < G ? P.tables.e4_count[g] : 0;
+        for (int k = 0; k < kMaxSlots; ++k) {
+            T.off[g][k][0] = P.tables.e4[g][k][0];
+            T.off[g][k][1] = P.tables.e4[g][k][1];
+        }
+    }
+    LevelScales sc;
+    for (int l = 0; l <= kMaxL; ++l) sc.v[l] = l <= P.geo.L ? P.scale[l] : 0.0;
+    hipLaunchKernelGGL(k_m2l_tables, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, P.geo, T, sc, G, S,
+                       P.p, pm, P.m2l_pw, P.m2l_lg, P.m2l_a0);
 }
 
 template <int PM>

@@ -55,8 +55,8 @@ static MixedLayout layout_of(const Plan &P)
     m.off_tab = o;
     o += (size_t)m.tab_levels * m.G * m.S * m.tab_elems * 2;
     o = (o + 255) & ~(size_t)255;
-    m.off_cnt = o;
-    o += 2 * 256 * sizeof(int32_t);
+    m.off_cnt = o;   // cell counts/offsets, cursors, tile offsets: 256 each
+    o += 3 * 256 * sizeof(int32_t);
     m.off_tiles = o;
     int64_t ncell = P.n_cells;
     o += (size_t)(ncell / kTileT + 2 * (kMaxL + 1) * kMaxGroups + 2) * 4 * sizeof(int32_t);
@@ -186,6 +186,56 @@ __global__ void k_group_scatter(int64_t first, int64_t n_cells, int L, int G, Ce
     if (key >= 0) list[off[key] + base[key] + rank] = (int32_t)gid;
 }
 
+// One block: turns the per-key cell counts into cell offsets (in place,
+// off[K] = total), tile offsets toff[0..K] (ceil(count / T) tiles per key)
+// and the tile total; clears the scatter cursors.
+__global__ __launch_bounds__(256) void k_tile_plan(int K, int32_t *__restrict__ cnt,
+                                                   int32_t *__restrict__ cursor,
+                                                   int32_t *__restrict__ toff,
+                                                   int32_t *__restrict__ n_tiles)
+{
+    __shared__ int32_t sc[256], st[256];
+    const int k = threadIdx.x;
+    const int32_t c = k < K ? cnt[k] : 0;
+    sc[k] = c;
+    st[k] = (c + kTileT - 1) / kTileT;
+    cursor[k] = 0;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {   // inclusive Hillis-Steele scans
+        const int32_t a = k >= d ? sc[k - d] : 0, b = k >= d ? st[k - d] : 0;
+        __syncthreads();
+        sc[k] += a;
+        st[k] += b;
+        __syncthreads();
+    }
+    if (k <= K) {
+        cnt[k] = k ? sc[k - 1] : 0;
+        toff[k] = k ? st[k - 1] : 0;
+    }
+    if (k == 0) *n_tiles = st[255];
+}
+
+// Thread per tile t < n_tiles: key = the k with toff[k] <= t < toff[k+1];
+// tile = {key, first list position, cell count (<= T), 0}.
+__global__ void k_tile_fill(int K, const int32_t *__restrict__ off, const int32_t *__restrict__ toff,
+                            const int32_t *__restrict__ n_tiles, int32_t *__restrict__ tiles)
+{
+    const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= *n_tiles) return;
+    int lo = 0, hi = K;   // toff[lo] <= t < toff[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (toff[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    const int32_t j = t - toff[lo];
+    const int32_t c = off[lo + 1] - off[lo];
+    tiles[4 * t] = lo;
+    tiles[4 * t + 1] = off[lo] + j * kTileT;
+    tiles[4 * t + 2] = min(kTileT, c - j * kTileT);
+    tiles[4 * t + 3] = 0;
+}
+
 int mixed_setup(Plan &P)
 {
     if (P.m2l_pm == 0 || P.geo.L < 1) return 0;
@@ -200,30 +250,18 @@ int mixed_setup(Plan &P)
     CellOffsets coff;
     for (int l = 0; l < kMaxL + 2; ++l) coff.v[l] = P.n_cells;
     for (int l = 0; l <= L; ++l) coff.v[l] = P.lev[l].cell_off;
-    hipMemsetAsync(cnt, 0, 2 * 256 * sizeof(int32_t), s);
+    int32_t *toff = cnt + 512;
+    hipMemsetAsync(cnt, 0, 256 * sizeof(int32_t), s);
     const int64_t first = P.lev[1].cell_off, n = P.n_cells - first;
+    const int K = L * G + G;   // keys l*G + g, l = 0..L (level 0 stays empty)
     if (n > 0)
         hipLaunchKernelGGL(k_group_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, first,
                            P.n_cells, L, G, coff, P.cell_occ, P.group, cnt);
-    std::vector<int32_t> hc(256, 0);
-    hipMemcpyAsync(hc.data(), cnt, 256 * sizeof(int32_t), hipMemcpyDeviceToHost, s);
-    hipStreamSynchronize(s);
-    std::vector<int32_t> off(256, 0), ht;
-    int32_t acc = 0;
-    for (int k = 0; k < (L + 1) * G; ++k) {
-        off[k] = acc;
-        for (int st = 0; st < hc[k]; st += kTileT) {
-            ht.push_back(k);
-            ht.push_back(acc + st);
-            ht.push_back(std::min(kTileT, hc[k] - st));
-            ht.push_back(0);
-        }
-        acc += hc[k];
-    }
-    P.mixed_tiles = (int)(ht.size() / 4);
-    hipMemcpy(cnt, off.data(), 256 * sizeof(int32_t), hipMemcpyHostToDevice);
-    hipMemsetAsync(cursor, 0, 256 * sizeof(int32_t), s);
-    if (!ht.empty()) hipMemcpy(tiles, ht.data(), ht.size() * sizeof(int32_t), hipMemcpyHostToDevice);
+    hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(256), 0, s, K, cnt, cursor, toff, P.counts + 1);
+    // sum_k ceil(c_k / T) <= (sum_k c_k) / T + (keys of levels >= 1)
+    P.mixed_tiles = (int)(n / kTileT + (int64_t)L * G + 1);
+    hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)((P.mixed_tiles + 255) / 256)), dim3(256), 0, s,
+                       K, cnt, toff, P.counts + 1, tiles);
     if (n > 0)
         hipLaunchKernelGGL(k_group_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, first,
                            P.n_cells, L, G, coff, P.cell_occ, P.group, cnt, cursor, list);
@@ -253,6 +291,7 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const EvalJob *__restrict__ 
     for (int64_t item = t_beg + lb; item < t_end; item += nb) {
         const int e = batch_entry(bm, item);
         const EvalJob &J = jobs[bm.job[e]];
+        if (item - bm.pre[e] >= J.counts[1]) continue;   // block-uniform
         const int32_t *tile = J.mix_tiles + 4 * (item - bm.pre[e]);
         const int key = tile[0], start = tile[1], count = tile[2];
         const int G = J.G, S = J.ew, p = J.p, pm = J.pm;

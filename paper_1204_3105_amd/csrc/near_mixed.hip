@@ -55,6 +55,7 @@ __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ j
         const EvalJob &J = jobs[bm.job[e]];
         double *phi = bm.phi_override ? bm.phi_override : J.phi;
         const int64_t it = item - bm.pre[e];
+        if (it >= J.counts[0]) continue;
         const int32_t li = J.work_near[2 * it], st = J.work_near[2 * it + 1];
         const int64_t gid = J.leaf_off + li;
         const int32_t t = st + lane;

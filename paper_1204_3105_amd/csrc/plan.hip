@@ -20,6 +20,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -41,24 +42,50 @@ static fmm_status fail(fmm_status st, const std::string &msg)
 
 // ------------------------------------------------------------ pool
 // Device memory is taken in 2 MiB granules and cached on release, keyed by
-// size, so repeated plans of similar size reuse their buffers.
+// size, so repeated plans of similar size reuse their buffers.  A plan that
+// runs on a caller's stream is released without waiting: its blocks carry a
+// fence (an event recorded behind the plan's last work), and whoever takes
+// such a block makes its stream wait for the fence (or the host, with no
+// stream) before touching it.
+struct Fence {
+    hipEvent_t ev = nullptr;
+    uint64_t id = 0;
+    ~Fence()
+    {
+        if (ev) hipEventDestroy(ev);
+    }
+};
 struct PoolBlock {
     void *p;
     size_t bytes;
     int device;
+    std::shared_ptr<Fence> fence;
 };
 static std::mutex g_pool_mu;
 static std::vector<PoolBlock> g_pool;
 static size_t g_pool_cached = 0;
+static uint64_t g_fence_id = 0;
 static const size_t kPoolCap = (size_t)16 << 30;
 
 static size_t round_granule(size_t b) { return (b + ((size_t)2 << 20) - 1) & ~(((size_t)2 << 20) - 1); }
 
-void *dev_alloc(size_t bytes, int *err)
+static void drop_pool_locked()
+{
+    for (auto &b : g_pool) {
+        if (b.fence) hipEventSynchronize(b.fence->ev);
+        hipFree(b.p);
+    }
+    g_pool.clear();
+    g_pool_cached = 0;
+}
+
+void *dev_alloc(size_t bytes, int *err, std::vector<uint64_t> *waited, hipStream_t stream)
 {
     bytes = round_granule(bytes ? bytes : 1);
     int dev = 0;
     hipGetDevice(&dev);
+    void *p = nullptr;
+    std::shared_ptr<Fence> fence;
     {
         std::lock_guard<std::mutex> lk(g_pool_mu);
         int best = -1;
@@ -69,21 +96,36 @@ void *dev_alloc(size_t bytes, int *err)
                 best = i;
         }
         if (best >= 0) {
-            void *p = g_pool[best].p;
+            p = g_pool[best].p;
+            fence = std::move(g_pool[best].fence);
             g_pool_cached -= g_pool[best].bytes;
             g_pool.erase(g_pool.begin() + best);
-            return p;
         }
     }
-    void *p = nullptr;
+    if (p) {
+        if (fence) {
+            // With `waited`, the block is used in the order of `stream`
+            // (which may be the null stream); without, by the host.
+            bool done = false;
+            if (waited)
+                for (uint64_t id : *waited) done = done || id == fence->id;
+            if (!done) {
+                if (waited) {
+                    hipStreamWaitEvent(stream, fence->ev, 0);
+                    waited->push_back(fence->id);
+                } else {
+                    hipEventSynchronize(fence->ev);
+                }
+            }
+        }
+        return p;
+    }
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
         // release the cache and retry once
         {
             std::lock_guard<std::mutex> lk(g_pool_mu);
-            for (auto &b : g_pool) hipFree(b.p);
-            g_pool.clear();
-            g_pool_cached = 0;
+            drop_pool_locked();
         }
         (void)hipGetLastError();
         e = hipMalloc(&p, bytes);
@@ -96,7 +138,7 @@ void *dev_alloc(size_t bytes, int *err)
     return p;
 }
 
-void dev_free(void *p, size_t bytes)
+static void pool_put(void *p, size_t bytes, std::shared_ptr<Fence> fence)
 {
     if (!p) return;
     bytes = round_granule(bytes ? bytes : 1);
@@ -104,16 +146,76 @@ void dev_free(void *p, size_t bytes)
     hipGetDevice(&dev);
     std::lock_guard<std::mutex> lk(g_pool_mu);
     if (g_pool_cached + bytes > kPoolCap) {
+        if (fence) hipEventSynchronize(fence->ev);
         hipFree(p);
         return;
     }
-    g_pool.push_back({p, bytes, dev});
+    g_pool.push_back({p, bytes, dev, std::move(fence)});
     g_pool_cached += bytes;
+}
+
+void dev_free(void *p, size_t bytes) { pool_put(p, bytes, nullptr); }
+
+// ------------------------------------------------------------ uploads
+// Host tables go to the device through a pinned ring so the copies stay on
+// the plan's stream; a region is reused once the copy that read it is done.
+namespace {
+struct Staging {
+    std::mutex mu;
+    char *buf = nullptr;
+    size_t cap = 0, head = 0;
+    struct Use {
+        size_t off, bytes;
+        hipEvent_t ev;
+    };
+    std::vector<Use> busy;
+};
+Staging g_stage;
+constexpr size_t kStageCap = (size_t)32 << 20;
+}  // namespace
+
+static hipError_t upload(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    if (bytes == 0) return hipSuccess;
+    std::lock_guard<std::mutex> lk(g_stage.mu);
+    if (!g_stage.buf && hipHostMalloc((void **)&g_stage.buf, kStageCap, hipHostMallocDefault) == hipSuccess)
+        g_stage.cap = kStageCap;
+    if (!g_stage.buf || bytes > g_stage.cap) {
+        // No ring: order the synchronous copy behind the stream's work.
+        (void)hipGetLastError();
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+    }
+    const size_t sz = (bytes + 255) & ~(size_t)255;
+    if (g_stage.head + sz > g_stage.cap) g_stage.head = 0;
+    const size_t off = g_stage.head;
+    for (size_t i = 0; i < g_stage.busy.size();) {
+        const Staging::Use &u = g_stage.busy[i];
+        if (u.off < off + sz && off < u.off + u.bytes) {
+            hipEventSynchronize(u.ev);
+            hipEventDestroy(u.ev);
+            g_stage.busy.erase(g_stage.busy.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+    memcpy(g_stage.buf + off, src, bytes);
+    hipError_t e = hipMemcpyAsync(dst, g_stage.buf + off, bytes, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    hipEvent_t ev;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+    hipEventRecord(ev, s);
+    g_stage.busy.push_back({off, sz, ev});
+    g_stage.head = off + sz;
+    return hipSuccess;
 }
 
 // ------------------------------------------------------------ plan storage
 struct PlanImpl : Plan {
     std::vector<std::pair<void *, size_t>> allocs;
+    std::vector<uint64_t> waited;   // fences this plan's stream already waits for
     int64_t device_bytes = 0;
     int64_t n_items_cap = 0;
     void *scratch = nullptr;
@@ -124,7 +226,7 @@ template <typename T>
 static T *take(PlanImpl *P, int64_t count, int *err)
 {
     size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
-    void *p = dev_alloc(bytes, err);
+    void *p = dev_alloc(bytes, err, &P->waited, P->stream);
     if (p) {
         P->allocs.push_back({p, bytes});
         P->device_bytes += (int64_t)round_granule(bytes);
@@ -134,8 +236,20 @@ static T *take(PlanImpl *P, int64_t count, int *err)
 
 static void release(PlanImpl *P)
 {
-    if (P->stream) hipStreamSynchronize(P->stream);
-    for (auto &a : P->allocs) dev_free(a.first, a.second);
+    std::shared_ptr<Fence> fence;
+    if (!P->own_stream && !P->allocs.empty()) {
+        fence = std::make_shared<Fence>();
+        if (hipEventCreateWithFlags(&fence->ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(fence->ev, P->stream) != hipSuccess) {
+            (void)hipGetLastError();
+            fence.reset();
+        } else {
+            std::lock_guard<std::mutex> lk(g_pool_mu);
+            fence->id = ++g_fence_id;
+        }
+    }
+    if (!fence) hipStreamSynchronize(P->stream);
+    for (auto &a : P->allocs) pool_put(a.first, a.second, fence);
     P->allocs.clear();
     for (auto &e : P->ev)
         if (e) hipEventDestroy(e);
@@ -273,16 +387,10 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     double *bbp = take<double>(P, 5 * 2 * nbb + 8, &err);
     if (err) return fail(FMM_E_NOMEM, "device allocation failed (bbox)");
     double *bbo = bbp + 10 * nbb;
-    double init[5] = {INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0};
-    FMM_HIP_CHECK(hipMemcpyAsync(bbo, init, sizeof(init), hipMemcpyHostToDevice, s));
-    if (n_src) {
-        launch_bbox(dsrc, n_src, bbp, nbb, s);
-        launch_bbox_final(bbp, nbb, bbo, s);
-    }
-    if (n_tgt && !same) {
-        launch_bbox(dtgt, n_tgt, bbp + 5 * nbb, nbb, s);
-        launch_bbox_final(bbp + 5 * nbb, nbb, bbo, s);
-    }
+    // The source and target partial boxes are reduced together.
+    launch_bbox(dsrc, n_src, bbp, nbb, s);
+    launch_bbox(dtgt, same ? 0 : n_tgt, bbp + 5 * nbb, nbb, s);
+    launch_bbox_final(bbp, 2 * nbb, bbo, s);
     double hb[5];
     FMM_HIP_CHECK(hipMemcpyAsync(hb, bbo, sizeof(hb), hipMemcpyDeviceToHost, s));
     FMM_HIP_CHECK(hipStreamSynchronize(s));
@@ -326,11 +434,11 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
         P->tx = take<double>(P, M, &err);
         P->ty = take<double>(P, M, &err);
     }
-    int32_t *bad = take<int32_t>(P, 8, &err);
+    int32_t *bad = take<int32_t>(P, 4 + kMaxL + 4, &err);
     size_t rtmp = std::max(radix_tmp_bytes(N), radix_tmp_bytes(M));
     char *sort_tmp = take<char>(P, (int64_t)rtmp, &err);
     if (err) return fail(FMM_E_NOMEM, "device allocation failed (keys)");
-    FMM_HIP_CHECK(hipMemsetAsync(bad, 0, 8 * sizeof(int32_t), s));
+    FMM_HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
     launch_keys(g, dsrc, N, P->skey, P->sperm, bad, s);
     if (!same) launch_keys(g, dtgt, M, P->tkey, P->tperm, bad, s);
     int bits = key_bits(g);
@@ -360,15 +468,13 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     launch_flags_to_ids(flags, dense_total, s);
     int32_t *ids = flags + dense_total;
     scan_exclusive(ids, ids, dense_total, total, scan_tmp, s);
-    // Level boundaries -> host.
-    std::vector<int32_t> bnd(g.L + 2);
-    for (int l = 0; l <= g.L; ++l)
-        FMM_HIP_CHECK(hipMemcpyAsync(&bnd[l], ids + P->lev[l].dense_off, sizeof(int32_t),
-                                     hipMemcpyDeviceToHost, s));
-    FMM_HIP_CHECK(hipMemcpyAsync(&bnd[g.L + 1], total, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    int32_t hbad = 0;
-    FMM_HIP_CHECK(hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    // Level boundaries and the out-of-domain count -> host, in one copy.
+    std::vector<int32_t> bnd(g.L + 3);
+    launch_gather_bounds(P->lev, g.L, ids, total, bad, bad + 4, s);
+    FMM_HIP_CHECK(hipMemcpyAsync(bnd.data(), bad + 4, sizeof(int32_t) * (g.L + 3),
+                                 hipMemcpyDeviceToHost, s));
     FMM_HIP_CHECK(hipStreamSynchronize(s));
+    const int32_t hbad = bnd[g.L + 2];
     if (hbad) return fail(FMM_E_DOMAIN, "points outside the root of the given geometry");
     for (int l = 0; l <= g.L; ++l) {
         P->lev[l].cell_off = bnd[l];
@@ -405,16 +511,11 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     int32_t *ncount = take<int32_t>(P, NL + 1, &err);
     int64_t items_cap = (M + kChunk - 1) / kChunk + NL + 1;
     P->work_near = take<int32_t>(P, 2 * items_cap, &err);
-    unsigned long long *pairs = take<unsigned long long>(P, 2, &err);
+    P->counts = take<int32_t>(P, 8, &err);
     if (err) return fail(FMM_E_NOMEM, "device allocation failed (cells)");
 
-    launch_compact(g, P->lev, dense_total, flags, ids, P->dense, P->cell_key, P->cell_occ, s);
-    FMM_HIP_CHECK(hipMemsetAsync(P->sb, 0, sizeof(int32_t) * C, s));
-    FMM_HIP_CHECK(hipMemsetAsync(P->se, 0, sizeof(int32_t) * C, s));
-    if (!same) {
-        FMM_HIP_CHECK(hipMemsetAsync(P->tb, 0, sizeof(int32_t) * C, s));
-        FMM_HIP_CHECK(hipMemsetAsync(P->te, 0, sizeof(int32_t) * C, s));
-    }
+    launch_compact(g, P->lev, dense_total, flags, ids, P->dense, P->cell_key, P->cell_occ, P->sb,
+                   P->se, same ? nullptr : P->tb, same ? nullptr : P->te, s);
     launch_cell_ranges(g, P->lev, P->skey, N, P->dense, P->sb, P->se, s);
     if (!same) launch_cell_ranges(g, P->lev, P->tkey, M, P->dense, P->tb, P->te, s);
     launch_cell_geometry(g, P->lev, P->n_cells, P->cell_key, P->dense, P->sb, P->se, P->tb, P->te,
@@ -422,25 +523,15 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     launch_lists(g, P->lev, P->tables, P->n_cells, P->cell_key, P->group, P->cell_occ, P->dense,
                  P->e4, P->near, s);
     launch_near_items(P->lev, g.L, P->tb, P->te, ncount, s);
-    scan_exclusive(ncount, ncount, P->lev[g.L].n, total, scan_tmp, s);
+    scan_exclusive(ncount, ncount, P->lev[g.L].n, P->counts + 0, scan_tmp, s);
     launch_near_items_fill(P->lev, g.L, P->tb, P->te, ncount, P->work_near, s);
-    FMM_HIP_CHECK(hipMemsetAsync(pairs, 0, 2 * sizeof(unsigned long long), s));
-    launch_count_pairs(P->lev, g.L, ew, nw, P->e4, P->near, P->cell_occ, P->sb, P->se, P->tb,
-                       P->te, pairs, s);
-    FMM_HIP_CHECK(hipMemsetAsync(P->lc, 0, sizeof(double) * 2 * (P->p + 1) * C, s));
+    // Only a one-level tree reads a local expansion that no M2L writes.
+    FMM_HIP_CHECK(hipMemsetAsync(P->lc, 0, sizeof(double) * 2 * (P->p + 1), s));
     P->m2l_pm = m2l_pm_for(P->p);
     if (P->m2l_pm > 0 && g.L >= 1) {
-        std::vector<double> pw, lg, a0;
-        m2l_tables(*P, P->m2l_pm, pw, lg, a0);
-        std::vector<double> all(pw.size() + lg.size() + a0.size());
-        std::copy(pw.begin(), pw.end(), all.begin());
-        std::copy(lg.begin(), lg.end(), all.begin() + pw.size());
-        std::copy(a0.begin(), a0.end(), all.begin() + pw.size() + lg.size());
-        P->m2l_pw = take<double>(P, (int64_t)all.size(), &err);
+        double *tab = take<double>(P, (int64_t)m2l_table_doubles(*P, P->m2l_pm), &err);
         if (err) return fail(FMM_E_NOMEM, "device allocation failed (M2L tables)");
-        P->m2l_lg = P->m2l_pw + pw.size();
-        P->m2l_a0 = P->m2l_lg + lg.size();
-        FMM_HIP_CHECK(hipMemcpy(P->m2l_pw, all.data(), all.size() * sizeof(double), hipMemcpyHostToDevice));
+        launch_m2l_tables(*P, P->m2l_pm, tab, s);
     }
     if (P->precision == FMM_PREC_MIXED) {
         P->sxl = take<float>(P, N, &err);
@@ -464,26 +555,22 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
         if (err) return fail(FMM_E_NOMEM, "device allocation failed (mixed M2L)");
         if (mixed_setup(*P)) return fail(FMM_E_DEVICE, "mixed-precision setup failed");
     }
-    int32_t hitems = 0;
-    unsigned long long hp[2] = {0, 0};
-    FMM_HIP_CHECK(hipMemcpyAsync(&hitems, total, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    FMM_HIP_CHECK(hipMemcpyAsync(hp, pairs, sizeof(hp), hipMemcpyDeviceToHost, s));
     FMM_HIP_CHECK(hipEventRecord(P->ev[1], s));
-    FMM_HIP_CHECK(hipStreamSynchronize(s));
-    P->n_work_near = P->lev[g.L].n > 0 ? hitems : 0;
-    P->n_m2l_pairs = (int64_t)hp[0];
-    P->n_near_pairs = (int64_t)hp[1];
-    P->plan_ms = elapsed(P->ev[0], P->ev[1]);
+    // Item counts stay on the device; launches use these upper bounds and
+    // kernels stop at the counts.
+    P->n_work_near = P->lev[g.L].n > 0 && M > 0 ? items_cap : 0;
+    P->n_m2l_pairs = P->n_near_pairs = -1;   // counted on first request
     if (!o.device_pointers) {
         P->io_u = take<double>(P, std::max<int64_t>(N, 1), &err);
         P->io_phi = take<double>(P, 2 * std::max<int64_t>(M, 1), &err);
         if (err) return fail(FMM_E_NOMEM, "device allocation failed (io)");
     }
     P->phi_int = take<double>(P, 2 * std::max<int64_t>(M, 1), &err);
+    if (P->lev[g.L].n == 0 || M == 0) FMM_HIP_CHECK(hipMemsetAsync(P->counts, 0, sizeof(int32_t), s));
     P->job_dev = take<EvalJob>(P, 1, &err);
     if (err) return fail(FMM_E_NOMEM, "device allocation failed (descriptor)");
     EvalJob J = make_job(*P);
-    FMM_HIP_CHECK(hipMemcpy(P->job_dev, &J, sizeof(J), hipMemcpyHostToDevice));
+    FMM_HIP_CHECK(upload(P->job_dev, &J, sizeof(J), s));
     return FMM_OK;
 }
 
@@ -539,8 +626,8 @@ fmm_status fmm_plan(fmm_tiling tiling, const double *src, int64_t n_src, const d
     if (prec == FMM_PREC_AUTO) prec = eps >= 1e-6 ? FMM_PREC_MIXED : FMM_PREC_FP64;
     P->precision = prec;
     hipGetDevice(&P->device);
-    if (o.device_pointers && o.stream) {
-        P->stream = (hipStream_t)o.stream;
+    if (o.device_pointers) {
+        P->stream = (hipStream_t)o.stream;   // NULL: the null stream
     } else {
         if (hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) != hipSuccess) {
             delete P;
@@ -620,6 +707,22 @@ fmm_status fmm_plan_info_get(fmm_plan_t plan, fmm_plan_info *info)
     info->targets_are_sources = P->same;
     info->e4_width = P->tables.e4_width;
     for (int l = 0; l <= P->geo.L && l < 32; ++l) info->n_cells[l] = P->lev[l].n;
+    if (P->n_m2l_pairs < 0) {
+        int err = 0;
+        unsigned long long *pairs = (unsigned long long *)dev_alloc(16, &err);
+        unsigned long long hp[2] = {0, 0};
+        if (!err) {
+            hipMemsetAsync(pairs, 0, 16, P->stream);
+            launch_count_pairs(P->lev, P->geo.L, P->tables.e4_width, P->tables.near_width, P->e4,
+                               P->near, P->cell_occ, P->sb, P->se, P->tb, P->te, pairs, P->stream);
+            hipMemcpyAsync(hp, pairs, 16, hipMemcpyDeviceToHost, P->stream);
+            hipStreamSynchronize(P->stream);
+            dev_free(pairs, 16);
+        }
+        P->n_m2l_pairs = (int64_t)hp[0];
+        P->n_near_pairs = (int64_t)hp[1];
+    }
+    if (P->plan_ms == 0 && hipEventSynchronize(P->ev[1]) == hipSuccess) P->plan_ms = elapsed(P->ev[0], P->ev[1]);
     info->n_m2l_pairs = P->n_m2l_pairs;
     info->n_near_pairs = P->n_near_pairs;
     info->device_bytes = P->device_bytes;

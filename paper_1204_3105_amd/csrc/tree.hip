@@ -108,7 +108,8 @@ __device__ __forceinline__ int level_of_cell(const Levels &s, int64_t gid)
 
 __global__ void k_compact(Levels s, const int32_t *__restrict__ flags, const int32_t *__restrict__ ids,
                           int64_t n, int32_t *__restrict__ dense, uint32_t *__restrict__ cell_key,
-                          uint8_t *__restrict__ occ)
+                          uint8_t *__restrict__ occ, int32_t *__restrict__ sb, int32_t *__restrict__ se,
+                          int32_t *__restrict__ tb, int32_t *__restrict__ te)
 {
     int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (j >= n) return;
@@ -122,14 +123,40 @@ __global__ void k_compact(Levels s, const int32_t *__restrict__ flags, const int
     dense[j] = gid;
     cell_key[gid] = (uint32_t)(j - s.l[l].dense_off);
     occ[gid] = (uint8_t)f;
+    sb[gid] = se[gid] = 0;   // ranges of absent kinds stay empty
+    if (tb) tb[gid] = te[gid] = 0;
 }
 
 void launch_compact(const GeoParams &g, const LevelInfo *lev, int64_t dense_total,
                     const int32_t *flags, const int32_t *ids, int32_t *dense, uint32_t *cell_key,
-                    uint8_t *occ, hipStream_t s)
+                    uint8_t *occ, int32_t *sb, int32_t *se, int32_t *tb, int32_t *te, hipStream_t s)
 {
     hipLaunchKernelGGL(k_compact, dim3((unsigned)((dense_total + 255) / 256)), dim3(256), 0, s,
-                       make_levels(g, lev), flags, ids, dense_total, dense, cell_key, occ);
+                       make_levels(g, lev), flags, ids, dense_total, dense, cell_key, occ, sb, se,
+                       tb, te);
+}
+
+// out[l] = first cell id of level l (l = 0..L), out[L+1] = cell count,
+// out[L+2] = points outside the root.
+__global__ void k_gather_bounds(Levels s, const int32_t *__restrict__ ids,
+                                const int32_t *__restrict__ total, const int32_t *__restrict__ bad,
+                                int32_t *__restrict__ out)
+{
+    const int l = threadIdx.x;
+    if (l <= s.L) out[l] = ids[s.l[l].dense_off];
+    if (l == 0) {
+        out[s.L + 1] = *total;
+        out[s.L + 2] = *bad;
+    }
+}
+
+void launch_gather_bounds(const LevelInfo *lev, int L, const int32_t *ids, const int32_t *total,
+                          const int32_t *bad, int32_t *out, hipStream_t s)
+{
+    Levels lv;
+    lv.L = L;
+    for (int l = 0; l <= L; ++l) lv.l[l] = lev[l];
+    hipLaunchKernelGGL(k_gather_bounds, dim3(1), dim3(64), 0, s, lv, ids, total, bad, out);
 }
 
 __global__ void k_ranges(int tiling, Levels s, const uint32_t *__restrict__ key, int64_t n,
@@ -179,43 +206,50 @@ __device__ __forceinline__ uint32_t quad_join(int64_t ix, int64_t iy, int l)
     return k;
 }
 
-// Eisenstein value of a level-l septree key in level-l units (Horner in beta).
+// Eisenstein value a + b w of a level-l septree key in level-l units:
+// sum_i digit_i beta^i, least significant digit first (|a|, |b| < 2^16 for
+// the 11 levels a 32-bit key holds).
 __device__ __forceinline__ void sept_value(uint32_t key, int l, int64_t &a, int64_t &b)
 {
     const int da[7] = {0, 1, 0, -1, -1, 0, 1};
     const int db[7] = {0, 0, 1, 1, 0, -1, -1};
-    uint32_t pw = 1;
-    for (int i = 1; i < l; ++i) pw *= 7u;
-    int64_t va = 0, vb = 0;
+    int32_t va = 0, vb = 0, qa = 1, qb = 0;   // q = beta^i
     for (int i = 0; i < l; ++i) {
-        int d = (int)((key / pw) % 7u);
-        // v <- v * beta + digit, beta (a + b w) = (a - 2b) + (2a + 3b) w
-        int64_t na = va - 2 * vb, nb = 2 * va + 3 * vb;
-        va = na + da[d];
-        vb = nb + db[d];
-        pw /= 7u;
+        const int d = (int)(key % 7u);
+        key /= 7u;
+        // v += q * digit; (qa + qb w)(x + y w) = (qa x - qb y) + (qa y + qb x + qb y) w
+        va += qa * da[d] - qb * db[d];
+        vb += qa * db[d] + qb * da[d] + qb * db[d];
+        // q *= beta, beta (a + b w) = (a - 2b) + (2a + 3b) w
+        const int32_t na = qa - 2 * qb, nb = 2 * qa + 3 * qb;
+        qa = na;
+        qb = nb;
     }
     a = va;
     b = vb;
 }
 
-__device__ __forceinline__ int64_t sept_encode(int64_t a, int64_t b, int ndig)
+// GBT digits of a + b w (level-l units, ndig digits), -1 if it needs more.
+// After the digit is removed, (a + b w)(3 - 2w) is divisible by 7 = beta
+// conj(beta); the exact quotient is the product with 7^-1 mod 2^32.
+__device__ __forceinline__ int64_t sept_encode(int32_t a, int32_t b, int ndig)
 {
     const int rdig[7] = {0, 1, 3, 2, 5, 6, 4};
     const int da[7] = {0, 1, 0, -1, -1, 0, 1};
     const int db[7] = {0, 0, 1, 1, 0, -1, -1};
-    int64_t key = 0, pw = 1;
+    constexpr uint32_t kInv7 = 0xB6DB6DB7u;
+    uint32_t key = 0, pw = 1;
     for (int i = 0; i < ndig; ++i) {
-        int64_t r = (a + 3 * b) % 7;
+        int32_t r = (a + 3 * b) % 7;
         if (r < 0) r += 7;
-        int d = rdig[r];
+        const int d = rdig[r];
         a -= da[d];
         b -= db[d];
-        int64_t na = 3 * a + 2 * b, nb = b - 2 * a;
-        a = na / 7;
-        b = nb / 7;
-        key += d * pw;
-        pw *= 7;
+        const uint32_t na = (uint32_t)(3 * a + 2 * b), nb = (uint32_t)(b - 2 * a);
+        a = (int32_t)(na * kInv7);
+        b = (int32_t)(nb * kInv7);
+        key += (uint32_t)d * pw;
+        pw *= 7u;
     }
     if (a != 0 || b != 0) return -1;
     return key;
@@ -246,31 +280,39 @@ __device__ __forceinline__ void tri_units(uint32_t key, int l, int L, int64_t &U
     o = up;
 }
 
-// Key of the level-l triangle whose centroid is (U, V); -1 if outside the root.
-__device__ __forceinline__ int64_t tri_encode(int64_t U, int64_t V, int l, int L)
+// Key of the level-l triangle whose centroid is (U, V); -1 if outside the
+// root.  Descent by the lines that split a triangle into its children: with
+// du = U - c_u, dv = o (V - c_v) and R the child offset unit, the apex child
+// (type 1) holds dv > R, the two base corners (types 2, 3) hold
+// 3 du + dv < -2R and -3 du + dv < -2R, and the inverted centre (type 0) the
+// rest.  Centroids of finer cells never lie on these lines.
+__device__ __forceinline__ int64_t tri_encode(int32_t U, int32_t V, int l, int L)
 {
-    int64_t lim = (int64_t)1 << (L + 1);
-    if (!(V > -((int64_t)1 << L) && 3 * U + V < lim && -3 * U + V < lim)) return -1;
-    int64_t cu = 0, cv = 0, key = 0;
+    const int32_t lim = 1 << (L + 1);
+    if (!(V > -(1 << L) && 3 * U + V < lim && -3 * U + V < lim)) return -1;
+    int32_t cu = 0, cv = 0;
+    uint32_t key = 0;
     int up = 1;
     for (int i = 1; i <= l; ++i) {
-        int64_t R = (int64_t)1 << (L - i);
-        int64_t pu[4] = {cu, cu, cu - R, cu + R};
-        int64_t pv[4] = {cv, cv + 2 * up * R, cv - up * R, cv - up * R};
-        int best = 0;
-        int64_t bd = INT64_MAX;
-        for (int t = 0; t < 4; ++t) {
-            int64_t du = U - pu[t], dv = V - pv[t];
-            int64_t d = 3 * du * du + dv * dv;
-            if (d < bd) {
-                bd = d;
-                best = t;
-            }
+        const int32_t R = 1 << (L - i);
+        const int32_t du = U - cu, dv = up * (V - cv);
+        uint32_t t;
+        if (dv > R) {
+            t = 1;
+            cv += 2 * up * R;
+        } else if (3 * du + dv < -2 * R) {
+            t = 2;
+            cu -= R;
+            cv -= up * R;
+        } else if (-3 * du + dv < -2 * R) {
+            t = 3;
+            cu += R;
+            cv -= up * R;
+        } else {
+            t = 0;
+            up = -up;
         }
-        cu = pu[best];
-        cv = pv[best];
-        if (best == 0) up = -up;
-        key = key * 4 + best;
+        key = key * 4u + t;
     }
     if (cu != U || cv != V) return -1;
     return key;
@@ -360,18 +402,18 @@ struct DevTables {
 // cell at (pa, pb) on level l; -1 if none.
 __device__ __forceinline__ int32_t lookup(const GeoParams &g, const Levels &s,
                                           const int32_t *__restrict__ dense,
-                                          const uint8_t *__restrict__ occ, int l, int64_t pa,
-                                          int64_t pb, int da, int db)
+                                          const uint8_t *__restrict__ occ, int l, int32_t pa,
+                                          int32_t pb, int da, int db)
 {
     int64_t key;
     if (g.tiling == kQuad) {
-        int64_t x = pa + da, y = pb + db, n = (int64_t)1 << l;
+        const int32_t x = pa + da, y = pb + db, n = 1 << l;
         if (x < 0 || y < 0 || x >= n || y >= n) return -1;
         key = quad_join(x, y, l);
     } else if (g.tiling == kSept) {
         key = sept_encode(pa + da, pb + db, l);
     } else {
-        int64_t R = (int64_t)1 << (g.L - l);
+        const int32_t R = 1 << (g.L - l);
         key = tri_encode(pa + da * R, pb + db * R, l, g.L);
     }
     if (key < 0) return -1;
@@ -390,15 +432,16 @@ __global__ void k_lists(GeoParams g, Levels s, DevTables t, int64_t n_cells,
     int l = level_of_cell(s, gid);
     bool tgt = occ[gid] & 2;
     uint32_t key = cell_key[gid];
-    int64_t pa, pb;
+    int64_t qa, qb;
     int orient = 1;
     if (g.tiling == kQuad) {
-        quad_split(key, l, pa, pb);
+        quad_split(key, l, qa, qb);
     } else if (g.tiling == kSept) {
-        sept_value(key, l, pa, pb);
+        sept_value(key, l, qa, qb);
     } else {
-        tri_units(key, l, g.L, pa, pb, orient);
+        tri_units(key, l, g.L, qa, qb, orient);
     }
+    const int32_t pa = (int32_t)qa, pb = (int32_t)qb;
     int32_t *row = e4 + gid * (int64_t)t.e4_width;
     int grp = group[gid];
     int cnt = (l >= 1 && tgt) ? t.e4_count[grp] : 0;
