@@ -109,8 +109,9 @@ typedef struct {
     int64_t device_bytes;    /* device memory held by the plan                */
     double plan_ms;          /* GPU time of the last fmm_plan                 */
     double eval_ms;          /* GPU time of the last fmm_eval                 */
-    double stage_ms[8];      /* last eval: upward, M2L, downward, near+L2P,
-                                (rest reserved)                               */
+    double stage_ms[8];      /* last eval: [0] upward pass, [1] M2L, [2] L2L,
+                                [3] P2P near field (runs beside 0..2),
+                                [4] wait for P2P + L2P; rest reserved          */
 } fmm_plan_info;
 
 /* Fill *opt with defaults: leaf_size 64, lmax -1, p -1, AUTO precision,

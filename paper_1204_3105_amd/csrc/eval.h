@@ -67,6 +67,10 @@ __device__ __forceinline__ int level_of(const EvalJob &J, int64_t gid)
     return l;
 }
 
+// The near field runs beside the far-field passes as a persistent grid of
+// one-wave blocks (up to 32 per SIMD, so effectively one per work item).
+constexpr int kNearWavesPerCU = 128;
+
 // Persistent-grid size for a phase with `items` work items.
 inline unsigned persistent_grid(int64_t items, int per_cu)
 {
@@ -88,6 +92,7 @@ void batch_m2l_mixed(const EvalJob *jobs, const BatchMap &m, int MT, int KB, hip
 bool mixed_shape_supported(int MT, int KB);
 void batch_split_mp(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_near_fp64(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
+void batch_l2p(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_near_mixed(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 
 // Host view of one plan for batching: its descriptor (host copy) and the
@@ -98,7 +103,11 @@ EvalJob make_job(const Plan &P);
 // holds the descriptors in device memory (jobs_dev[i] describes plans[i]).
 // phi_single, when not null and the batch has one plan, receives the output
 // instead of the plan's own buffer.
+// Evaluates a batch of plans on stream s.  ev[0..3]: ends of the upward
+// pass, M2L, L2L and the whole evaluation (recorded on s); ev[4]: fork to
+// the side stream, ev[5..6]: start and end of the P2P near field there.
+hipStream_t side_stream();   // per-device stream for the near field
 void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_single, hipStream_t s,
-               hipEvent_t *stage_events);
+               hipStream_t side, hipEvent_t *ev);
 
 }  // namespace fmm

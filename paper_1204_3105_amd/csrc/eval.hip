@@ -2,8 +2,10 @@
 //
 // Phase order (Greengard-Rokhlin sweep; paper Sec. 2 cites it):
 //   P2M at the leaves, M2M from level L-1 up to 1, M2L on every level >= 1
-//   (the E4 lists), L2L from level 2 down to L, then L2P + P2P per target
-//   leaf.  Strengths are gathered into sorted order by the caller.
+//   (the E4 lists), L2L from level 2 down to L, then L2P per target leaf.
+//   The P2P near field depends on none of these and runs on a side stream
+//   from the start; L2P waits for it and adds the far field to its sums.
+//   Strengths are gathered into sorted order by the caller.
 // Each phase is one launch (per kernel variant) covering every plan of the
 // batch that has work in it; level-wise phases pair plans by their distance
 // from the leaves (M2M) or from the top (L2L), so plans of different depth
@@ -11,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "eval.h"
@@ -120,8 +123,23 @@ struct Launcher {
 
 }  // namespace
 
+hipStream_t side_stream()
+{
+    static std::mutex mu;
+    static hipStream_t ss[64] = {};
+    int dev = 0;
+    hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev < 0 || dev >= 64) return nullptr;
+    if (!ss[dev] && hipStreamCreateWithFlags(&ss[dev], hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        ss[dev] = nullptr;
+    }
+    return ss[dev];
+}
+
 void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_single, hipStream_t s,
-               hipEvent_t *ev)
+               hipStream_t side, hipEvent_t *ev)
 {
     Launcher Lc{jobs_dev, s, n == 1 ? phi_single : nullptr, {}};
     Lc.reset();
@@ -134,6 +152,28 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
 
     int pmax = 1;
     for (int i = 0; i < n; ++i) pmax = std::max(pmax, plans[i]->p);
+    // The P2P near field needs only the sorted sources and the lists: it runs
+    // on the side stream beside the far-field passes on s; L2P joins them.
+    {
+        hipEventRecord(ev[4], s);
+        hipStreamWaitEvent(side, ev[4], 0);
+        hipEventRecord(ev[5], side);
+        {
+            Launcher Ls{jobs_dev, side, n == 1 ? phi_single : nullptr, {}};
+            Ls.reset();
+            auto f = [&](const BatchMap &m) { batch_near_fp64(jobs_dev, m, side); };
+            for (int i = 0; i < n; ++i)
+                if (plans[i]->precision != FMM_PREC_MIXED) Ls.add(i, 0, plans[i]->n_work_near, f);
+            if (Ls.m.n > 0) f(Ls.m);
+            Ls.reset();
+            auto g = [&](const BatchMap &m) { batch_near_mixed(jobs_dev, m, side); };
+            for (int i = 0; i < n; ++i)
+                if (plans[i]->precision == FMM_PREC_MIXED) Ls.add(i, 0, plans[i]->n_work_near, g);
+            if (Ls.m.n > 0) g(Ls.m);
+        }
+        hipEventRecord(ev[6], side);
+    }
+
     // P2M
     {
         auto f = [&](const BatchMap &m) { batch_p2m(jobs_dev, m, pmax, s); };
@@ -170,7 +210,7 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
         }
         go(f);
     }
-    if (ev) hipEventRecord(ev[0], s);
+    hipEventRecord(ev[0], s);
 
     // M2L, one launch per kernel variant present in the batch.
     {
@@ -206,7 +246,7 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
                 go(f);
             }
     }
-    if (ev) hipEventRecord(ev[1], s);
+    hipEventRecord(ev[1], s);
 
     // L2L, step k: level 2 + k.
     for (int l = 2; l <= maxL; ++l)
@@ -219,20 +259,16 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
                 if (plans[i]->geo.L >= l && plans[i]->m2l_pm == pm) Lc.add(i, l, plans[i]->lev[l].n, f);
             go(f);
         }
-    if (ev) hipEventRecord(ev[2], s);
+    hipEventRecord(ev[2], s);
 
-    // L2P + P2P
+    // L2P, after the near field.
+    hipStreamWaitEvent(s, ev[6], 0);
     {
-        auto f = [&](const BatchMap &m) { batch_near_fp64(jobs_dev, m, s); };
-        for (int i = 0; i < n; ++i)
-            if (plans[i]->precision != FMM_PREC_MIXED) Lc.add(i, 0, plans[i]->n_work_near, f);
+        auto f = [&](const BatchMap &m) { batch_l2p(jobs_dev, m, s); };
+        for (int i = 0; i < n; ++i) Lc.add(i, 0, plans[i]->n_work_near, f);
         go(f);
-        auto g = [&](const BatchMap &m) { batch_near_mixed(jobs_dev, m, s); };
-        for (int i = 0; i < n; ++i)
-            if (plans[i]->precision == FMM_PREC_MIXED) Lc.add(i, 0, plans[i]->n_work_near, g);
-        go(g);
     }
-    if (ev) hipEventRecord(ev[3], s);
+    hipEventRecord(ev[3], s);
 }
 
 }  // namespace fmm

@@ -90,7 +90,9 @@ __global__ __launch_bounds__(64) void k_p2m(const EvalJob *__restrict__ jobs, Ba
     constexpr int kChunkS = 32;
     constexpr int kStride = kChunkS + 1;   // odd stride: conflict-free row reads
     extern __shared__ double tab[];          // 2 (pmax + 1) rows of kStride
+    __shared__ double invk[kMaxP + 1];       // 1/k
     const int lane = threadIdx.x;
+    for (int k = lane; k <= kMaxP; k += 64) invk[k] = k ? 1.0 / (double)k : 0.0;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
         const int e = batch_entry(bm, item);
         const EvalJob &J = jobs[bm.job[e]];
@@ -117,7 +119,7 @@ __global__ __launch_bounds__(64) void k_p2m(const EvalJob *__restrict__ jobs, Ba
             }
             cd pw = half ? w : cmul(w, w);   // w^1 or w^2
             for (int k = 1 + (half ? 0 : 1); k <= J.p; k += 2) {
-                const double f = -u / (double)k;
+                const double f = -u * invk[k];
                 tab[(2 * k) * kStride + src_lane] = pw.x * f;
                 tab[(2 * k + 1) * kStride + src_lane] = pw.y * f;
                 pw = cmul(pw, w2);

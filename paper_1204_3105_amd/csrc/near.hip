@@ -1,13 +1,13 @@
-// near.hip -- L2P and the P2P near field, fused per target leaf (FP64).
+// near.hip -- the P2P near field (FP64) and L2P.
 //
 // Each work item is one target leaf and up to 64 of its targets (one wave,
-// one target per lane).  The lane evaluates the leaf's local expansion
-// (Greengard-Rokhlin evaluation of sum_m b~_m ((y - c)/ell)^m, Horner) and
-// then sums u_i Log(y - x_i) over the sources of the leaf and its
-// neighbours ({T} u Neighbors(T), paper Sec. 4), staged through LDS 64 at a
-// time.  Re = ln|y - x| = 0.5 ln(dx^2 + dy^2), Im = atan2(dy, dx) with a
-// -0 dy read as +0; a source with the target's exact coordinates is
-// skipped.  The result is written in the caller's target order.
+// one target per lane).  P2P sums u_i Log(y - x_i) over the sources of the
+// leaf and its neighbours ({T} u Neighbors(T), paper Sec. 4), staged through
+// LDS 64 at a time: Re = ln|y - x| = 0.5 ln(dx^2 + dy^2), Im = atan2(dy, dx)
+// with a -0 dy read as +0; a source with the target's exact coordinates is
+// skipped.  It writes the near sum in the caller's target order and runs
+// beside the far-field passes; L2P then adds the leaf's local expansion
+// (Greengard-Rokhlin evaluation of sum_m b~_m ((y - c)/ell)^m, Horner).
 #include "eval.h"
 
 namespace fmm {
@@ -27,19 +27,6 @@ __global__ __launch_bounds__(64) void k_near_fp64(const EvalJob *__restrict__ jo
         const int32_t t = st + lane;
         const bool ok = t < J.te[gid];
         const double y0 = ok ? J.tx[t] : 0.0, y1 = ok ? J.ty[t] : 0.0;
-
-        // L2P
-        const int P1 = J.p + 1;
-        const double *b = J.lc + gid * 2 * P1;
-        const double inv = 1.0 / J.scale[J.L];
-        const double zr = (y0 - J.cx[gid]) * inv, zi = (y1 - J.cy[gid]) * inv;
-        double fr = b[2 * J.p], fi = b[2 * J.p + 1];
-        for (int m = J.p - 1; m >= 0; --m) {
-            const double nr = fr * zr - fi * zi + b[2 * m];
-            const double ni = fr * zi + fi * zr + b[2 * m + 1];
-            fr = nr;
-            fi = ni;
-        }
 
         // P2P
         double re = 0.0, im = 0.0;
@@ -68,16 +55,53 @@ __global__ __launch_bounds__(64) void k_near_fp64(const EvalJob *__restrict__ jo
         }
         if (ok) {
             const int64_t o = J.tperm[t];
-            phi[2 * o] = fr + re;
-            phi[2 * o + 1] = fi + im;
+            phi[2 * o] = re;
+            phi[2 * o + 1] = im;
         }
+    }
+}
+
+// L2P: phi += the target leaf's local expansion, FP64 Horner (same items).
+__global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, BatchMap bm)
+{
+    const int lane = threadIdx.x;
+    for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
+        const int e = batch_entry(bm, item);
+        const EvalJob &J = jobs[bm.job[e]];
+        double *phi = bm.phi_override ? bm.phi_override : J.phi;
+        const int64_t it = item - bm.pre[e];
+        if (it >= J.counts[0]) continue;
+        const int32_t li = J.work_near[2 * it], st = J.work_near[2 * it + 1];
+        const int64_t gid = J.leaf_off + li;
+        const int32_t t = st + lane;
+        if (t >= J.te[gid]) continue;
+        const int P1 = J.p + 1;
+        const double *b = J.lc + gid * 2 * P1;
+        const double inv = 1.0 / J.scale[J.L];
+        const double zr = (J.tx[t] - J.cx[gid]) * inv, zi = (J.ty[t] - J.cy[gid]) * inv;
+        double fr = b[2 * J.p], fi = b[2 * J.p + 1];
+        for (int m = J.p - 1; m >= 0; --m) {
+            const double nr = fr * zr - fi * zi + b[2 * m];
+            const double ni = fr * zi + fi * zr + b[2 * m + 1];
+            fr = nr;
+            fi = ni;
+        }
+        const int64_t o = J.tperm[t];
+        phi[2 * o] = phi[2 * o] + fr;
+        phi[2 * o + 1] = phi[2 * o + 1] + fi;
     }
 }
 
 void batch_near_fp64(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
 {
     if (m.n <= 0 || m.pre[m.n] <= 0) return;
-    hipLaunchKernelGGL(k_near_fp64, dim3(persistent_grid(m.pre[m.n], 128)), dim3(64), 0, s, jobs, m);
+    hipLaunchKernelGGL(k_near_fp64, dim3(persistent_grid(m.pre[m.n], kNearWavesPerCU)), dim3(64), 0, s, jobs, m);
+}
+
+void batch_l2p(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
+{
+    if (m.n <= 0 || m.pre[m.n] <= 0) return;
+    hipLaunchKernelGGL(k_l2p, dim3(persistent_grid(m.pre[m.n], 64)), dim3(64), 0, s, jobs, m);
 }
 
 }  // namespace fmm

@@ -1,5 +1,5 @@
-// near_mixed.hip -- L2P (FP64) and the P2P near field in FP32 with
-// compensated (Kahan) sums, fused per target leaf.
+// near_mixed.hip -- the P2P near field in FP32 with compensated (Kahan)
+// sums; the FP64 L2P is added afterwards (near.hip).
 //
 // Points are held as FP32 offsets from their own leaf centre, so a pair's
 // separation y - x = (t_loc - (c_S - c_T)) - s_loc is formed from small
@@ -7,39 +7,33 @@
 // absolute FP32 coordinates would suffer.  Per pair:
 //   Re += u * ln|y - x|  = (u ln2 / 2) * log2(dx^2 + dy^2)   (hardware log2)
 //   Im += u * atan2(dy, dx)                                   (own atan2)
-// Both sums are compensated in FP32 (Kahan steps on blocks of four plainly
-// summed pairs) and added to the FP64 far field.
+// Both sums are compensated in FP32 (Kahan steps on blocks of eight plainly
+// summed pairs) and stored in FP64 for the far field to be added to.
 // A pair with a zero separation is skipped (bitwise-equal points).
 #include "eval.h"
 
 namespace fmm {
 
-// atan(t) = t * sum_k c_k t^(2k) for |t| <= tan(pi/8): weighted least-squares
-// fit on Chebyshev nodes (gen_atan_poly.py); max abs error 2.8e-8 in FP32.
-static constexpr float kAtan0 = 9.999999994e-01f, kAtan1 = -3.333330808e-01f,
-                       kAtan2 = 1.999823819e-01f, kAtan3 = -1.424042995e-01f,
-                       kAtan4 = 1.057579194e-01f, kAtan5 = -6.040182834e-02f;
-static constexpr float kTanPi8 = 0.41421356237309503f;
-static constexpr float kPi = 3.14159265358979324f, kPi2 = 1.57079632679489662f,
-                       kPi4 = 0.78539816339744831f;
+// atan(t) = t * sum_k c_k t^(2k) for 0 <= t <= 1: weighted least-squares
+// fit on Chebyshev nodes (gen_atan_poly.py); max abs error 1.8e-7 in FP32.
+static constexpr float kAtanPoly[8] = {9.999999114e-01f, -3.333209348e-01f, 1.997137453e-01f,
+                                       -1.402941598e-01f, 9.942748199e-02f, -5.990455402e-02f,
+                                       2.455700589e-02f, -4.780421207e-03f};
+static constexpr float kPi = 3.14159265358979324f, kPi2 = 1.57079632679489662f;
 
-// atan2 on the principal branch (-pi, pi]; y = -0 is treated as +0.
+// atan2 on the principal branch (-pi, pi]; y = -0 is treated as +0 and
+// (0, 0) gives 0.  t = min/max of |x|, |y| (the max floored so that t stays
+// finite), then the octant is restored.
 __device__ __forceinline__ float atan2_f32(float y, float x)
 {
     const float ax = fabsf(x), ay = fabsf(y);
-    const float mn = fminf(ax, ay), mx = fmaxf(ax, ay);
-    const bool big = mn > kTanPi8 * mx;   // reduce by pi/4: t = (mn - mx)/(mn + mx)
-    const float num = big ? mn - mx : mn;
-    const float den = big ? mn + mx : mx;
-    const float t = num * __builtin_amdgcn_rcpf(den);
+    const float mn = fminf(ax, ay), mx = fmaxf(fmaxf(ax, ay), 1e-30f);
+    const float t = mn * __builtin_amdgcn_rcpf(mx);
     const float z = t * t;
-    float p = kAtan5;
-    p = fmaf(p, z, kAtan4);
-    p = fmaf(p, z, kAtan3);
-    p = fmaf(p, z, kAtan2);
-    p = fmaf(p, z, kAtan1);
-    p = fmaf(p, z, kAtan0);
-    float a = fmaf(t, p, big ? kPi4 : 0.0f);
+    float p = kAtanPoly[7];
+#pragma unroll
+    for (int k = 6; k >= 0; --k) p = fmaf(p, z, kAtanPoly[k]);
+    float a = t * p;
     a = (ay > ax) ? kPi2 - a : a;
     a = (x < 0.0f) ? kPi - a : a;
     return (y < 0.0f) ? -a : a;
@@ -62,25 +56,7 @@ __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ j
         const bool ok = t < J.te[gid];
         const double tcx = J.cx[gid], tcy = J.cy[gid];
 
-        // L2P in FP64.
-        double fr = 0.0, fi = 0.0;
-        float tlx = 0.0f, tly = 0.0f;
-        if (ok) {
-            const int P1 = J.p + 1;
-            const double *b = J.lc + gid * 2 * P1;
-            const double inv = 1.0 / J.scale[J.L];
-            const double zr = (J.tx[t] - tcx) * inv, zi = (J.ty[t] - tcy) * inv;
-            fr = b[2 * J.p];
-            fi = b[2 * J.p + 1];
-            for (int m = J.p - 1; m >= 0; --m) {
-                const double nr = fr * zr - fi * zi + b[2 * m];
-                const double ni = fr * zi + fi * zr + b[2 * m + 1];
-                fr = nr;
-                fi = ni;
-            }
-            tlx = J.txl[t];
-            tly = J.tyl[t];
-        }
+        const float tlx = ok ? J.txl[t] : 0.0f, tly = ok ? J.tyl[t] : 0.0f;
 
         float rs = 0.0f, rc = 0.0f, is = 0.0f, ic = 0.0f;
         // Kahan step for both sums.
@@ -124,17 +100,18 @@ __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ j
                         acc(live ? sv.z * lg : 0.0f, live ? sv.w * at : 0.0f);
                     }
                 } else {
-                    // Distinct leaves: separations are nonzero; the floor
-                    // only keeps a pair closer than FP32 resolution finite.
-                    // Four pairs are summed plainly, then Kahan-added.
+                    // Distinct leaves: separations are nonzero; the 1e-37
+                    // inside r^2 only keeps a pair closer than FP32
+                    // resolution finite.  Eight pairs are summed plainly,
+                    // then Kahan-added.
                     int j = 0;
-                    for (; j + 4 <= nsrc; j += 4) {
+                    for (; j + 8 <= nsrc; j += 8) {
                         float pr = 0.0f, pi = 0.0f;
 #pragma unroll
-                        for (int jj = 0; jj < 4; ++jj) {
+                        for (int jj = 0; jj < 8; ++jj) {
                             const float4 sv = sh[j + jj];
                             const float dx = ax - sv.x, dy = ay - sv.y;
-                            const float r2 = fmaxf(fmaf(dx, dx, dy * dy), 1e-37f);
+                            const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-37f));
                             pr = fmaf(sv.z, __log2f(r2), pr);
                             pi = fmaf(sv.w, atan2_f32(dy, dx), pi);
                         }
@@ -143,7 +120,7 @@ __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ j
                     for (; j < nsrc; ++j) {
                         const float4 sv = sh[j];
                         const float dx = ax - sv.x, dy = ay - sv.y;
-                        const float r2 = fmaxf(fmaf(dx, dx, dy * dy), 1e-37f);
+                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-37f));
                         acc(sv.z * __log2f(r2), sv.w * atan2_f32(dy, dx));
                     }
                 }
@@ -151,8 +128,8 @@ __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ j
         }
         if (ok) {
             const int64_t o = J.tperm[t];
-            phi[2 * o] = fr + ((double)rs - (double)rc);
-            phi[2 * o + 1] = fi + ((double)is - (double)ic);
+            phi[2 * o] = (double)rs - (double)rc;
+            phi[2 * o + 1] = (double)is - (double)ic;
         }
     }
 }
@@ -160,7 +137,7 @@ __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ j
 void batch_near_mixed(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
 {
     if (m.n <= 0 || m.pre[m.n] <= 0) return;
-    hipLaunchKernelGGL(k_near_mixed, dim3(persistent_grid(m.pre[m.n], 128)), dim3(64), 0, s, jobs, m);
+    hipLaunchKernelGGL(k_near_mixed, dim3(persistent_grid(m.pre[m.n], kNearWavesPerCU)), dim3(64), 0, s, jobs, m);
 }
 
 }  // namespace fmm

@@ -674,11 +674,13 @@ fmm_status fmm_eval(fmm_plan_t plan, const double *u, double *phi)
         FMM_HIP_CHECK(hipEventRecord(P->ev[4], s));
         FMM_HIP_CHECK(hipEventRecord(P->ev[5], s));
         FMM_HIP_CHECK(hipEventRecord(P->ev[6], s));
+        FMM_HIP_CHECK(hipEventRecord(P->ev[8], s));
+        FMM_HIP_CHECK(hipEventRecord(P->ev[9], s));
     } else {
         EvalJob J = make_job(*P);
         batch_gather_u((const EvalJob *)P->job_dev, J, du, s);
         Plan *one = P;
-        run_batch(&one, 1, (const EvalJob *)P->job_dev, dphi, s, &P->ev[3]);
+        run_batch(&one, 1, (const EvalJob *)P->job_dev, dphi, s, side_stream(), &P->ev[3]);
     }
     FMM_HIP_CHECK(hipGetLastError());
     P->evaluated = true;
@@ -732,7 +734,8 @@ fmm_status fmm_plan_info_get(fmm_plan_t plan, fmm_plan_info *info)
         info->stage_ms[0] = elapsed(P->ev[2], P->ev[3]);
         info->stage_ms[1] = elapsed(P->ev[3], P->ev[4]);
         info->stage_ms[2] = elapsed(P->ev[4], P->ev[5]);
-        info->stage_ms[3] = elapsed(P->ev[5], P->ev[6]);
+        info->stage_ms[3] = elapsed(P->ev[8], P->ev[9]);
+        info->stage_ms[4] = elapsed(P->ev[5], P->ev[6]);
     }
     (void)hipGetLastError();
     return FMM_OK;

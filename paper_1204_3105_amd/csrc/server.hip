@@ -59,8 +59,9 @@ struct Server {
     int64_t used = 0;
     int admitted = 0;
     bool stop = false;
-    hipStream_t s_plan = nullptr, s_eval = nullptr;
+    hipStream_t s_plan = nullptr, s_eval = nullptr, s_near = nullptr;
     hipEvent_t done_ev = nullptr;
+    hipEvent_t bev[7] = {};   // run_batch stage, fork and near-field events
     EvalJob *jobs = nullptr;
     size_t jobs_cap = 0;
     int device = 0;
@@ -172,7 +173,8 @@ static void launch_batch(Server &S, std::vector<Req *> &batch)
         EvalJob J = make_job(*plans[i]);
         batch_gather_u(S.jobs, J, work[i]->d_u, S.s_eval);
     }
-    if (!plans.empty()) run_batch(plans.data(), (int)plans.size(), S.jobs, nullptr, S.s_eval, nullptr);
+    if (!plans.empty())
+        run_batch(plans.data(), (int)plans.size(), S.jobs, nullptr, S.s_eval, S.s_near, S.bev);
     hipEventRecord(S.done_ev, S.s_eval);
 }
 
@@ -271,10 +273,18 @@ fmm_status fmm_server_create(const fmm_server_options *opt, fmm_server_t *out)
     hipGetDevice(&S->device);
     if (hipStreamCreateWithFlags(&S->s_plan, hipStreamNonBlocking) != hipSuccess ||
         hipStreamCreateWithFlags(&S->s_eval, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&S->s_near, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&S->done_ev, hipEventDisableTiming) != hipSuccess) {
         set_error("stream or event creation failed");
         delete S;
         return FMM_E_DEVICE;
+    }
+    for (auto &e : S->bev) {
+        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+            set_error("event creation failed");
+            delete S;
+            return FMM_E_DEVICE;
+        }
     }
     S->th = std::thread(scheduler, S);
     *out = (fmm_server_t)S;
@@ -379,8 +389,10 @@ fmm_status fmm_server_destroy(fmm_server_t s)
     for (auto &kv : S->all) delete kv.second;
     if (S->jobs) dev_free(S->jobs, S->jobs_cap * sizeof(EvalJob));
     hipEventDestroy(S->done_ev);
+    for (auto &e : S->bev) hipEventDestroy(e);
     hipStreamDestroy(S->s_plan);
     hipStreamDestroy(S->s_eval);
+    hipStreamDestroy(S->s_near);
     delete S;
     return FMM_OK;
 }

@@ -239,7 +239,7 @@ class Plan:
             "targets_are_sources": bool(inf.targets_are_sources), "e4_width": inf.e4_width,
             "n_cells": list(inf.n_cells[: inf.lmax + 1]), "n_m2l_pairs": inf.n_m2l_pairs,
             "n_near_pairs": inf.n_near_pairs, "device_bytes": inf.device_bytes,
-            "plan_ms": inf.plan_ms, "eval_ms": inf.eval_ms, "stage_ms": list(inf.stage_ms[:4]),
+            "plan_ms": inf.plan_ms, "eval_ms": inf.eval_ms, "stage_ms": list(inf.stage_ms[:5]),
         }
 
     def export_points(self):
