@@ -629,17 +629,19 @@ fmm_status fmm_plan(fmm_tiling tiling, const double *src, int64_t n_src, const d
     if (o.device_pointers) {
         P->stream = (hipStream_t)o.stream;   // NULL: the null stream
     } else {
-        if (hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking) != hipSuccess) {
+        const hipError_t e = hipStreamCreateWithFlags(&P->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
             delete P;
-            return fail(FMM_E_DEVICE, "hipStreamCreate failed");
+            return fail(FMM_E_DEVICE, std::string("hipStreamCreate failed: ") + hipGetErrorString(e));
         }
         P->own_stream = true;
     }
-    for (auto &e : P->ev) {
-        if (hipEventCreate(&e) != hipSuccess) {
+    for (auto &ev : P->ev) {
+        const hipError_t e = hipEventCreate(&ev);
+        if (e != hipSuccess) {
             release(P);
             delete P;
-            return fail(FMM_E_DEVICE, "hipEventCreate failed");
+            return fail(FMM_E_DEVICE, std::string("hipEventCreate failed: ") + hipGetErrorString(e));
         }
     }
     fmm_status st = build_plan(P, (int)tiling, src, n_src, tgt, n_tgt, eps, o);

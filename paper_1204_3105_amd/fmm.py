@@ -78,6 +78,14 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError("libfmm2d.so is not built (run __graft_entry__.build()): %s" % LIB_PATH)
+    # PyTorch ships its own HIP runtime under the same soname.  Loading torch
+    # first makes the library bind to that runtime, so device pointers and
+    # streams from torch are valid here; loading ours first would put a second
+    # HIP runtime into the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     D = C.POINTER(C.c_double)

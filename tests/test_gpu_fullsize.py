@@ -1,0 +1,128 @@
+"""Parity at the benchmark's full sizes, in the launch configuration the
+benchmark times: device-resident complex128 points and float64 strengths,
+plan + evaluate on torch's stream, leaf size 64.
+
+* N = M = 2^20 uniform in the unit square (the benchmark's own draw), all
+  three tilings, eps = 1e-6 in the mixed form and the FP64 form, and
+  eps = 1e-10 in FP64: keys, permutations, cells, ranges, E4 and near lists
+  bit-exact against the oracle; potentials on 512 seeded targets against the
+  oracle run on all sources (FP64 <= 1e-12, mixed <= eps) and the real part
+  against the direct sum (<= eps).
+* 4M Gaussian-mixture sources (8 clusters, sigma 0.02, N(0,1) strengths)
+  with 4M separate uniform targets, septree and triangle-quadtree, eps 1e-6,
+  mixed and FP64.
+* 16M points uniform in the unit disk, quadtree and septree, eps 1e-4 and
+  1e-6, mixed and FP64.
+Every case prints its sizes, p, depth and errors before asserting.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1204_3105_amd import inputs
+from test_gpu_parity import check_tree
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_1204_3105_amd import fmm
+    fmm.lib()
+    return fmm
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    return torch
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def solve(F, torch, w, tiling, eps, prec):
+    dev = torch.device("cuda:0")
+    src = torch.tensor(w.xs + 1j * w.ys, dtype=torch.complex128, device=dev)
+    tgt = src if w.same else torch.tensor(w.xt + 1j * w.yt, dtype=torch.complex128, device=dev)
+    u = torch.tensor(w.u, dtype=torch.float64, device=dev)
+    plan = F.Plan(tiling, src=src, tgt=tgt, eps=eps, precision=prec, leaf_size=64)
+    phi = plan.eval(u).cpu().numpy()
+    return plan, phi
+
+
+def check_sampled(orc, w, tiling, inf, phis, eps, nsample, seed, direct=True):
+    """phis: {precision: phi}.  One oracle run on all sources for the sampled
+    targets serves every precision (same geometry, depth and p)."""
+    idx = inputs.subsample(w.n_tgt, nsample, seed)
+    g = orc.geom(tiling, inf["lmax"], *inf["geometry"])
+    ref = orc.fmm(g, inf["p"], w.xs, w.ys, w.u, w.xt[idx], w.yt[idx])
+    d = orc.direct_principal(w.xs, w.ys, w.u, w.xt[idx], w.yt[idx]) if direct else None
+    for prec, phi in phis.items():
+        e = rel(phi[idx], ref)
+        er = rel(phi[idx].real, d.real) if direct else float("nan")
+        say("  %s %s N=%d M=%d p=%d L=%d eps=%g: rel L2 vs oracle %.3e, Re vs direct %.3e"
+            % (tiling, prec, w.n_src, w.n_tgt, inf["p"], inf["lmax"], eps, e, er))
+        assert e <= (1e-12 if prec == "fp64" else eps), (prec, e)
+        if direct:
+            assert er <= eps, (prec, er)
+
+
+@pytest.mark.parametrize("tiling", ["quad", "sept", "tri"])
+def test_uniform_1m_eps6(F, orc, torch, tiling):
+    w = inputs.uniform_square(1 << 20, seed=2)
+    say("uniform 2^20 %s eps 1e-6" % tiling)
+    phis, infos = {}, {}
+    for prec in ("mixed", "fp64"):
+        plan, phis[prec] = solve(F, torch, w, tiling, 1e-6, prec)
+        infos[prec] = plan.info()
+        assert infos[prec]["precision"] == prec
+        if prec == "mixed":
+            check_tree(F, orc, plan, w, tiling)
+            say("  tree, keys and lists bit-exact")
+        plan.close()
+    assert infos["mixed"]["p"] == infos["fp64"]["p"]
+    assert infos["mixed"]["geometry"] == infos["fp64"]["geometry"]
+    check_sampled(orc, w, tiling, infos["fp64"], phis, 1e-6, 512, 7)
+
+
+@pytest.mark.parametrize("tiling", ["quad", "sept", "tri"])
+def test_uniform_1m_eps10_fp64(F, orc, torch, tiling):
+    w = inputs.uniform_square(1 << 20, seed=2)
+    say("uniform 2^20 %s eps 1e-10 fp64" % tiling)
+    plan, phi = solve(F, torch, w, tiling, 1e-10, "fp64")
+    inf = plan.info()
+    plan.close()
+    check_sampled(orc, w, tiling, inf, {"fp64": phi}, 1e-10, 256, 8)
+
+
+@pytest.mark.parametrize("tiling", ["sept", "tri"])
+def test_gaussian_mixture_4m(F, orc, torch, tiling):
+    w = inputs.gaussian_mixture(4 << 20, 4 << 20, seed=3)
+    say("gaussian mixture 4M -> 4M uniform %s eps 1e-6" % tiling)
+    phis, inf = {}, None
+    for prec in ("mixed", "fp64"):
+        plan, phis[prec] = solve(F, torch, w, tiling, 1e-6, prec)
+        inf = plan.info()
+        plan.close()
+    check_sampled(orc, w, tiling, inf, phis, 1e-6, 256, 9)
+
+
+@pytest.mark.parametrize("tiling", ["quad", "sept"])
+@pytest.mark.parametrize("eps", [1e-4, 1e-6])
+def test_unit_disk_16m(F, orc, torch, tiling, eps):
+    w = inputs.unit_disk(16 << 20, seed=4)
+    say("unit disk 16M %s eps %g" % (tiling, eps))
+    phis, inf = {}, None
+    for prec in ("mixed", "fp64"):
+        plan, phis[prec] = solve(F, torch, w, tiling, eps, prec)
+        inf = plan.info()
+        plan.close()
+    check_sampled(orc, w, tiling, inf, phis, eps, 128, 10)
