@@ -275,13 +275,27 @@ int mixed_setup(Plan &P)
     return hipGetLastError() != hipSuccess;
 }
 
+// One workgroup (4 waves) per tile of up to 64 target cells of one (level,
+// group); wave w owns target columns 16w..16w+15.  The slots with at least one
+// source in the tile are listed first (E4 rows staged in LDS), then processed
+// as a software pipeline: while the MFMAs of slot i read its split matrix
+// from one LDS buffer, the matrix, monopole row and gathered source columns of
+// slot i+1 are already in flight to registers and go to the other buffer
+// after the MFMAs, so one barrier per slot and no load on the critical path.
 template <int MT, int KB>
 __global__ __launch_bounds__(256) void k_m2l_bf16x3(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
     constexpr int NA = MT * KB * 3 * 64;   // bf16x8 vectors of one slot's matrix
-    __shared__ bf16x8 Ash[NA];
+    constexpr int NR = 32 * MT;            // output rows (>= 2(p+1))
+    constexpr int PER = (NA + 255) / 256;  // staging vectors per thread
+    __shared__ bf16x8 Ash[2][NA];
+    __shared__ double A0s[2][NR];
+    __shared__ int32_t srcs[kMaxSlots][64];
+    __shared__ int8_t act[kMaxSlots];
+    __shared__ int32_t nact;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int n = lane % 16, q = lane / 16;
+    const bf16x8 zero8 = {};
     // XCD-aware order: the 8 XCDs each take a contiguous eighth of the tiles
     // (workgroups are dealt to XCDs round-robin), so the tiles of one
     // (level, group) -- which share translation matrices -- stay on one L2.
@@ -296,64 +310,117 @@ __global__ __launch_bounds__(256) void k_m2l_bf16x3(const EvalJob *__restrict__ 
         const int key = tile[0], start = tile[1], count = tile[2];
         const int G = J.G, S = J.ew, p = J.p, pm = J.pm;
         const int l = key / G, g = key % G;
-        const int col = 16 * w + n;
-        const bool valid = col < count;
-        const int32_t gid = valid ? J.mix_list[start + col] : -1;
         const int P1 = p + 1;
         const int tl = J.sept ? l : 0;
+        const bf16x8 *Tbase = (const bf16x8 *)J.mix_tab + ((size_t)tl * G + g) * S * (size_t)NA;
+        const double *A0base = J.m2l_a0 + 2 * ((size_t)l * G + g) * S * (pm + 1);
+        const bf16x8 *Bbase = (const bf16x8 *)J.mix_b + q;
+
+        // E4 rows of the tile's targets -> srcs[slot][column] (4 threads per
+        // target), then the list of slots that have any source.
+        __syncthreads();   // the previous tile is done with the LDS
+        {
+            const int c = threadIdx.x >> 2, part = threadIdx.x & 3;
+            const int32_t gc = c < count ? J.mix_list[start + c] : -1;
+            for (int s = part; s < S; s += 4) srcs[s][c] = gc >= 0 ? J.e4[(int64_t)gc * S + s] : -1;
+        }
+        __syncthreads();
+        if (threadIdx.x < S) {
+            bool any = false;
+            for (int c = 0; c < 64; ++c) any = any || srcs[threadIdx.x][c] >= 0;
+            act[threadIdx.x] = any ? 1 : 0;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int k = 0;
+            for (int s = 0; s < S; ++s)
+                if (act[s]) act[k++] = (int8_t)s;
+            nact = k;
+        }
+        __syncthreads();
+        const int NS = nact;
+        const int col = 16 * w + n;
+
+        bf16x8 stage[PER];
+        double a0row = 0.0;
+        bf16x8 bcur[3 * KB], bnext[3 * KB];
+        double a0cur = 0.0, a0next = 0.0;
+        // Global loads of slot s: its matrix and monopole row into registers,
+        // this lane's gathered source column into b.
+        auto load_slot = [&](int s, bf16x8 *b, double &a0) {
+            const bf16x8 *T = Tbase + (size_t)s * NA;
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int i = threadIdx.x + 256 * k;
+                stage[k] = i < NA ? T[i] : zero8;
+            }
+            a0row = (threadIdx.x < NR && threadIdx.x < 2 * P1)
+                        ? A0base[(size_t)s * 2 * (pm + 1) + threadIdx.x] : 0.0;
+            const int32_t src = srcs[s][col];
+            if (src >= 0) {
+                const bf16x8 *Bs = Bbase + (int64_t)src * KB * 3 * 4;
+#pragma unroll
+                for (int k = 0; k < 3 * KB; ++k) b[k] = Bs[k * 4];
+                a0 = J.mp[(int64_t)src * 2 * P1];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 3 * KB; ++k) b[k] = zero8;
+                a0 = 0.0;
+            }
+        };
+        auto store_slot = [&](int buf) {
+#pragma unroll
+            for (int k = 0; k < PER; ++k) {
+                const int i = threadIdx.x + 256 * k;
+                if (i < NA) Ash[buf][i] = stage[k];
+            }
+            if (threadIdx.x < NR) A0s[buf][threadIdx.x] = a0row;
+        };
+
         double acc[MT][4];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[mt][j] = 0.0;
-        for (int s = 0; s < S; ++s) {
-            const int32_t src = valid ? J.e4[(int64_t)gid * S + s] : -1;
-            // Block-uniform skip when no target of the tile has this slot.
-            if (!__syncthreads_or(src >= 0)) continue;
-            const bf16x8 *T = (const bf16x8 *)(J.mix_tab + (((size_t)tl * G + g) * S + s) * (size_t)(NA * 8));
-            for (int i = threadIdx.x; i < NA; i += 256) Ash[i] = T[i];
-            const double *a = src >= 0 ? J.mp + (int64_t)src * 2 * P1 : nullptr;
-            bf16x8 bh[KB], bmd[KB], bl[KB];
-            const bf16x8 *Bs = (const bf16x8 *)J.mix_b + ((int64_t)(src >= 0 ? src : 0) * KB * 3) * 4 + q;
-#pragma unroll
-            for (int kb = 0; kb < KB; ++kb) {
-                if (src >= 0) {
-                    bh[kb] = Bs[(kb * 3 + 0) * 4];
-                    bmd[kb] = Bs[(kb * 3 + 1) * 4];
-                    bl[kb] = Bs[(kb * 3 + 2) * 4];
-                } else {
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) bh[kb][j] = bmd[kb][j] = bl[kb][j] = (__bf16)0.0f;
-                }
-            }
-            const double a0 = a ? a[0] : 0.0;
-            const double *A0 = J.m2l_a0 + 2 * (((size_t)l * G + g) * S + s) * (pm + 1);
-            __syncthreads();
+        if (NS > 0) {
+            load_slot(act[0], bcur, a0cur);
+            store_slot(0);
+        }
+        __syncthreads();
+        for (int i = 0; i < NS; ++i) {
+            const int buf = i & 1;
+            const bool more = i + 1 < NS;
+            if (more) load_slot(act[i + 1], bnext, a0next);
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
                 floatx4 c = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int kb = 0; kb < KB; ++kb) {
-                    const bf16x8 *t3 = Ash + (mt * KB + kb) * 3 * 64;
+                    const bf16x8 *t3 = Ash[buf] + (mt * KB + kb) * 3 * 64;
                     const bf16x8 ah = t3[lane], am = t3[64 + lane], al = t3[128 + lane];
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[kb], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bmd[kb], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh[kb], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[kb], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[kb], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bmd[kb], c, 0, 0, 0);
+                    const bf16x8 bh = bcur[kb * 3 + 0], bmd = bcur[kb * 3 + 1], bl = bcur[kb * 3 + 2];
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bmd, c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bh, c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am, bmd, c, 0, 0, 0);
                 }
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int row = 16 * mt + 4 * q + j;
                     // monopole terms in FP64: a0 Log(c_T - c_S), -a0 delta^-m / m
-                    const double t0 = (a && row < 2 * P1) ? a0 * A0[row] : 0.0;
-                    acc[mt][j] += (double)c[j] + t0;
+                    const int row = 16 * mt + 4 * q + j;
+                    acc[mt][j] += (double)c[j] + a0cur * A0s[buf][row];
                 }
             }
+            if (more) store_slot(buf ^ 1);
             __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 3 * KB; ++k) bcur[k] = bnext[k];
+            a0cur = a0next;
         }
-        if (valid) {
+        if (col < count) {
+            const int32_t gid = J.mix_list[start + col];
             double *out = J.lc + (int64_t)gid * 2 * P1;
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)

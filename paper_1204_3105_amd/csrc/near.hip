@@ -62,27 +62,34 @@ __global__ __launch_bounds__(64) void k_near_fp64(const EvalJob *__restrict__ jo
 }
 
 // L2P: phi += the target leaf's local expansion, FP64 Horner (same items).
+// The leaf's coefficient row is staged in LDS by the whole wave first, so the
+// Horner loop reads broadcast LDS instead of a chain of dependent loads.
 __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
+    __shared__ double row[2 * (kMaxP + 1)];
     const int lane = threadIdx.x;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
         const int e = batch_entry(bm, item);
         const EvalJob &J = jobs[bm.job[e]];
         double *phi = bm.phi_override ? bm.phi_override : J.phi;
         const int64_t it = item - bm.pre[e];
-        if (it >= J.counts[0]) continue;
+        if (it >= J.counts[0]) continue;   // uniform across the wave
         const int32_t li = J.work_near[2 * it], st = J.work_near[2 * it + 1];
         const int64_t gid = J.leaf_off + li;
-        const int32_t t = st + lane;
-        if (t >= J.te[gid]) continue;
         const int P1 = J.p + 1;
         const double *b = J.lc + gid * 2 * P1;
+        __syncthreads();
+        if (lane < 2 * P1) row[lane] = b[lane];
+        if (lane + 64 < 2 * P1) row[lane + 64] = b[lane + 64];
+        __syncthreads();
+        const int32_t t = st + lane;
+        if (t >= J.te[gid]) continue;
         const double inv = 1.0 / J.scale[J.L];
         const double zr = (J.tx[t] - J.cx[gid]) * inv, zi = (J.ty[t] - J.cy[gid]) * inv;
-        double fr = b[2 * J.p], fi = b[2 * J.p + 1];
+        double fr = row[2 * J.p], fi = row[2 * J.p + 1];
         for (int m = J.p - 1; m >= 0; --m) {
-            const double nr = fr * zr - fi * zi + b[2 * m];
-            const double ni = fr * zi + fi * zr + b[2 * m + 1];
+            const double nr = fr * zr - fi * zi + row[2 * m];
+            const double ni = fr * zi + fi * zr + row[2 * m + 1];
             fr = nr;
             fi = ni;
         }

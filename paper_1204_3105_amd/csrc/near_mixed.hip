@@ -39,9 +39,20 @@ __device__ __forceinline__ float atan2_f32(float y, float x)
     return (y < 0.0f) ? -a : a;
 }
 
+__device__ __forceinline__ float readlane_f(float v, int k)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+// One wave per work item (a target leaf and up to 64 of its targets, one per
+// lane).  The item's near cells are described once, one lane per slot (cell,
+// source range, FP32 offset from the target leaf), and read back with
+// readlane; sources go through LDS in chunks of 64 with the next chunk's
+// loads in flight while the current one is summed (double buffer, one
+// barrier per chunk).
 __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
-    __shared__ float4 sh[64];
+    __shared__ float4 sh[2][64];
     const int lane = threadIdx.x;
     const float half_ln2 = 0.34657359027997264f;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
@@ -55,8 +66,32 @@ __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ j
         const int32_t t = st + lane;
         const bool ok = t < J.te[gid];
         const double tcx = J.cx[gid], tcy = J.cy[gid];
-
         const float tlx = ok ? J.txl[t] : 0.0f, tly = ok ? J.tyl[t] : 0.0f;
+
+        // Near-cell table, lane k = slot k; an absent or empty cell has an
+        // empty range.
+        const int nw = J.nw;
+        int32_t mc = -1, mb = 0, me = 0;
+        float mdx = 0.0f, mdy = 0.0f;
+        if (lane < nw) {
+            mc = J.near[li * nw + lane];
+            if (mc >= 0) {
+                mb = J.sb[mc];
+                me = J.se[mc];
+                mdx = (float)(J.cx[mc] - tcx);
+                mdy = (float)(J.cy[mc] - tcy);
+            }
+        }
+        auto beg = [&](int k) { return __builtin_amdgcn_readlane(mb, k); };
+        auto end = [&](int k) { return __builtin_amdgcn_readlane(me, k); };
+        float4 pf = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        auto fetch = [&](int k, int32_t base) {
+            const int32_t i = base + lane;
+            if (i < end(k)) {
+                const float u = J.suf[i];
+                pf = make_float4(J.sxl[i], J.syl[i], u * half_ln2, u);
+            }
+        };
 
         float rs = 0.0f, rc = 0.0f, is = 0.0f, ic = 0.0f;
         // Kahan step for both sums.
@@ -70,61 +105,73 @@ __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ j
             ic = (ti - is) - yi;
             is = ti;
         };
-        for (int k = 0; k < J.nw; ++k) {
+        int k = 0;
+        while (k < nw && beg(k) == end(k)) ++k;
+        int32_t base = k < nw ? beg(k) : 0;
+        int buf = 0;
+        if (k < nw) {
+            fetch(k, base);
+            sh[0][lane] = pf;
+        }
+        __syncthreads();
+        while (k < nw) {
+            // The chunk after this one: the rest of this cell, else the next
+            // nonempty cell.
+            int k2 = k;
+            int32_t base2 = base + 64;
+            if (base2 >= end(k)) {
+                k2 = k + 1;
+                while (k2 < nw && beg(k2) == end(k2)) ++k2;
+                base2 = k2 < nw ? beg(k2) : 0;
+            }
+            if (k2 < nw) fetch(k2, base2);
+
             // Slot 0 is the target leaf itself: only there can a source have
             // the target's exact coordinates (equal points share a leaf key).
-            const int32_t c = __builtin_amdgcn_readfirstlane(J.near[li * J.nw + k]);
-            if (c < 0) continue;
-            const bool self = c == gid;
-            const float ax = tlx - (float)(J.cx[c] - tcx);
-            const float ay = tly - (float)(J.cy[c] - tcy);
-            const int32_t b0 = __builtin_amdgcn_readfirstlane(J.sb[c]);
-            const int32_t e0 = __builtin_amdgcn_readfirstlane(J.se[c]);
-            for (int32_t base = b0; base < e0; base += 64) {
-                __syncthreads();
-                const int32_t i = base + lane;
-                if (i < e0) {
-                    const float u = J.suf[i];
-                    sh[lane] = make_float4(J.sxl[i], J.syl[i], u * half_ln2, u);
+            const bool self = __builtin_amdgcn_readlane(mc, k) == gid;
+            const float ax = tlx - readlane_f(mdx, k);
+            const float ay = tly - readlane_f(mdy, k);
+            const int nsrc = end(k) - base < 64 ? end(k) - base : 64;
+            const float4 *src = sh[buf];
+            if (self) {
+                for (int j = 0; j < nsrc; ++j) {
+                    const float4 sv = src[j];
+                    const float dx = ax - sv.x, dy = ay - sv.y;
+                    const float r2 = fmaf(dx, dx, dy * dy);
+                    const bool live = r2 > 0.0f;
+                    const float lg = __log2f(live ? r2 : 1.0f);
+                    const float at = atan2_f32(dy, dx);
+                    acc(live ? sv.z * lg : 0.0f, live ? sv.w * at : 0.0f);
                 }
-                __syncthreads();
-                const int nsrc = e0 - base < 64 ? e0 - base : 64;
-                if (self) {
-                    for (int j = 0; j < nsrc; ++j) {
-                        const float4 sv = sh[j];
-                        const float dx = ax - sv.x, dy = ay - sv.y;
-                        const float r2 = fmaf(dx, dx, dy * dy);
-                        const bool live = r2 > 0.0f;
-                        const float lg = __log2f(live ? r2 : 1.0f);
-                        const float at = atan2_f32(dy, dx);
-                        acc(live ? sv.z * lg : 0.0f, live ? sv.w * at : 0.0f);
-                    }
-                } else {
-                    // Distinct leaves: separations are nonzero; the 1e-37
-                    // inside r^2 only keeps a pair closer than FP32
-                    // resolution finite.  Eight pairs are summed plainly,
-                    // then Kahan-added.
-                    int j = 0;
-                    for (; j + 8 <= nsrc; j += 8) {
-                        float pr = 0.0f, pi = 0.0f;
+            } else {
+                // Distinct leaves: separations are nonzero; the 1e-37 inside
+                // r^2 only keeps a pair closer than FP32 resolution finite.
+                // Eight pairs are summed plainly, then Kahan-added.
+                int j = 0;
+                for (; j + 8 <= nsrc; j += 8) {
+                    float pr = 0.0f, pi = 0.0f;
 #pragma unroll
-                        for (int jj = 0; jj < 8; ++jj) {
-                            const float4 sv = sh[j + jj];
-                            const float dx = ax - sv.x, dy = ay - sv.y;
-                            const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-37f));
-                            pr = fmaf(sv.z, __log2f(r2), pr);
-                            pi = fmaf(sv.w, atan2_f32(dy, dx), pi);
-                        }
-                        acc(pr, pi);
-                    }
-                    for (; j < nsrc; ++j) {
-                        const float4 sv = sh[j];
+                    for (int jj = 0; jj < 8; ++jj) {
+                        const float4 sv = src[j + jj];
                         const float dx = ax - sv.x, dy = ay - sv.y;
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-37f));
-                        acc(sv.z * __log2f(r2), sv.w * atan2_f32(dy, dx));
+                        pr = fmaf(sv.z, __log2f(r2), pr);
+                        pi = fmaf(sv.w, atan2_f32(dy, dx), pi);
                     }
+                    acc(pr, pi);
+                }
+                for (; j < nsrc; ++j) {
+                    const float4 sv = src[j];
+                    const float dx = ax - sv.x, dy = ay - sv.y;
+                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-37f));
+                    acc(sv.z * __log2f(r2), sv.w * atan2_f32(dy, dx));
                 }
             }
+            if (k2 < nw) sh[buf ^ 1][lane] = pf;
+            __syncthreads();
+            k = k2;
+            base = base2;
+            buf ^= 1;
         }
         if (ok) {
             const int64_t o = J.tperm[t];

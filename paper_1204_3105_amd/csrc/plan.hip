@@ -212,6 +212,47 @@ static hipError_t upload(void *dst, const void *src, size_t bytes, hipStream_t s
     return hipSuccess;
 }
 
+// ------------------------------------------------------------ readbacks
+// The planner needs two small results on the host (the bounding box, the
+// level boundaries).  Kernels write them straight into coherent pinned host
+// memory (one buffer per host thread, kept for the thread's life); the host
+// spins on an event recorded behind the writer instead of sleeping in a
+// stream synchronisation.
+struct Readback {
+    char *host = nullptr;
+    char *dev = nullptr;
+};
+static constexpr size_t kReadbackBytes = 4096;
+
+static Readback *readback()
+{
+    static thread_local Readback rb;
+    if (!rb.host) {
+        void *h = nullptr, *d = nullptr;
+        if (hipHostMalloc(&h, kReadbackBytes, hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        if (hipHostGetDevicePointer(&d, h, 0) != hipSuccess) {
+            (void)hipGetLastError();
+            hipHostFree(h);
+            return nullptr;
+        }
+        rb.host = (char *)h;
+        rb.dev = (char *)d;
+    }
+    return &rb;
+}
+
+static hipError_t spin_wait(hipEvent_t ev, hipStream_t s)
+{
+    hipError_t e = hipEventRecord(ev, s);
+    if (e != hipSuccess) return e;
+    while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
+    }
+    return e;
+}
+
 // ------------------------------------------------------------ plan storage
 struct PlanImpl : Plan {
     std::vector<std::pair<void *, size_t>> allocs;
@@ -384,16 +425,17 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
 
     // Bounding box (sources and targets), also flags non-finite input.
     const int nbb = 256;
-    double *bbp = take<double>(P, 5 * 2 * nbb + 8, &err);
+    double *bbp = take<double>(P, 5 * 2 * nbb, &err);
     if (err) return fail(FMM_E_NOMEM, "device allocation failed (bbox)");
-    double *bbo = bbp + 10 * nbb;
     // The source and target partial boxes are reduced together.
     launch_bbox(dsrc, n_src, bbp, nbb, s);
     launch_bbox(dtgt, same ? 0 : n_tgt, bbp + 5 * nbb, nbb, s);
-    launch_bbox_final(bbp, 2 * nbb, bbo, s);
+    Readback *rb = readback();
+    if (!rb) return fail(FMM_E_DEVICE, "pinned readback buffer unavailable");
+    launch_bbox_final(bbp, 2 * nbb, (double *)rb->dev, s);
+    FMM_HIP_CHECK(spin_wait(P->ev[10], s));
     double hb[5];
-    FMM_HIP_CHECK(hipMemcpyAsync(hb, bbo, sizeof(hb), hipMemcpyDeviceToHost, s));
-    FMM_HIP_CHECK(hipStreamSynchronize(s));
+    memcpy(hb, (const void *)rb->host, sizeof(hb));
     if (hb[4] > 0) return fail(FMM_E_INVALID, "non-finite coordinate in the input");
     if (n_src + n_tgt == 0) hb[0] = hb[2] = 0.0, hb[1] = hb[3] = 1.0;
 
@@ -434,7 +476,7 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
         P->tx = take<double>(P, M, &err);
         P->ty = take<double>(P, M, &err);
     }
-    int32_t *bad = take<int32_t>(P, 4 + kMaxL + 4, &err);
+    int32_t *bad = take<int32_t>(P, 4, &err);
     size_t rtmp = std::max(radix_tmp_bytes(N), radix_tmp_bytes(M));
     char *sort_tmp = take<char>(P, (int64_t)rtmp, &err);
     if (err) return fail(FMM_E_NOMEM, "device allocation failed (keys)");
@@ -470,10 +512,9 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     scan_exclusive(ids, ids, dense_total, total, scan_tmp, s);
     // Level boundaries and the out-of-domain count -> host, in one copy.
     std::vector<int32_t> bnd(g.L + 3);
-    launch_gather_bounds(P->lev, g.L, ids, total, bad, bad + 4, s);
-    FMM_HIP_CHECK(hipMemcpyAsync(bnd.data(), bad + 4, sizeof(int32_t) * (g.L + 3),
-                                 hipMemcpyDeviceToHost, s));
-    FMM_HIP_CHECK(hipStreamSynchronize(s));
+    launch_gather_bounds(P->lev, g.L, ids, total, bad, (int32_t *)rb->dev, s);
+    FMM_HIP_CHECK(spin_wait(P->ev[11], s));
+    memcpy(bnd.data(), (const void *)rb->host, sizeof(int32_t) * (g.L + 3));
     const int32_t hbad = bnd[g.L + 2];
     if (hbad) return fail(FMM_E_DOMAIN, "points outside the root of the given geometry");
     for (int l = 0; l <= g.L; ++l) {
