@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 LANE_OPS = 256 * 4 * 16 * 2.4e9
 # VALU instructions per source-target pair in the near-field inner loop of our
 # gfx950 build (counted from the kernels' AMD assembly; see the design notes).
-VALU_PER_PAIR = {"fp64": 181.0, "mixed": 31.0}
+VALU_PER_PAIR = {"fp64": 110.0, "mixed": 31.0}
 HBM_PEAK = 8.0e12
 MFMA_BF16_PEAK = 2.5e15
 FP64_PEAK = 78.6e12

@@ -4,7 +4,7 @@
 //   P2M at the leaves, M2M from level L-1 up to 1, M2L on every level >= 1
 //   (the E4 lists), L2L from level 2 down to L, then L2P per target leaf.
 //   The P2P near field depends on none of these and runs on a side stream
-//   from the start; L2P waits for it and adds the far field to its sums.
+//   once P2M is done; L2P waits for it and adds the far field to its sums.
 //   Strengths are gathered into sorted order by the caller.
 // Each phase is one launch (per kernel variant) covering every plan of the
 // batch that has work in it; level-wise phases pair plans by their distance
@@ -152,8 +152,15 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
 
     int pmax = 1;
     for (int i = 0; i < n; ++i) pmax = std::max(pmax, plans[i]->p);
+    // P2M
+    {
+        auto f = [&](const BatchMap &m) { batch_p2m(jobs_dev, m, pmax, s); };
+        for (int i = 0; i < n; ++i) Lc.add(i, 0, plans[i]->lev[plans[i]->geo.L].n, f);
+        go(f);
+    }
     // The P2P near field needs only the sorted sources and the lists: it runs
-    // on the side stream beside the far-field passes on s; L2P joins them.
+    // on the side stream beside the far-field passes after P2M (which runs
+    // alone, at full occupancy); L2P joins them.
     {
         hipEventRecord(ev[4], s);
         hipStreamWaitEvent(side, ev[4], 0);
@@ -174,12 +181,6 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
         hipEventRecord(ev[6], side);
     }
 
-    // P2M
-    {
-        auto f = [&](const BatchMap &m) { batch_p2m(jobs_dev, m, pmax, s); };
-        for (int i = 0; i < n; ++i) Lc.add(i, 0, plans[i]->lev[plans[i]->geo.L].n, f);
-        go(f);
-    }
     // Translation kernel variants: lane form for orders up to 48 (register
     // arrays of PM + 1 coefficients), block form beyond.
     const int pms[] = {0, 8, 16, 24, 32, 40, 48};

@@ -5,16 +5,105 @@
 // leaf and its neighbours ({T} u Neighbors(T), paper Sec. 4), staged through
 // LDS 64 at a time: Re = ln|y - x| = 0.5 ln(dx^2 + dy^2), Im = atan2(dy, dx)
 // with a -0 dy read as +0; a source with the target's exact coordinates is
-// skipped.  It writes the near sum in the caller's target order and runs
-// beside the far-field passes; L2P then adds the leaf's local expansion
-// (Greengard-Rokhlin evaluation of sum_m b~_m ((y - c)/ell)^m, Horner).
+// skipped.  ln and atan2 are evaluated by the FP64 routines below.  It writes
+// the near sum in the caller's target order and runs beside the far-field
+// passes; L2P then adds the leaf's local expansion (Greengard-Rokhlin
+// evaluation of sum_m b~_m ((y - c)/ell)^m, Horner).
 #include "eval.h"
 
 namespace fmm {
 
+// ------------------------------------------------------------ FP64 math
+// Constants from gen_f64_consts.py (series in 60-digit arithmetic).
+static constexpr double kLn2Hi = 0.6931471803691238, kLn2Lo = 1.9082149292705877e-10;
+static constexpr double kPiHi = 3.141592653589793, kPiLo = 1.2246467991473532e-16;
+static constexpr double kPi2Hi = 1.5707963267948966, kPi2Lo = 6.123233995736766e-17;
+static constexpr double kPi6Hi = 0.5235987755982989, kPi6Lo = -5.360408832255455e-17;
+static constexpr double kInvSqrt3 = 0.5773502691896257, kTanPi12 = 0.2679491924311227;
+static constexpr double kSqrtHalf = 0.7071067811865476;
+
+// n / d for d in a safe range (no zero, infinity or denormal): hardware
+// reciprocal, two Newton steps, one residual correction.
+__device__ __forceinline__ double div_f64(double n, double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    const double q = n * r;
+    return fma(r, fma(-d, q, n), q);
+}
+
+// ln x for a positive normal x (Cody & Waite): x = 2^e m, m in
+// [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s), s = (m - 1)/(m + 1),
+// |s| <= 3 - 2 sqrt(2); atanh(s)/s = sum_k s^(2k)/(2k+1), k <= 10
+// (remainder below 1e-17 relative); e ln 2 in two parts.
+__device__ __forceinline__ double ln_f64(double x)
+{
+    int e;
+    double m = frexp(x, &e);   // m in [1/2, 1)
+    const bool lo = m < kSqrtHalf;
+    m = lo ? 2.0 * m : m;
+    e = lo ? e - 1 : e;
+    const double s = div_f64(m - 1.0, m + 1.0);
+    const double z = s * s;
+    double p = 1.0 / 21.0;
+    p = fma(p, z, 1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    const double lm = 2.0 * s + 2.0 * s * (z * p);
+    const double de = (double)e;
+    return fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
+}
+
+// atan2(y, x) on (-pi, pi], y = -0 read as +0, (x, y) != (0, 0) (Cody &
+// Waite): with mn, mx = min, max of |x|, |y|, t = mn/mx in [0, 1]; above
+// tan(pi/12) the addition formula with k = 1/sqrt(3) gives
+// atan t = pi/6 + atan((mn - k mx)/(mx + k mn)), so one division serves
+// both ranges; atan(t) = sum_k (-1)^k t^(2k+1)/(2k+1), k <= 13 for
+// |t| <= tan(pi/12); then the octant.
+__device__ __forceinline__ double atan2_f64(double y, double x)
+{
+    const double ax = fabs(x), ay = fabs(y);
+    const double mn = fmin(ax, ay), mx = fmax(ax, ay);
+    const bool red = mn > kTanPi12 * mx;
+    const double num = red ? fma(-kInvSqrt3, mx, mn) : mn;
+    const double den = red ? fma(kInvSqrt3, mn, mx) : mx;
+    const double t = div_f64(num, den);
+    const double z = t * t;
+    double p = -1.0 / 27.0;
+    p = fma(p, z, 1.0 / 25.0);
+    p = fma(p, z, -1.0 / 23.0);
+    p = fma(p, z, 1.0 / 21.0);
+    p = fma(p, z, -1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, -1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, -1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, -1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, -1.0 / 3.0);
+    double a = fma(t * z, p, t);
+    a = red ? kPi6Hi + (kPi6Lo + a) : a;
+    a = (ay > ax) ? kPi2Hi + (kPi2Lo - a) : a;
+    a = (x < 0.0) ? kPiHi + (kPiLo - a) : a;
+    return (y < 0.0) ? -a : a;
+}
+
+
+// One wave per work item, as the FP32 kernel: a per-item near-cell table
+// (one lane per slot) and double-buffered source chunks in LDS.  Only the
+// leaf itself can hold a source at the target's exact position (equal points
+// share a key), so only its chunks test for zero separation.
 __global__ __launch_bounds__(64) void k_near_fp64(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
-    __shared__ double shx[64], shy[64], shu[64];
+    __shared__ double shx[2][64], shy[2][64], shu[2][64];
     const int lane = threadIdx.x;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
         const int e = batch_entry(bm, item);
@@ -28,30 +117,79 @@ __global__ __launch_bounds__(64) void k_near_fp64(const EvalJob *__restrict__ jo
         const bool ok = t < J.te[gid];
         const double y0 = ok ? J.tx[t] : 0.0, y1 = ok ? J.ty[t] : 0.0;
 
-        // P2P
+        const int nw = J.nw;
+        int32_t mc = -1, mb = 0, me = 0;
+        if (lane < nw) {
+            mc = J.near[li * nw + lane];
+            if (mc >= 0) {
+                mb = J.sb[mc];
+                me = J.se[mc];
+            }
+        }
+        auto beg = [&](int k) { return __builtin_amdgcn_readlane(mb, k); };
+        auto end = [&](int k) { return __builtin_amdgcn_readlane(me, k); };
+        double px = 0.0, py = 0.0, pu = 0.0;
+        auto fetch = [&](int k, int32_t base) {
+            const int32_t i = base + lane;
+            if (i < end(k)) {
+                px = J.sx[i];
+                py = J.sy[i];
+                pu = J.su[i];
+            }
+        };
+
         double re = 0.0, im = 0.0;
-        for (int k = 0; k < J.nw; ++k) {
-            const int32_t c = J.near[li * J.nw + k];
-            if (c < 0) continue;
-            const int32_t b0 = J.sb[c], e0 = J.se[c];
-            for (int32_t base = b0; base < e0; base += 64) {
-                __syncthreads();
-                const int32_t i = base + lane;
-                if (i < e0) {
-                    shx[lane] = J.sx[i];
-                    shy[lane] = J.sy[i];
-                    shu[lane] = J.su[i];
-                }
-                __syncthreads();
-                const int nsrc = e0 - base < 64 ? e0 - base : 64;
+        int k = 0;
+        while (k < nw && beg(k) == end(k)) ++k;
+        int32_t base = k < nw ? beg(k) : 0;
+        int buf = 0;
+        if (k < nw) {
+            fetch(k, base);
+            shx[0][lane] = px;
+            shy[0][lane] = py;
+            shu[0][lane] = pu;
+        }
+        __syncthreads();
+        while (k < nw) {
+            int k2 = k;
+            int32_t base2 = base + 64;
+            if (base2 >= end(k)) {
+                k2 = k + 1;
+                while (k2 < nw && beg(k2) == end(k2)) ++k2;
+                base2 = k2 < nw ? beg(k2) : 0;
+            }
+            if (k2 < nw) fetch(k2, base2);
+
+            const bool self = __builtin_amdgcn_readlane(mc, k) == gid;
+            const int nsrc = end(k) - base < 64 ? end(k) - base : 64;
+            const double *sx = shx[buf], *sy = shy[buf], *su = shu[buf];
+            if (self) {
                 for (int j = 0; j < nsrc; ++j) {
-                    const double dx = y0 - shx[j], dy = y1 - shy[j];
-                    if (dx == 0.0 && dy == 0.0) continue;
-                    const double u = shu[j];
-                    re += u * (0.5 * log(dx * dx + dy * dy));
-                    im += u * atan2(dy + 0.0, dx);
+                    const double dx = y0 - sx[j], dy = y1 - sy[j];
+                    const double r2 = dx * dx + dy * dy;
+                    const bool live = r2 > 0.0;
+                    const double lg = ln_f64(live ? r2 : 1.0);
+                    const double at = atan2_f64(dy, live ? dx : 1.0);
+                    re += live ? su[j] * (0.5 * lg) : 0.0;
+                    im += live ? su[j] * at : 0.0;
+                }
+            } else {
+                for (int j = 0; j < nsrc; ++j) {
+                    const double dx = y0 - sx[j], dy = y1 - sy[j];
+                    const double u = su[j];
+                    re += u * (0.5 * ln_f64(dx * dx + dy * dy));
+                    im += u * atan2_f64(dy, dx);
                 }
             }
+            if (k2 < nw) {
+                shx[buf ^ 1][lane] = px;
+                shy[buf ^ 1][lane] = py;
+                shu[buf ^ 1][lane] = pu;
+            }
+            __syncthreads();
+            k = k2;
+            base = base2;
+            buf ^= 1;
         }
         if (ok) {
             const int64_t o = J.tperm[t];
