@@ -29,7 +29,7 @@ constexpr int kMaxP = 60;         // highest expansion order
 constexpr int kMaxSlots = 42;     // largest E4 list (septree)
 constexpr int kNearSlots = 13;    // largest closed neighbourhood (triangles)
 constexpr int kMaxGroups = 8;     // M2L target groups (triangle: 4 types x 2)
-constexpr int kChunk = 64;        // targets per near-field work item
+constexpr int kChunk = 64;        // targets per near-field work item (at most)
 
 enum Tiling { kQuad = 0, kSept = 1, kTri = 2 };
 

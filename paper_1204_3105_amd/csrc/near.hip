@@ -97,13 +97,20 @@ __device__ __forceinline__ double atan2_f64(double y, double x)
 }
 
 
-// One wave per work item, as the FP32 kernel: a per-item near-cell table
-// (one lane per slot) and double-buffered source chunks in LDS.  Only the
-// leaf itself can hold a source at the target's exact position (equal points
-// share a key), so only its chunks test for zero separation.
-__global__ __launch_bounds__(64) void k_near_fp64(const EvalJob *__restrict__ jobs, BatchMap bm)
+// One wave per work item, laid out as the FP32 kernel: g = min(near slots,
+// 64/m) groups of m target lanes, group q summing the q-th of g equal slices
+// of the item's sources (listed cell after cell) in rounds of LDS-staged
+// chunks (64/g sources rounded down to a multiple of
+// 8, at least 8, padded with zero-strength sources far away); the groups'
+// partial sums are added in group order.  Only slot 0, the leaf itself, can
+// hold a source at the target's exact position (equal points share a key),
+// so only rounds that include it test for zero separation.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_near_fp64(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
-    __shared__ double shx[2][64], shy[2][64], shu[2][64];
+    __shared__ double shx[kNearSlots * 9], shy[kNearSlots * 9], shu[kNearSlots * 9];
+    __shared__ int32_t cbeg[kNearSlots], cend[kNearSlots], cum[kNearSlots + 1];
+    double(*red)[64] = reinterpret_cast<double(*)[64]>(shx);   // after the rounds (needs 128)
+    static_assert(kNearSlots * 9 * 3 >= 128, "reduction buffer");
     const int lane = threadIdx.x;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
         const int e = batch_entry(bm, item);
@@ -113,58 +120,70 @@ __global__ __launch_bounds__(64) void k_near_fp64(const EvalJob *__restrict__ jo
         if (it >= J.counts[0]) continue;
         const int32_t li = J.work_near[2 * it], st = J.work_near[2 * it + 1];
         const int64_t gid = J.leaf_off + li;
-        const int32_t t = st + lane;
-        const bool ok = t < J.te[gid];
-        const double y0 = ok ? J.tx[t] : 0.0, y1 = ok ? J.ty[t] : 0.0;
-
         const int nw = J.nw;
-        int32_t mc = -1, mb = 0, me = 0;
-        if (lane < nw) {
-            mc = J.near[li * nw + lane];
-            if (mc >= 0) {
-                mb = J.sb[mc];
-                me = J.se[mc];
-            }
-        }
-        auto beg = [&](int k) { return __builtin_amdgcn_readlane(mb, k); };
-        auto end = [&](int k) { return __builtin_amdgcn_readlane(me, k); };
-        double px = 0.0, py = 0.0, pu = 0.0;
-        auto fetch = [&](int k, int32_t base) {
-            const int32_t i = base + lane;
-            if (i < end(k)) {
-                px = J.sx[i];
-                py = J.sy[i];
-                pu = J.su[i];
-            }
-        };
+        const int m = min(kChunk, J.te[gid] - st);
+        const int g = max(1, min(nw, 64 / m));
+        const int cl = max(8, (64 / g) & ~7);
+        const int stride = cl + 1;
+        const int grp = lane / m, tau = lane - grp * m;
+        const bool in = grp < g;
+        const int32_t t = st + tau;
+        const double y0 = in ? J.tx[t] : 0.0, y1 = in ? J.ty[t] : 0.0;
 
-        double re = 0.0, im = 0.0;
-        int k = 0;
-        while (k < nw && beg(k) == end(k)) ++k;
-        int32_t base = k < nw ? beg(k) : 0;
-        int buf = 0;
-        if (k < nw) {
-            fetch(k, base);
-            shx[0][lane] = px;
-            shy[0][lane] = py;
-            shu[0][lane] = pu;
+        __syncthreads();   // the previous item is done with the LDS
+        if (lane < nw) {
+            const int32_t c = J.near[li * nw + lane];
+            cbeg[lane] = c >= 0 ? J.sb[c] : 0;
+            cend[lane] = c >= 0 ? J.se[c] : 0;
         }
         __syncthreads();
-        while (k < nw) {
-            int k2 = k;
-            int32_t base2 = base + 64;
-            if (base2 >= end(k)) {
-                k2 = k + 1;
-                while (k2 < nw && beg(k2) == end(k2)) ++k2;
-                base2 = k2 < nw ? beg(k2) : 0;
+        if (lane == 0) {
+            int32_t a = 0;
+            for (int q = 0; q < nw; ++q) {
+                cum[q] = a;
+                a += cend[q] - cbeg[q];
             }
-            if (k2 < nw) fetch(k2, base2);
+            cum[nw] = a;
+        }
+        __syncthreads();
 
-            const bool self = __builtin_amdgcn_readlane(mc, k) == gid;
-            const int nsrc = end(k) - base < 64 ? end(k) - base : 64;
-            const double *sx = shx[buf], *sy = shy[buf], *su = shu[buf];
-            if (self) {
-                for (int j = 0; j < nsrc; ++j) {
+        double re = 0.0, im = 0.0;
+        // This lane's group sums the slice [pos, hi) of the item's sources
+        // listed cell after cell; k is the cell holding pos, base its index.
+        const int32_t total = cum[nw];
+        int32_t pos = in ? (int32_t)((int64_t)grp * total / g) : total;
+        const int32_t hi = in ? (int32_t)((int64_t)(grp + 1) * total / g) : total;
+        int k = 0;
+        while (k + 1 < nw && cum[k + 1] <= pos) ++k;
+        int32_t base = cbeg[k] + (pos - cum[k]);
+        const int goff = (in ? grp : 0) * stride;
+        for (;;) {
+            const bool busy = pos < hi;
+            if (!__any(busy)) break;
+            const int n = busy ? min(min(cl, cend[k] - base), hi - pos) : 0;
+            const bool self_round = __any(busy && k == 0);
+            int maxn = n;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) maxn = max(maxn, __shfl_xor(maxn, o));
+            const int padn = (maxn + 7) & ~7;
+            if (in) {
+                for (int j = tau; j < padn; j += m) {
+                    double x = 1e100, y = 1e100, u = 0.0;
+                    if (j < n) {
+                        const int32_t i = base + j;
+                        x = J.sx[i];
+                        y = J.sy[i];
+                        u = J.su[i];
+                    }
+                    shx[grp * stride + j] = x;
+                    shy[grp * stride + j] = y;
+                    shu[grp * stride + j] = u;
+                }
+            }
+            __syncthreads();
+            const double *sx = shx + goff, *sy = shy + goff, *su = shu + goff;
+            if (self_round) {
+                for (int j = 0; j < padn; ++j) {
                     const double dx = y0 - sx[j], dy = y1 - sy[j];
                     const double r2 = dx * dx + dy * dy;
                     const bool live = r2 > 0.0;
@@ -174,27 +193,36 @@ __global__ __launch_bounds__(64) void k_near_fp64(const EvalJob *__restrict__ jo
                     im += live ? su[j] * at : 0.0;
                 }
             } else {
-                for (int j = 0; j < nsrc; ++j) {
+                for (int j = 0; j < padn; ++j) {
                     const double dx = y0 - sx[j], dy = y1 - sy[j];
                     const double u = su[j];
                     re += u * (0.5 * ln_f64(dx * dx + dy * dy));
                     im += u * atan2_f64(dy, dx);
                 }
             }
-            if (k2 < nw) {
-                shx[buf ^ 1][lane] = px;
-                shy[buf ^ 1][lane] = py;
-                shu[buf ^ 1][lane] = pu;
-            }
             __syncthreads();
-            k = k2;
-            base = base2;
-            buf ^= 1;
+            if (busy) {
+                pos += n;
+                base += n;
+                if (base >= cend[k] && pos < hi) {
+                    ++k;
+                    while (cbeg[k] == cend[k]) ++k;   // pos < hi: a nonempty cell follows
+                    base = cbeg[k];
+                }
+            }
         }
-        if (ok) {
+        red[0][lane] = re;   // the last round's barrier freed the staging buffers
+        red[1][lane] = im;
+        __syncthreads();
+        if (grp == 0) {
+            double sr = 0.0, si = 0.0;
+            for (int q = 0; q < g; ++q) {
+                sr += red[0][q * m + tau];
+                si += red[1][q * m + tau];
+            }
             const int64_t o = J.tperm[t];
-            phi[2 * o] = re;
-            phi[2 * o + 1] = im;
+            phi[2 * o] = sr;
+            phi[2 * o + 1] = si;
         }
     }
 }
@@ -204,6 +232,7 @@ __global__ __launch_bounds__(64) void k_near_fp64(const EvalJob *__restrict__ jo
 // Horner loop reads broadcast LDS instead of a chain of dependent loads.
 __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
+    static_assert(kChunk <= 64, "one item per wave");
     __shared__ double row[2 * (kMaxP + 1)];
     const int lane = threadIdx.x;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
@@ -221,7 +250,7 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
         if (lane + 64 < 2 * P1) row[lane + 64] = b[lane + 64];
         __syncthreads();
         const int32_t t = st + lane;
-        if (t >= J.te[gid]) continue;
+        if (lane >= kChunk || t >= J.te[gid]) continue;
         const double inv = 1.0 / J.scale[J.L];
         const double zr = (J.tx[t] - J.cx[gid]) * inv, zi = (J.ty[t] - J.cy[gid]) * inv;
         double fr = row[2 * J.p], fi = row[2 * J.p + 1];

@@ -8,7 +8,8 @@
 //   Re += u * ln|y - x|  = (u ln2 / 2) * log2(dx^2 + dy^2)   (hardware log2)
 //   Im += u * atan2(dy, dx)                                   (own atan2)
 // Both sums are compensated in FP32 (Kahan steps on blocks of eight plainly
-// summed pairs) and stored in FP64 for the far field to be added to.
+// summed pairs) and stored in FP64 for the far field to be added to.  The
+// 1e18 padding sources have zero strength: their terms are exact zeros.
 // A pair with a zero separation is skipped (bitwise-equal points).
 #include "eval.h"
 
@@ -39,20 +40,22 @@ __device__ __forceinline__ float atan2_f32(float y, float x)
     return (y < 0.0f) ? -a : a;
 }
 
-__device__ __forceinline__ float readlane_f(float v, int k)
+// One wave per work item: a target leaf and up to 64 of its targets.  With m
+// targets the wave runs g = min(near slots, 64/m) groups of m lanes (one
+// target per lane); the item's sources, listed cell after cell, are cut into
+// g equal slices, one per group, so an item with few targets still fills the
+// wave.  Each round every group
+// stages the next chunk of its slice (within one cell) in LDS (64/g sources rounded
+// down to a multiple of 8, at least 8; padded to a multiple of 8 with
+// zero-strength sources far away) and sums it; the groups' partial sums of a
+// target are added in group order at the end.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_near_mixed(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
-}
-
-// One wave per work item (a target leaf and up to 64 of its targets, one per
-// lane).  The item's near cells are described once, one lane per slot (cell,
-// source range, FP32 offset from the target leaf), and read back with
-// readlane; sources go through LDS in chunks of 64 with the next chunk's
-// loads in flight while the current one is summed (double buffer, one
-// barrier per chunk).
-__global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ jobs, BatchMap bm)
-{
-    __shared__ float4 sh[2][64];
+    // g (cl + 1) <= 117 for every g: 64 (g = 1), 66, 51, 68, 45, ..., 117 (g = 13)
+    __shared__ float4 sh[kNearSlots * 9];
+    __shared__ int32_t cbeg[kNearSlots], cend[kNearSlots], cum[kNearSlots + 1];
+    __shared__ float cdx[kNearSlots], cdy[kNearSlots];
+    double(*red)[64] = reinterpret_cast<double(*)[64]>(sh);   // after the rounds
     const int lane = threadIdx.x;
     const float half_ln2 = 0.34657359027997264f;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
@@ -63,35 +66,45 @@ __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ j
         if (it >= J.counts[0]) continue;
         const int32_t li = J.work_near[2 * it], st = J.work_near[2 * it + 1];
         const int64_t gid = J.leaf_off + li;
-        const int32_t t = st + lane;
-        const bool ok = t < J.te[gid];
-        const double tcx = J.cx[gid], tcy = J.cy[gid];
-        const float tlx = ok ? J.txl[t] : 0.0f, tly = ok ? J.tyl[t] : 0.0f;
-
-        // Near-cell table, lane k = slot k; an absent or empty cell has an
-        // empty range.
         const int nw = J.nw;
-        int32_t mc = -1, mb = 0, me = 0;
-        float mdx = 0.0f, mdy = 0.0f;
+        const int m = min(kChunk, J.te[gid] - st);
+        const int g = max(1, min(nw, 64 / m));
+        const int cl = max(8, (64 / g) & ~7);
+        const int stride = g == 1 ? 64 : cl + 1;
+        const int grp = lane / m, tau = lane - grp * m;
+        const bool in = grp < g;
+        const int32_t t = st + tau;
+        const float tlx = in ? J.txl[t] : 0.0f, tly = in ? J.tyl[t] : 0.0f;
+        const double tcx = J.cx[gid], tcy = J.cy[gid];
+
+        // Near-cell table (slot 0 is the leaf itself); an absent cell has an
+        // empty range.
+        __syncthreads();   // the previous item is done with the LDS
         if (lane < nw) {
-            mc = J.near[li * nw + lane];
-            if (mc >= 0) {
-                mb = J.sb[mc];
-                me = J.se[mc];
-                mdx = (float)(J.cx[mc] - tcx);
-                mdy = (float)(J.cy[mc] - tcy);
+            const int32_t c = J.near[li * nw + lane];
+            int32_t b0 = 0, e0 = 0;
+            float dx = 0.0f, dy = 0.0f;
+            if (c >= 0) {
+                b0 = J.sb[c];
+                e0 = J.se[c];
+                dx = (float)(J.cx[c] - tcx);
+                dy = (float)(J.cy[c] - tcy);
             }
+            cbeg[lane] = b0;
+            cend[lane] = e0;
+            cdx[lane] = dx;
+            cdy[lane] = dy;
         }
-        auto beg = [&](int k) { return __builtin_amdgcn_readlane(mb, k); };
-        auto end = [&](int k) { return __builtin_amdgcn_readlane(me, k); };
-        float4 pf = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        auto fetch = [&](int k, int32_t base) {
-            const int32_t i = base + lane;
-            if (i < end(k)) {
-                const float u = J.suf[i];
-                pf = make_float4(J.sxl[i], J.syl[i], u * half_ln2, u);
+        __syncthreads();
+        if (lane == 0) {
+            int32_t a = 0;
+            for (int q = 0; q < nw; ++q) {
+                cum[q] = a;
+                a += cend[q] - cbeg[q];
             }
-        };
+            cum[nw] = a;
+        }
+        __syncthreads();
 
         float rs = 0.0f, rc = 0.0f, is = 0.0f, ic = 0.0f;
         // Kahan step for both sums.
@@ -105,37 +118,44 @@ __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ j
             ic = (ti - is) - yi;
             is = ti;
         };
+        // This lane's group sums the slice [pos, hi) of the item's sources
+        // listed cell after cell; k is the cell holding pos, base its index.
+        const int32_t total = cum[nw];
+        int32_t pos = in ? (int32_t)((int64_t)grp * total / g) : total;
+        const int32_t hi = in ? (int32_t)((int64_t)(grp + 1) * total / g) : total;
         int k = 0;
-        while (k < nw && beg(k) == end(k)) ++k;
-        int32_t base = k < nw ? beg(k) : 0;
-        int buf = 0;
-        if (k < nw) {
-            fetch(k, base);
-            sh[0][lane] = pf;
-        }
-        __syncthreads();
-        while (k < nw) {
-            // The chunk after this one: the rest of this cell, else the next
-            // nonempty cell.
-            int k2 = k;
-            int32_t base2 = base + 64;
-            if (base2 >= end(k)) {
-                k2 = k + 1;
-                while (k2 < nw && beg(k2) == end(k2)) ++k2;
-                base2 = k2 < nw ? beg(k2) : 0;
+        while (k + 1 < nw && cum[k + 1] <= pos) ++k;
+        int32_t base = cbeg[k] + (pos - cum[k]);
+        const float4 *gsh = sh + (in ? grp : 0) * stride;
+        for (;;) {
+            const bool busy = pos < hi;
+            if (!__any(busy)) break;
+            const int n = busy ? min(min(cl, cend[k] - base), hi - pos) : 0;
+            // Only group 0 meets slot 0, the one cell where a source can sit
+            // at the target's exact coordinates.
+            const bool self_round = __any(busy && k == 0);
+            int maxn = n;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) maxn = max(maxn, __shfl_xor(maxn, o));
+            const int padn = (maxn + 7) & ~7;
+            if (in) {
+                float4 *w = sh + grp * stride;
+                for (int j = tau; j < padn; j += m) {
+                    float4 v = make_float4(1e18f, 1e18f, 0.0f, 0.0f);
+                    if (j < n) {
+                        const int32_t i = base + j;
+                        const float u = J.suf[i];
+                        v = make_float4(J.sxl[i], J.syl[i], u * half_ln2, u);
+                    }
+                    w[j] = v;
+                }
             }
-            if (k2 < nw) fetch(k2, base2);
-
-            // Slot 0 is the target leaf itself: only there can a source have
-            // the target's exact coordinates (equal points share a leaf key).
-            const bool self = __builtin_amdgcn_readlane(mc, k) == gid;
-            const float ax = tlx - readlane_f(mdx, k);
-            const float ay = tly - readlane_f(mdy, k);
-            const int nsrc = end(k) - base < 64 ? end(k) - base : 64;
-            const float4 *src = sh[buf];
-            if (self) {
-                for (int j = 0; j < nsrc; ++j) {
-                    const float4 sv = src[j];
+            __syncthreads();
+            const float ax = tlx - (busy ? cdx[k] : 0.0f);
+            const float ay = tly - (busy ? cdy[k] : 0.0f);
+            if (self_round) {
+                for (int j = 0; j < padn; ++j) {
+                    const float4 sv = gsh[j];
                     const float dx = ax - sv.x, dy = ay - sv.y;
                     const float r2 = fmaf(dx, dx, dy * dy);
                     const bool live = r2 > 0.0f;
@@ -147,12 +167,11 @@ __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ j
                 // Distinct leaves: separations are nonzero; the 1e-37 inside
                 // r^2 only keeps a pair closer than FP32 resolution finite.
                 // Eight pairs are summed plainly, then Kahan-added.
-                int j = 0;
-                for (; j + 8 <= nsrc; j += 8) {
+                for (int j = 0; j < padn; j += 8) {
                     float pr = 0.0f, pi = 0.0f;
 #pragma unroll
                     for (int jj = 0; jj < 8; ++jj) {
-                        const float4 sv = src[j + jj];
+                        const float4 sv = gsh[j + jj];
                         const float dx = ax - sv.x, dy = ay - sv.y;
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-37f));
                         pr = fmaf(sv.z, __log2f(r2), pr);
@@ -160,23 +179,30 @@ __global__ __launch_bounds__(64) void k_near_mixed(const EvalJob *__restrict__ j
                     }
                     acc(pr, pi);
                 }
-                for (; j < nsrc; ++j) {
-                    const float4 sv = src[j];
-                    const float dx = ax - sv.x, dy = ay - sv.y;
-                    const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-37f));
-                    acc(sv.z * __log2f(r2), sv.w * atan2_f32(dy, dx));
+            }
+            __syncthreads();
+            if (busy) {
+                pos += n;
+                base += n;
+                if (base >= cend[k] && pos < hi) {
+                    ++k;
+                    while (cbeg[k] == cend[k]) ++k;   // pos < hi: a nonempty cell follows
+                    base = cbeg[k];
                 }
             }
-            if (k2 < nw) sh[buf ^ 1][lane] = pf;
-            __syncthreads();
-            k = k2;
-            base = base2;
-            buf ^= 1;
         }
-        if (ok) {
+        red[0][lane] = (double)rs - (double)rc;   // the last round's barrier freed sh
+        red[1][lane] = (double)is - (double)ic;
+        __syncthreads();
+        if (grp == 0) {
+            double re = 0.0, im = 0.0;
+            for (int q = 0; q < g; ++q) {
+                re += red[0][q * m + tau];
+                im += red[1][q * m + tau];
+            }
             const int64_t o = J.tperm[t];
-            phi[2 * o] = (double)rs - (double)rc;
-            phi[2 * o + 1] = (double)is - (double)ic;
+            phi[2 * o] = re;
+            phi[2 * o + 1] = im;
         }
     }
 }
