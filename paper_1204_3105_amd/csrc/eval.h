@@ -42,7 +42,8 @@ struct EvalJob {
     // Device counts written at plan time: [0] near-field items, [1] mixed M2L
     // tiles.  Launches are sized by host upper bounds; kernels stop here.
     const int32_t *counts;
-    double *phi;   // output, caller's target order, 2 n_tgt doubles
+    double *phi;    // output, caller's target order, 2 n_tgt doubles
+    double *nsum;   // near-field sums, sorted target order, 2 n_tgt doubles
 };
 
 struct BatchMap {

@@ -83,6 +83,7 @@ EvalJob make_job(const Plan &P)
     J.m2l_a0 = P.m2l_a0;
     J.binom = P.binom;
     J.phi = P.phi_int;
+    J.nsum = P.nsum;
     if (P.precision == FMM_PREC_MIXED && P.mixed) {
         int MT, KB;
         mixed_pointers(P, &J.mix_tab, &J.mix_tiles, &J.mix_list, &J.mix_b, &MT, &KB);

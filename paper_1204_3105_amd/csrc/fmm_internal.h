@@ -137,6 +137,7 @@ struct Plan {
     // batched evaluation (caller's target order)
     void *job_dev = nullptr;
     double *phi_int = nullptr;
+    double *nsum = nullptr;         // near-field sums in sorted target order
 
     // scratch for staging host inputs / outputs
     double *io_u = nullptr;

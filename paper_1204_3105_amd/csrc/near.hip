@@ -6,9 +6,9 @@
 // LDS 64 at a time: Re = ln|y - x| = 0.5 ln(dx^2 + dy^2), Im = atan2(dy, dx)
 // with a -0 dy read as +0; a source with the target's exact coordinates is
 // skipped.  ln and atan2 are evaluated by the FP64 routines below.  It writes
-// the near sum in the caller's target order and runs beside the far-field
-// passes; L2P then adds the leaf's local expansion (Greengard-Rokhlin
-// evaluation of sum_m b~_m ((y - c)/ell)^m, Horner).
+// the near sums in sorted target order and runs beside the far-field passes;
+// L2P then adds the leaf's local expansion (Greengard-Rokhlin evaluation of
+// sum_m b~_m ((y - c)/ell)^m, Horner) and writes Phi in the caller's order.
 #include "eval.h"
 
 namespace fmm {
@@ -115,7 +115,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
         const int e = batch_entry(bm, item);
         const EvalJob &J = jobs[bm.job[e]];
-        double *phi = bm.phi_override ? bm.phi_override : J.phi;
         const int64_t it = item - bm.pre[e];
         if (it >= J.counts[0]) continue;
         const int32_t li = J.work_near[2 * it], st = J.work_near[2 * it + 1];
@@ -220,14 +219,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
                 sr += red[0][q * m + tau];
                 si += red[1][q * m + tau];
             }
-            const int64_t o = J.tperm[t];
-            phi[2 * o] = sr;
-            phi[2 * o + 1] = si;
+            J.nsum[2 * t] = sr;   // sorted order: L2P adds the far field and un-permutes
+            J.nsum[2 * t + 1] = si;
         }
     }
 }
 
-// L2P: phi += the target leaf's local expansion, FP64 Horner (same items).
+// L2P: phi (caller's order) = near sum (sorted order) + the target leaf's
+// local expansion, FP64 Horner (same items).
 // The leaf's coefficient row is staged in LDS by the whole wave first, so the
 // Horner loop reads broadcast LDS instead of a chain of dependent loads.
 __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, BatchMap bm)
@@ -261,8 +260,8 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
             fi = ni;
         }
         const int64_t o = J.tperm[t];
-        phi[2 * o] = phi[2 * o] + fr;
-        phi[2 * o + 1] = phi[2 * o + 1] + fi;
+        phi[2 * o] = J.nsum[2 * t] + fr;
+        phi[2 * o + 1] = J.nsum[2 * t + 1] + fi;
     }
 }
 

@@ -61,7 +61,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
         const int e = batch_entry(bm, item);
         const EvalJob &J = jobs[bm.job[e]];
-        double *phi = bm.phi_override ? bm.phi_override : J.phi;
         const int64_t it = item - bm.pre[e];
         if (it >= J.counts[0]) continue;
         const int32_t li = J.work_near[2 * it], st = J.work_near[2 * it + 1];
@@ -200,9 +199,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void
                 re += red[0][q * m + tau];
                 im += red[1][q * m + tau];
             }
-            const int64_t o = J.tperm[t];
-            phi[2 * o] = re;
-            phi[2 * o + 1] = im;
+            J.nsum[2 * t] = re;   // sorted order: L2P adds the far field and un-permutes
+            J.nsum[2 * t + 1] = im;
         }
     }
 }
