@@ -1,12 +1,14 @@
 // sort.hip -- device-wide exclusive scan and stable LSD radix sort.
 //
 // The radix sort orders (key, index) pairs by key, keeping equal keys in
-// index order, so the sorted permutation is unique.  Each pass handles 8
-// bits: per-tile digit histograms, one exclusive scan over the
+// index order, so the sorted permutation is unique.  Each pass handles 7 to
+// 10 bits: per-tile digit histograms, one exclusive scan over the
 // [digit][tile] table, and a scatter in which every element's rank among
 // equal digits of its tile is found with wave64 ballots (a match mask per
 // lane) and per-wave counters in LDS.  Tiles are read in striped order, so
 // ranks follow the original order and the pass is stable.
+#include <algorithm>
+
 #include "fmm_internal.h"
 
 namespace fmm {
@@ -127,64 +129,78 @@ void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *total, 
 }
 
 // ------------------------------------------------------------------ radix
+// Digits of W bits (7..10); a key of B bits takes ceil(B/10) passes, the
+// digits split evenly, so keys up to 20 bits sort in two passes.
 constexpr int kRadixThreads = 256;
 constexpr int kRadixItems = 8;
 constexpr int kRadixTile = kRadixThreads * kRadixItems;   // striped rounds of 256
+constexpr int kRadixMaxBins = 1024;
 
-__global__ void k_radix_count(const uint32_t *__restrict__ keys, int64_t n, int shift,
-                              int32_t *__restrict__ counts, int ntiles)
+template <int W>
+__global__ __launch_bounds__(kRadixThreads) void k_radix_count(const uint32_t *__restrict__ keys, int64_t n,
+                                                               int shift, int32_t *__restrict__ counts,
+                                                               int ntiles)
 {
-    __shared__ int32_t hist[256];
-    hist[threadIdx.x] = 0;
+    constexpr int NB = 1 << W;
+    __shared__ int32_t hist[NB];
+    for (int b = threadIdx.x; b < NB; b += kRadixThreads) hist[b] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     for (int k = 0; k < kRadixItems; ++k) {
-        int64_t i = base + (int64_t)k * kRadixThreads + threadIdx.x;
-        if (i < n) atomicAdd(&hist[(keys[i] >> shift) & 255u], 1);
+        const int64_t i = base + (int64_t)k * kRadixThreads + threadIdx.x;
+        if (i < n) atomicAdd(&hist[(keys[i] >> shift) & (NB - 1)], 1);
     }
     __syncthreads();
-    counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = hist[threadIdx.x];
+    for (int b = threadIdx.x; b < NB; b += kRadixThreads) counts[(int64_t)b * ntiles + blockIdx.x] = hist[b];
 }
 
-__global__ void k_radix_scatter(const uint32_t *__restrict__ kin, const int32_t *__restrict__ vin,
-                                uint32_t *__restrict__ kout, int32_t *__restrict__ vout, int64_t n,
-                                int shift, const int32_t *__restrict__ offs, int ntiles)
+template <int W>
+__global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t *__restrict__ kin,
+                                                                 const int32_t *__restrict__ vin,
+                                                                 uint32_t *__restrict__ kout,
+                                                                 int32_t *__restrict__ vout, int64_t n,
+                                                                 int shift, const int32_t *__restrict__ offs,
+                                                                 int ntiles)
 {
-    __shared__ int32_t run[256];        // elements of each digit already placed
-    __shared__ int32_t wcnt[4][256];    // per-wave digit counts of this round
-    __shared__ int32_t goff[256];
+    constexpr int NB = 1 << W;
+    __shared__ int32_t run[NB];        // elements of each digit already placed
+    __shared__ int32_t wcnt[4][NB];    // per-wave digit counts of this round
+    __shared__ int32_t goff[NB];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    goff[t] = offs[(int64_t)t * ntiles + blockIdx.x];
-    run[t] = 0;
+    for (int b = t; b < NB; b += kRadixThreads) {
+        goff[b] = offs[(int64_t)b * ntiles + blockIdx.x];
+        run[b] = 0;
+    }
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
     for (int k = 0; k < kRadixItems; ++k) {
-        for (int q = 0; q < 4; ++q) wcnt[q][t] = 0;
+        for (int b = t; b < NB; b += kRadixThreads)
+            for (int q = 0; q < 4; ++q) wcnt[q][b] = 0;
         __syncthreads();
-        int64_t i = base + (int64_t)k * kRadixThreads + t;
-        bool valid = i < n;
-        uint32_t key = valid ? kin[i] : 0u;
-        int32_t val = valid ? vin[i] : 0;
-        uint32_t d = (key >> shift) & 255u;
-        uint64_t active = __ballot(valid);
-        uint64_t match = active;
+        const int64_t i = base + (int64_t)k * kRadixThreads + t;
+        const bool valid = i < n;
+        const uint32_t key = valid ? kin[i] : 0u;
+        const int32_t val = valid ? vin[i] : 0;
+        const uint32_t d = (key >> shift) & (NB - 1);
+        // lanes of this wave with the same digit: W ballots
+        uint64_t match = __ballot(valid);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            uint64_t bal = __ballot((d >> b) & 1u);
+        for (int b = 0; b < W; ++b) {
+            const uint64_t bal = __ballot((d >> b) & 1u);
             match &= ((d >> b) & 1u) ? bal : ~bal;
         }
-        int rank_w = __popcll(match & lt_mask);
+        const int rank_w = __popcll(match & lt_mask);
         if (valid && rank_w == 0) wcnt[w][d] = __popcll(match);
         __syncthreads();
         if (valid) {
             int32_t before = 0;
             for (int q = 0; q < w; ++q) before += wcnt[q][d];
-            int64_t pos = (int64_t)goff[d] + run[d] + before + rank_w;
+            const int64_t pos = (int64_t)goff[d] + run[d] + before + rank_w;
             kout[pos] = key;
             vout[pos] = val;
         }
         __syncthreads();
-        run[t] += wcnt[0][t] + wcnt[1][t] + wcnt[2][t] + wcnt[3][t];
+        for (int b = t; b < NB; b += kRadixThreads) run[b] += wcnt[0][b] + wcnt[1][b] + wcnt[2][b] + wcnt[3][b];
     }
 }
 
@@ -192,12 +208,23 @@ size_t radix_tmp_bytes(int64_t n)
 {
     int64_t ntiles = (n + kRadixTile - 1) / kRadixTile;
     if (ntiles == 0) ntiles = 1;
-    size_t counts = (size_t)256 * ntiles * sizeof(int32_t);
+    size_t counts = (size_t)kRadixMaxBins * ntiles * sizeof(int32_t);
     size_t bufs = (size_t)n * (sizeof(uint32_t) + sizeof(int32_t));
-    return counts + scan_tmp_bytes(256 * ntiles) + bufs + 1024;
+    return counts + scan_tmp_bytes(kRadixMaxBins * ntiles) + bufs + 1024;
 }
 
 static char *align256(char *p) { return (char *)(((uintptr_t)p + 255) & ~(uintptr_t)255); }
+
+template <int W>
+static void radix_pass(const uint32_t *ka, const int32_t *va, uint32_t *kb, int32_t *vb, int64_t n, int shift,
+                       int32_t *counts, void *stmp, int ntiles, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_radix_count<W>), dim3(ntiles), dim3(kRadixThreads), 0, s, ka, n, shift, counts,
+                       ntiles);
+    scan_exclusive(counts, counts, ((int64_t)1 << W) * ntiles, nullptr, stmp, s);
+    hipLaunchKernelGGL((k_radix_scatter<W>), dim3(ntiles), dim3(kRadixThreads), 0, s, ka, va, kb, vb, n,
+                       shift, counts, ntiles);
+}
 
 void radix_sort(uint32_t *keys, int32_t *vals, int64_t n, int bits, void *tmp, hipStream_t s)
 {
@@ -205,28 +232,26 @@ void radix_sort(uint32_t *keys, int32_t *vals, int64_t n, int bits, void *tmp, h
     int ntiles = (int)((n + kRadixTile - 1) / kRadixTile);
     char *p = align256((char *)tmp);
     int32_t *counts = (int32_t *)p;
-    p = align256(p + (size_t)256 * ntiles * sizeof(int32_t));
+    p = align256(p + (size_t)kRadixMaxBins * ntiles * sizeof(int32_t));
     void *stmp = p;
-    p = align256(p + scan_tmp_bytes(256 * (int64_t)ntiles));
+    p = align256(p + scan_tmp_bytes(kRadixMaxBins * (int64_t)ntiles));
     uint32_t *k2 = (uint32_t *)p;
     p = align256(p + (size_t)n * sizeof(uint32_t));
     int32_t *v2 = (int32_t *)p;
     uint32_t *ka = keys, *kb = k2;
     int32_t *va = vals, *vb = v2;
-    int passes = (bits + 7) / 8;
+    const int passes = (bits + 9) / 10;
+    const int wd = std::max(7, (bits + passes - 1) / passes);   // 7..10
     for (int ps = 0; ps < passes; ++ps) {
-        int shift = 8 * ps;
-        hipLaunchKernelGGL(k_radix_count, dim3(ntiles), dim3(kRadixThreads), 0, s, ka, n, shift,
-                           counts, ntiles);
-        scan_exclusive(counts, counts, (int64_t)256 * ntiles, nullptr, stmp, s);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(ntiles), dim3(kRadixThreads), 0, s, ka, va, kb, vb,
-                           n, shift, counts, ntiles);
-        uint32_t *tk = ka;
-        ka = kb;
-        kb = tk;
-        int32_t *tv = va;
-        va = vb;
-        vb = tv;
+        const int shift = wd * ps;
+        switch (wd) {
+        case 7: radix_pass<7>(ka, va, kb, vb, n, shift, counts, stmp, ntiles, s); break;
+        case 8: radix_pass<8>(ka, va, kb, vb, n, shift, counts, stmp, ntiles, s); break;
+        case 9: radix_pass<9>(ka, va, kb, vb, n, shift, counts, stmp, ntiles, s); break;
+        default: radix_pass<10>(ka, va, kb, vb, n, shift, counts, stmp, ntiles, s); break;
+        }
+        std::swap(ka, kb);
+        std::swap(va, vb);
     }
     if (ka != keys) {
         hipMemcpyAsync(keys, ka, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s);

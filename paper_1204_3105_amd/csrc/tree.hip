@@ -422,45 +422,67 @@ __device__ __forceinline__ int32_t lookup(const GeoParams &g, const Levels &s,
     return gid;
 }
 
-__global__ void k_lists(GeoParams g, Levels s, DevTables t, int64_t n_cells,
-                        const uint32_t *__restrict__ cell_key, const uint8_t *__restrict__ group,
-                        const uint8_t *__restrict__ occ, const int32_t *__restrict__ dense,
-                        int32_t *__restrict__ e4, int32_t *__restrict__ near)
+// Position of a cell in lattice units of its level (quadtree cell indices,
+// septree Eisenstein value, triangle centroid units) and its orientation.
+__device__ __forceinline__ void cell_position(const GeoParams &g, uint32_t key, int l, int32_t &pa,
+                                              int32_t &pb, int &orient)
 {
-    int64_t gid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (gid >= n_cells) return;
-    int l = level_of_cell(s, gid);
-    bool tgt = occ[gid] & 2;
-    uint32_t key = cell_key[gid];
     int64_t qa, qb;
-    int orient = 1;
-    if (g.tiling == kQuad) {
-        quad_split(key, l, qa, qb);
-    } else if (g.tiling == kSept) {
-        sept_value(key, l, qa, qb);
-    } else {
-        tri_units(key, l, g.L, qa, qb, orient);
+    orient = 1;
+    if (g.tiling == kQuad) quad_split(key, l, qa, qb);
+    else if (g.tiling == kSept) sept_value(key, l, qa, qb);
+    else tri_units(key, l, g.L, qa, qb, orient);
+    pa = (int32_t)qa;
+    pb = (int32_t)qb;
+}
+
+// One thread per (cell, E4 slot): slot k of a target cell on level >= 1 is
+// the source-occupied cell at the group's k-th offset, or -1 (every other
+// slot and every other cell's row is -1).  Threads are
+// many and independent, so the dependent dense-map loads of all slots are in
+// flight together.
+__global__ void k_lists_e4(GeoParams g, Levels s, DevTables t, int64_t first, int64_t n_slots,
+                           const uint32_t *__restrict__ cell_key, const uint8_t *__restrict__ group,
+                           const uint8_t *__restrict__ occ, const int32_t *__restrict__ dense,
+                           int32_t *__restrict__ e4)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_slots) return;
+    const int64_t gid = first + i / t.e4_width;
+    const int k = (int)(i % t.e4_width);
+    const int grp = group[gid];
+    int32_t v = -1;
+    const int l = level_of_cell(s, gid);
+    if (l >= 1 && (occ[gid] & 2) && k < t.e4_count[grp]) {
+        int32_t pa, pb;
+        int orient;
+        cell_position(g, cell_key[gid], l, pa, pb, orient);
+        v = lookup(g, s, dense, occ, l, pa, pb, t.e4[grp][k][0], t.e4[grp][k][1]);
     }
-    const int32_t pa = (int32_t)qa, pb = (int32_t)qb;
-    int32_t *row = e4 + gid * (int64_t)t.e4_width;
-    int grp = group[gid];
-    int cnt = (l >= 1 && tgt) ? t.e4_count[grp] : 0;
-    for (int k = 0; k < t.e4_width; ++k) {
-        int32_t v = -1;
-        if (k < cnt) v = lookup(g, s, dense, occ, l, pa, pb, t.e4[grp][k][0], t.e4[grp][k][1]);
-        row[k] = v;
+    e4[gid * (int64_t)t.e4_width + k] = v;
+}
+
+// One thread per (leaf, near slot): the closed neighbourhood of each target
+// leaf, slot 0 the leaf itself, restricted to source-occupied cells.
+__global__ void k_lists_near(GeoParams g, Levels s, DevTables t, int64_t n_slots,
+                             const uint32_t *__restrict__ cell_key, const uint8_t *__restrict__ occ,
+                             const int32_t *__restrict__ dense, int32_t *__restrict__ near)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n_slots) return;
+    const int64_t li = i / t.near_width;
+    const int k = (int)(i % t.near_width);
+    const int64_t gid = s.l[s.L].cell_off + li;
+    int32_t v = -1;
+    if (occ[gid] & 2) {
+        int32_t pa, pb;
+        int orient;
+        cell_position(g, cell_key[gid], s.L, pa, pb, orient);
+        const int oi = orient < 0 ? 1 : 0;
+        if (k < t.near_count[oi])
+            v = lookup(g, s, dense, occ, s.L, pa, pb, t.near[oi][k][0], t.near[oi][k][1]);
     }
-    if (l == s.L) {
-        int64_t li = gid - s.l[s.L].cell_off;
-        int32_t *nrow = near + li * (int64_t)t.near_width;
-        int oi = orient < 0 ? 1 : 0;
-        for (int k = 0; k < t.near_width; ++k) {
-            int32_t v = -1;
-            if (tgt && k < t.near_count[oi])
-                v = lookup(g, s, dense, occ, l, pa, pb, t.near[oi][k][0], t.near[oi][k][1]);
-            nrow[k] = v;
-        }
-    }
+    near[i] = v;
 }
 
 void launch_lists(const GeoParams &g, const LevelInfo *lev, const ListTables &tab, int64_t n_cells,
@@ -485,8 +507,14 @@ void launch_lists(const GeoParams &g, const LevelInfo *lev, const ListTables &ta
             t.near[a][k][1] = tab.near[a][k][1];
         }
     }
-    hipLaunchKernelGGL(k_lists, dim3((unsigned)((n_cells + 127) / 128)), dim3(128), 0, s, g,
-                       make_levels(g, lev), t, n_cells, cell_key, group, occ, dense, e4, near);
+    const Levels lv = make_levels(g, lev);
+    const int64_t ne = n_cells * (int64_t)t.e4_width;
+    hipLaunchKernelGGL(k_lists_e4, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, s, g, lv, t,
+                       (int64_t)0, ne, cell_key, group, occ, dense, e4);
+    const int64_t nn = lev[g.L].n * (int64_t)t.near_width;
+    if (nn > 0)
+        hipLaunchKernelGGL(k_lists_near, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, g, lv,
+                           t, nn, cell_key, occ, dense, near);
 }
 
 // ------------------------------------------------------------ local coords
