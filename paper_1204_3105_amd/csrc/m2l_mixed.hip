@@ -283,7 +283,7 @@ int mixed_setup(Plan &P)
 // slot i+1 are already in flight to registers and go to the other buffer
 // after the MFMAs, so one barrier per slot and no load on the critical path.
 template <int MT, int KB>
-__global__ __launch_bounds__(256) void k_m2l_bf16x3(const EvalJob *__restrict__ jobs, BatchMap bm)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_m2l_bf16x3(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
     constexpr int NA = MT * KB * 3 * 64;   // bf16x8 vectors of one slot's matrix
     constexpr int NR = 32 * MT;            // output rows (>= 2(p+1))
