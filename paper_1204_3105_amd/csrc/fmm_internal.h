@@ -204,6 +204,7 @@ void launch_m2l_tables(Plan &P, int pm, double *base, hipStream_t s);
 
 // m2l_mixed.hip
 size_t mixed_bytes(const Plan &P);
+int64_t plan_device_bytes(const Plan *P);
 int mixed_setup(Plan &P);
 
 // errors

@@ -140,12 +140,36 @@ __device__ int64_t key_quad(const GeoParams &g, double x, double y)
 // Eisenstein value z = a + b w -> GBT digits (least significant first) by
 // repeated division by beta.  The residue of z modulo beta is (a + 3b) mod 7
 // (w = 3 mod beta); residue -> digit k whose value w^(k-1) has that residue.
+// After the digit is removed, z conj(beta) = z (3 - 2w) is divisible by
+// 7 = beta conj(beta).  Small values (|a|, |b| < 2^27, every point inside a
+// root of up to 11 levels) divide exactly in 32-bit arithmetic by the inverse
+// of 7 mod 2^32; larger ones (far outside the root) take the 64-bit path.
 __device__ __forceinline__ int64_t gbt_encode(int64_t a, int64_t b, int ndig)
 {
     // residue r -> digit, and the digit's (a, b) value
     const int rdig[7] = {0, 1, 3, 2, 5, 6, 4};
     const int da[7] = {0, 1, 0, -1, -1, 0, 1};
     const int db[7] = {0, 0, 1, 1, 0, -1, -1};
+    const int64_t lim = (int64_t)1 << 27;
+    if (a > -lim && a < lim && b > -lim && b < lim) {
+        constexpr uint32_t kInv7 = 0xB6DB6DB7u;
+        int32_t x = (int32_t)a, y = (int32_t)b;
+        uint32_t key = 0, pw = 1;
+        for (int i = 0; i < ndig; ++i) {
+            int32_t r = (x + 3 * y) % 7;
+            if (r < 0) r += 7;
+            const int d = rdig[r];
+            x -= da[d];
+            y -= db[d];
+            const uint32_t nx = (uint32_t)(3 * x + 2 * y), ny = (uint32_t)(y - 2 * x);
+            x = (int32_t)(nx * kInv7);
+            y = (int32_t)(ny * kInv7);
+            key += (uint32_t)d * pw;
+            pw *= 7u;
+        }
+        if (x != 0 || y != 0) return -1;   // needs more than ndig digits
+        return key;
+    }
     int64_t key = 0, pw = 1;
     for (int i = 0; i < ndig; ++i) {
         int64_t r = (a + 3 * b) % 7;

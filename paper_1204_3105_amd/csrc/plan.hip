@@ -297,6 +297,8 @@ static void release(PlanImpl *P)
     if (P->own_stream && P->stream) hipStreamDestroy(P->stream);
 }
 
+int64_t plan_device_bytes(const Plan *P) { return ((const PlanImpl *)P)->device_bytes; }
+
 // ------------------------------------------------------------ rules
 static const double kQ[3] = {
     0.54691816067802259,   // quadtree 1/(1 + 2(sqrt2 - 1))
@@ -505,8 +507,12 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     int32_t *total = take<int32_t>(P, 4, &err);
     if (err) return fail(FMM_E_NOMEM, "device allocation failed (levels)");
     FMM_HIP_CHECK(hipMemsetAsync(flags, 0, sizeof(int32_t) * dense_total, s));
-    launch_mark_cells(g, P->lev, P->skey, N, 1, flags, s);
-    launch_mark_cells(g, P->lev, P->tkey, M, 2, flags, s);
+    if (same) {
+        launch_mark_cells(g, P->lev, P->skey, N, 3, flags, s);   // both occupancy bits at once
+    } else {
+        launch_mark_cells(g, P->lev, P->skey, N, 1, flags, s);
+        launch_mark_cells(g, P->lev, P->tkey, M, 2, flags, s);
+    }
     launch_flags_to_ids(flags, dense_total, s);
     int32_t *ids = flags + dense_total;
     scan_exclusive(ids, ids, dense_total, total, scan_tmp, s);

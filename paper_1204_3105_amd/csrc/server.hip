@@ -118,11 +118,12 @@ static bool plan_request(Server &S, Req *r)
         r->status = st;
         return false;
     }
-    fmm_plan_info inf;
-    fmm_plan_info_get(r->plan, &inf);
-    r->reserved = inf.device_bytes + (int64_t)(r->pts_bytes + r->tgt_bytes + r->u_bytes);
-    r->p = inf.p;
-    r->lmax = inf.lmax;
+    // Sizes straight from the plan (fmm_plan_info_get would also count the
+    // interaction pairs, which the scheduler does not need).
+    const Plan *P = (const Plan *)r->plan;
+    r->reserved = plan_device_bytes(P) + (int64_t)(r->pts_bytes + r->tgt_bytes + r->u_bytes);
+    r->p = P->p;
+    r->lmax = P->geo.L;
     return true;
 }
 

@@ -146,9 +146,16 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_count(const uint32_t *_
     for (int b = threadIdx.x; b < NB; b += kRadixThreads) hist[b] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    uint32_t kk[kRadixItems];   // all loads in flight before the first atomic
+#pragma unroll
     for (int k = 0; k < kRadixItems; ++k) {
         const int64_t i = base + (int64_t)k * kRadixThreads + threadIdx.x;
-        if (i < n) atomicAdd(&hist[(keys[i] >> shift) & (NB - 1)], 1);
+        kk[k] = i < n ? keys[i] : 0xffffffffu;
+    }
+#pragma unroll
+    for (int k = 0; k < kRadixItems; ++k) {
+        const int64_t i = base + (int64_t)k * kRadixThreads + threadIdx.x;
+        if (i < n) atomicAdd(&hist[(kk[k] >> shift) & (NB - 1)], 1);
     }
     __syncthreads();
     for (int b = threadIdx.x; b < NB; b += kRadixThreads) counts[(int64_t)b * ntiles + blockIdx.x] = hist[b];
@@ -173,14 +180,23 @@ __global__ __launch_bounds__(kRadixThreads) void k_radix_scatter(const uint32_t 
     }
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    uint32_t kk[kRadixItems];   // the tile's loads all in flight before the first round
+    int32_t vv[kRadixItems];
+#pragma unroll
+    for (int k = 0; k < kRadixItems; ++k) {
+        const int64_t i = base + (int64_t)k * kRadixThreads + t;
+        kk[k] = i < n ? kin[i] : 0u;
+        vv[k] = i < n ? vin[i] : 0;
+    }
+#pragma unroll
     for (int k = 0; k < kRadixItems; ++k) {
         for (int b = t; b < NB; b += kRadixThreads)
             for (int q = 0; q < 4; ++q) wcnt[q][b] = 0;
         __syncthreads();
         const int64_t i = base + (int64_t)k * kRadixThreads + t;
         const bool valid = i < n;
-        const uint32_t key = valid ? kin[i] : 0u;
-        const int32_t val = valid ? vin[i] : 0;
+        const uint32_t key = kk[k];
+        const int32_t val = vv[k];
         const uint32_t d = (key >> shift) & (NB - 1);
         // lanes of this wave with the same digit: W ballots
         uint64_t match = __ballot(valid);
