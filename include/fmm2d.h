@@ -164,6 +164,21 @@ const char *fmm_last_error(void);
  * q measured on GBT aggregates).  Returns -1 for bad arguments. */
 int32_t fmm_order_for_eps(fmm_tiling tiling, double eps);
 
+/* Direct sum (Sec. 2, eq. 2 evaluated term by term; the baseline the paper
+ * compares the FMM with, Sec. 9): phi[j] = sum_i u[i] Log(tgt[j] - src[i])
+ * on the principal branch, Log z = ln|z| + i Arg z with Arg in (-pi, pi]
+ * and a -0 imaginary part read as +0; a source with the target's exact
+ * coordinates is skipped.  FP64 with compensated sums, sources taken in
+ * index order.  src: n_src complex128 points; tgt: n_tgt complex128 points
+ * (may equal src); u: n_src doubles; phi: n_tgt complex128 out.  opt may be
+ * NULL (host pointers); with opt->device_pointers the pointers are device
+ * pointers and the work is ordered on opt->stream; other option fields are
+ * ignored.  Returns FMM_E_INVALID for null arrays with nonzero sizes or
+ * negative sizes, FMM_E_INVALID for a non-finite coordinate (host pointers
+ * only), FMM_E_NOMEM or FMM_E_DEVICE on device failures. */
+fmm_status fmm_direct(const double *src, int64_t n_src, const double *tgt, int64_t n_tgt,
+                      const double *u, double *phi, const fmm_options *opt);
+
 /* ------------------------------------------------------------------ serving
  * A request loop that admits independent solves by free device memory,
  * keeps their plans resident, and runs the same phase of every admitted

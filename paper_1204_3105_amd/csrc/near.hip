@@ -265,6 +265,58 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
     }
 }
 
+// Direct sum: 256 targets per workgroup (one per thread), all sources
+// staged through LDS 256 at a time in index order; Neumaier-compensated FP64
+// sums of u ln|y - x| and u Arg(y - x); a source at the target's exact
+// coordinates is skipped.
+__global__ __launch_bounds__(256) void k_direct(const double *__restrict__ src, int64_t n_src,
+                                                const double *__restrict__ tgt, int64_t n_tgt,
+                                                const double *__restrict__ u, double *__restrict__ phi)
+{
+    __shared__ double sx[256], sy[256], su[256];
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const bool ok = j < n_tgt;
+    const double y0 = ok ? tgt[2 * j] : 0.0, y1 = ok ? tgt[2 * j + 1] : 0.0;
+    double re = 0.0, rc = 0.0, im = 0.0, ic = 0.0;
+    auto add = [](double &s, double &c, double v) {   // Neumaier step
+        const double t = s + v;
+        c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
+        s = t;
+    };
+    for (int64_t base = 0; base < n_src; base += 256) {
+        __syncthreads();
+        const int64_t i = base + threadIdx.x;
+        if (i < n_src) {
+            sx[threadIdx.x] = src[2 * i];
+            sy[threadIdx.x] = src[2 * i + 1];
+            su[threadIdx.x] = u[i];
+        }
+        __syncthreads();
+        const int ns = n_src - base < 256 ? (int)(n_src - base) : 256;
+        for (int k = 0; k < ns; ++k) {
+            const double dx = y0 - sx[k], dy = y1 - sy[k];
+            const double r2 = dx * dx + dy * dy;
+            const bool live = r2 > 0.0;
+            const double lg = ln_f64(live ? r2 : 1.0);
+            const double at = atan2_f64(dy, live ? dx : 1.0);
+            add(re, rc, live ? su[k] * (0.5 * lg) : 0.0);
+            add(im, ic, live ? su[k] * at : 0.0);
+        }
+    }
+    if (ok) {
+        phi[2 * j] = re + rc;
+        phi[2 * j + 1] = im + ic;
+    }
+}
+
+void launch_direct(const double *src, int64_t n_src, const double *tgt, int64_t n_tgt, const double *u,
+                   double *phi, hipStream_t s)
+{
+    if (n_tgt <= 0) return;
+    hipLaunchKernelGGL(k_direct, dim3((unsigned)((n_tgt + 255) / 256)), dim3(256), 0, s, src, n_src, tgt,
+                       n_tgt, u, phi);
+}
+
 void batch_near_fp64(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
 {
     if (m.n <= 0 || m.pre[m.n] <= 0) return;

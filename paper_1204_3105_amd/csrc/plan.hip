@@ -16,6 +16,7 @@
 //                     disk covers the box's circumscribed disk; L as above.
 //   p = ceil(ln eps / ln q) - 1, q = max(r/R, 1/(1 + rho/r)) of the tiling.
 #include <math.h>
+#include <cmath>
 #include <string.h>
 
 #include <algorithm>
@@ -641,6 +642,55 @@ fmm_status fmm_options_default(fmm_options *opt)
 }
 
 int32_t fmm_order_for_eps(fmm_tiling tiling, double eps) { return order_for((int)tiling, eps); }
+
+fmm_status fmm_direct(const double *src, int64_t n_src, const double *tgt, int64_t n_tgt,
+                      const double *u, double *phi, const fmm_options *opt)
+{
+    g_err.clear();
+    if (n_src < 0 || n_tgt < 0) return fail(FMM_E_INVALID, "negative size");
+    if ((n_src > 0 && (!src || !u)) || (n_tgt > 0 && (!tgt || !phi)))
+        return fail(FMM_E_INVALID, "null array");
+    if (opt && opt->struct_size != sizeof(fmm_options)) return fail(FMM_E_INVALID, "bad options struct size");
+    if (n_tgt == 0) return FMM_OK;
+    const bool dev = opt && opt->device_pointers;
+    if (dev) {
+        launch_direct(src, n_src, tgt, n_tgt, u, phi, (hipStream_t)opt->stream);
+        FMM_HIP_CHECK(hipGetLastError());
+        return FMM_OK;
+    }
+    for (int64_t i = 0; i < 2 * n_src; ++i)
+        if (!std::isfinite(src[i])) return fail(FMM_E_INVALID, "non-finite coordinate in the input");
+    for (int64_t i = 0; i < 2 * n_tgt; ++i)
+        if (!std::isfinite(tgt[i])) return fail(FMM_E_INVALID, "non-finite coordinate in the input");
+    hipStream_t s;
+    FMM_HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    int err = 0;
+    const size_t bs = 16 * (size_t)std::max<int64_t>(n_src, 1), bt = 16 * (size_t)n_tgt;
+    const size_t bu = 8 * (size_t)std::max<int64_t>(n_src, 1);
+    double *ds = (double *)dev_alloc(bs, &err), *dt = (double *)dev_alloc(bt, &err);
+    double *du = (double *)dev_alloc(bu, &err), *dp = (double *)dev_alloc(bt, &err);
+    fmm_status st = FMM_OK;
+    if (err) {
+        st = fail(FMM_E_NOMEM, "device allocation failed (direct)");
+    } else if (hipMemcpyAsync(ds, src, 16 * n_src, hipMemcpyHostToDevice, s) != hipSuccess ||
+               hipMemcpyAsync(dt, tgt, bt, hipMemcpyHostToDevice, s) != hipSuccess ||
+               hipMemcpyAsync(du, u, 8 * n_src, hipMemcpyHostToDevice, s) != hipSuccess) {
+        st = fail(FMM_E_DEVICE, "host to device copy failed (direct)");
+    } else {
+        launch_direct(ds, n_src, dt, n_tgt, du, dp, s);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(phi, dp, bt, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            st = fail(FMM_E_DEVICE, "direct sum failed");
+    }
+    hipStreamSynchronize(s);
+    dev_free(ds, bs);
+    dev_free(dt, bt);
+    dev_free(du, bu);
+    dev_free(dp, bt);
+    hipStreamDestroy(s);
+    return st;
+}
 
 fmm_status fmm_plan(fmm_tiling tiling, const double *src, int64_t n_src, const double *tgt,
                     int64_t n_tgt, double eps, const fmm_options *opt, fmm_plan_t *out)

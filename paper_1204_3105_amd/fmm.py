@@ -66,7 +66,7 @@ class Result(C.Structure):
 EXPORTED = ["fmm_options_default", "fmm_plan", "fmm_eval", "fmm_plan_info_get",
             "fmm_plan_export_points", "fmm_plan_export_level", "fmm_plan_destroy",
             "fmm_last_error", "fmm_order_for_eps", "fmm_server_create", "fmm_submit",
-            "fmm_poll", "fmm_server_drain", "fmm_server_destroy"]
+            "fmm_poll", "fmm_server_drain", "fmm_server_destroy", "fmm_direct"]
 
 _lib = None
 
@@ -110,6 +110,8 @@ def lib():
     L.fmm_last_error.restype = C.c_char_p
     L.fmm_order_for_eps.argtypes = [C.c_int, C.c_double]
     L.fmm_order_for_eps.restype = C.c_int32
+    L.fmm_direct.argtypes = [P, C.c_int64, P, C.c_int64, P, P, C.POINTER(Options)]
+    L.fmm_direct.restype = C.c_int
     L.fmm_server_create.argtypes = [C.POINTER(ServerOptions), C.POINTER(P)]
     L.fmm_server_create.restype = C.c_int
     L.fmm_submit.argtypes = [P, C.POINTER(Request), C.POINTER(C.c_uint64)]
@@ -302,6 +304,54 @@ def solve(tiling, xs, ys, u, xt=None, yt=None, eps=1e-6, **kw):
     """One-shot host solve: plan + eval + destroy."""
     with Plan(tiling, xs, ys, xt, yt, eps, **kw) as p:
         return p.eval(u)
+
+
+def direct(xs, ys, u, xt=None, yt=None, *, src=None, tgt=None, out=None, stream=None):
+    """Direct sum of u_i Log(y_j - x_i) on the GPU (fmm_direct in the C ABI).
+
+    Host mode: direct(xs, ys, u, xt, yt) with numpy arrays (targets default
+    to the sources) returns a complex128 ndarray.  Device mode:
+    direct(None, None, u, src=tensor, tgt=tensor) with complex128 CUDA
+    tensors returns (or fills) a complex128 CUDA tensor, ordered on `stream`
+    (default: torch's current stream)."""
+    L = lib()
+    opt = Options()
+    _check(L.fmm_options_default(C.byref(opt)))
+    if src is not None and _is_torch(src) and src.is_cuda:
+        import torch
+        s = src.contiguous()
+        t = s if (tgt is None or tgt is src) else tgt.contiguous()
+        for a in (s, t):
+            if a.dtype != torch.complex128:
+                raise TypeError("device points must be complex128")
+        u = u.contiguous()
+        if u.dtype != torch.float64 or not u.is_cuda or u.numel() != s.numel():
+            raise TypeError("u must be a float64 CUDA tensor of n_src elements")
+        if out is None:
+            out = torch.empty(t.numel(), dtype=torch.complex128, device=s.device)
+        opt.device_pointers = 1
+        st = stream if stream is not None else torch.cuda.current_stream()
+        opt.stream = C.c_void_p(st.cuda_stream)
+        _check(L.fmm_direct(C.c_void_p(s.data_ptr()), s.numel(), C.c_void_p(t.data_ptr()), t.numel(),
+                            C.c_void_p(u.data_ptr()), C.c_void_p(out.data_ptr()), C.byref(opt)))
+        return out
+    s = _points_host(src) if src is not None else _points_host(xs, ys)
+    if tgt is not None:
+        t = _points_host(tgt)
+    elif xt is not None:
+        t = _points_host(xt, yt)
+    else:
+        t = s
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    ns, nt = len(s) // 2, len(t) // 2
+    if len(u) != ns:
+        raise ValueError("u must have n_src elements")
+    res = np.empty(nt, dtype=np.complex128) if out is None else out
+    _check(L.fmm_direct(C.c_void_p(s.ctypes.data) if ns else None, ns,
+                        C.c_void_p(t.ctypes.data) if nt else None, nt,
+                        C.c_void_p(u.ctypes.data) if ns else None,
+                        C.c_void_p(res.ctypes.data) if nt else None, C.byref(opt)))
+    return res
 
 
 class Server:

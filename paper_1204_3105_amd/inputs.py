@@ -125,6 +125,43 @@ def serving_stream(n_requests: int, seed: int, rate: float, n_lo: float = 1e3, n
     return out
 
 
+def polygon_points(g: np.random.Generator, cx, cy, n_sides, radius, rotation, counts):
+    """Uniform points in regular polygons by the point picking of Sec. 9.
+
+    Cell c is the regular n_sides[c]-gon with centre (cx[c], cy[c]),
+    circumradius radius[c] and its first vertex at angle rotation[c]; it gets
+    counts[c] points.  The polygon is cut into n isosceles triangles (centre
+    and one edge); each triangle's two halves (split along its altitude) fit
+    together into an s/2 x a rectangle (s the edge, a the apothem).  A point
+    (x, y) uniform in the rectangle, folded back onto the half-triangle it
+    lies in, is uniform in the triangle, and a third uniform z picks the
+    triangle.  Draw order: x, y, z for all points of all cells.  Returns the
+    (x, y) arrays, cell after cell."""
+    cx, cy = np.asarray(cx, dtype=np.float64), np.asarray(cy, dtype=np.float64)
+    n_sides = np.broadcast_to(np.asarray(n_sides, dtype=np.int64), cx.shape)
+    radius = np.broadcast_to(np.asarray(radius, dtype=np.float64), cx.shape)
+    rotation = np.broadcast_to(np.asarray(rotation, dtype=np.float64), cx.shape)
+    counts = np.broadcast_to(np.asarray(counts, dtype=np.int64), cx.shape)
+    cell = np.repeat(np.arange(len(cx)), counts)
+    total = len(cell)
+    x, y, z = g.random(total), g.random(total), g.random(total)
+    n = n_sides[cell]
+    half = np.pi / n
+    s2 = radius[cell] * np.sin(half)          # half the edge
+    a = radius[cell] * np.cos(half)           # apothem
+    px, py = x * s2, y * a                    # uniform in the rectangle [0, s/2] x [0, a]
+    # Local frame of the triangle: centre at 0, its edge's midpoint at (0, a).
+    # Above the diagonal from (0, 0) to (s/2, a): the right half as it is;
+    # below it: reflected onto the left half.
+    below = py * s2 < px * a
+    lx = np.where(below, px - s2, px)
+    ly = np.where(below, a - py, py)
+    k = np.minimum((z * n).astype(np.int64), n - 1)
+    th = rotation[cell] + half + 2.0 * np.pi * k / n   # direction of triangle k's apothem
+    ct, st = np.cos(th), np.sin(th)
+    return cx[cell] + ly * ct + lx * st, cy[cell] + ly * st - lx * ct
+
+
 def subsample(n: int, k: int, seed: int) -> np.ndarray:
     """k distinct sorted indices out of n (k >= n gives all)."""
     if k >= n:

@@ -76,3 +76,30 @@ def test_server_option_validation(F):
     o.hbm_budget_bytes = 1 << 20
     o.max_inflight = 0
     assert lib.fmm_server_create(C.byref(o), C.byref(s)) == 1
+
+
+def test_direct_validation(F):
+    lib = F.lib()
+    o = F.Options()
+    assert lib.fmm_options_default(C.byref(o)) == 0
+    pts = (C.c_double * 4)(0.1, 0.2, 0.3, 0.4)
+    u = (C.c_double * 2)(1.0, -1.0)
+    phi = (C.c_double * 4)()
+    # negative sizes, null arrays, a bad options struct: rejected before any device call
+    assert lib.fmm_direct(pts, -1, pts, 2, u, phi, C.byref(o)) == 1
+    assert lib.fmm_direct(pts, 2, pts, -2, u, phi, C.byref(o)) == 1
+    assert lib.fmm_direct(None, 2, pts, 2, u, phi, C.byref(o)) == 1
+    assert lib.fmm_direct(pts, 2, pts, 2, None, phi, C.byref(o)) == 1
+    assert lib.fmm_direct(pts, 2, None, 2, u, phi, C.byref(o)) == 1
+    assert lib.fmm_direct(pts, 2, pts, 2, u, None, C.byref(o)) == 1
+    assert b"null" in lib.fmm_last_error()
+    bad = (C.c_double * 4)(0.1, float("nan"), 0.3, 0.4)
+    assert lib.fmm_direct(bad, 2, pts, 2, u, phi, None) == 1
+    assert b"finite" in lib.fmm_last_error()
+    assert lib.fmm_direct(pts, 2, bad, 2, u, phi, None) == 1
+    o2 = F.Options()
+    lib.fmm_options_default(C.byref(o2))
+    o2.struct_size = 3
+    assert lib.fmm_direct(pts, 2, pts, 2, u, phi, C.byref(o2)) == 1
+    # no targets: nothing to do, no device needed
+    assert lib.fmm_direct(pts, 2, None, 0, u, None, None) == 0
