@@ -205,8 +205,11 @@ void launch_m2l_tables(Plan &P, int pm, double *base, hipStream_t s);
 // m2l_mixed.hip
 size_t mixed_bytes(const Plan &P);
 int64_t plan_device_bytes(const Plan *P);
+// Direct sum: slices of the sources per target block (direct_slices), with
+// partial sums in part (slices * n_tgt complex128; unused for one slice).
+int direct_slices(int64_t n_src, int64_t n_tgt);
 void launch_direct(const double *src, int64_t n_src, const double *tgt, int64_t n_tgt, const double *u,
-                   double *phi, hipStream_t s);
+                   double *phi, double *part, int slices, hipStream_t s);
 int mixed_setup(Plan &P);
 
 // errors

@@ -9,6 +9,8 @@
 // the near sums in sorted target order and runs beside the far-field passes;
 // L2P then adds the leaf's local expansion (Greengard-Rokhlin evaluation of
 // sum_m b~_m ((y - c)/ell)^m, Horner) and writes Phi in the caller's order.
+#include <algorithm>
+
 #include "eval.h"
 
 namespace fmm {
@@ -265,56 +267,99 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
     }
 }
 
-// Direct sum: 256 targets per workgroup (one per thread), all sources
-// staged through LDS 256 at a time in index order; Neumaier-compensated FP64
-// sums of u ln|y - x| and u Arg(y - x); a source at the target's exact
-// coordinates is skipped.
+// Direct sum over a grid of (256-target block, source slice): each thread
+// sums one target over its block's slice of the sources, staged through LDS
+// 256 at a time in index order, and writes the slice's partial sum (with
+// one slice, Phi itself).  Pairs are taken eight at a time: their terms are
+// added plainly, then the group is Kahan-added to the running sums.  A
+// source at the target's exact coordinates is skipped; the padding sources
+// have zero strength and sit far away.
 __global__ __launch_bounds__(256) void k_direct(const double *__restrict__ src, int64_t n_src,
                                                 const double *__restrict__ tgt, int64_t n_tgt,
-                                                const double *__restrict__ u, double *__restrict__ phi)
+                                                const double *__restrict__ u, int64_t slice,
+                                                double *__restrict__ out)
 {
     __shared__ double sx[256], sy[256], su[256];
     const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     const bool ok = j < n_tgt;
     const double y0 = ok ? tgt[2 * j] : 0.0, y1 = ok ? tgt[2 * j + 1] : 0.0;
+    const int64_t s0 = blockIdx.y * slice;
+    const int64_t s1 = min(n_src, s0 + slice);
     double re = 0.0, rc = 0.0, im = 0.0, ic = 0.0;
-    auto add = [](double &s, double &c, double v) {   // Neumaier step
-        const double t = s + v;
-        c += fabs(s) >= fabs(v) ? (s - t) + v : (v - t) + s;
-        s = t;
-    };
-    for (int64_t base = 0; base < n_src; base += 256) {
+    for (int64_t base = s0; base < s1; base += 256) {
         __syncthreads();
         const int64_t i = base + threadIdx.x;
-        if (i < n_src) {
-            sx[threadIdx.x] = src[2 * i];
-            sy[threadIdx.x] = src[2 * i + 1];
-            su[threadIdx.x] = u[i];
-        }
+        const bool in = i < s1;
+        sx[threadIdx.x] = in ? src[2 * i] : 1e100;
+        sy[threadIdx.x] = in ? src[2 * i + 1] : 1e100;
+        su[threadIdx.x] = in ? u[i] : 0.0;
         __syncthreads();
-        const int ns = n_src - base < 256 ? (int)(n_src - base) : 256;
-        for (int k = 0; k < ns; ++k) {
-            const double dx = y0 - sx[k], dy = y1 - sy[k];
-            const double r2 = dx * dx + dy * dy;
-            const bool live = r2 > 0.0;
-            const double lg = ln_f64(live ? r2 : 1.0);
-            const double at = atan2_f64(dy, live ? dx : 1.0);
-            add(re, rc, live ? su[k] * (0.5 * lg) : 0.0);
-            add(im, ic, live ? su[k] * at : 0.0);
+        const int ns = (int)min((int64_t)256, (s1 - base + 7) & ~(int64_t)7);
+        for (int k = 0; k < ns; k += 8) {
+            double pr = 0.0, pi = 0.0;
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk) {
+                const double dx = y0 - sx[k + kk], dy = y1 - sy[k + kk];
+                const double r2 = dx * dx + dy * dy;
+                const bool live = r2 > 0.0;
+                const double w = live ? su[k + kk] : 0.0;
+                pr = fma(0.5 * w, ln_f64(live ? r2 : 1.0), pr);
+                pi = fma(w, atan2_f64(dy, live ? dx : 1.0), pi);
+            }
+            const double yr = pr - rc, tr = re + yr;
+            rc = (tr - re) - yr;
+            re = tr;
+            const double yi = pi - ic, ti = im + yi;
+            ic = (ti - im) - yi;
+            im = ti;
         }
     }
     if (ok) {
-        phi[2 * j] = re + rc;
-        phi[2 * j + 1] = im + ic;
+        double *o = out + 2 * (blockIdx.y * n_tgt + j);
+        o[0] = re - rc;
+        o[1] = im - ic;
     }
 }
 
+// Phi[j] = the slices' partial sums for target j, added in slice order
+// (Neumaier).
+__global__ __launch_bounds__(256) void k_direct_reduce(const double *__restrict__ part, int64_t n_tgt,
+                                                       int slices, double *__restrict__ phi)
+{
+    const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j >= n_tgt) return;
+    double s[2] = {0.0, 0.0}, c[2] = {0.0, 0.0};
+    for (int q = 0; q < slices; ++q)
+        for (int h = 0; h < 2; ++h) {
+            const double v = part[2 * (q * n_tgt + j) + h];
+            const double t = s[h] + v;
+            c[h] += fabs(s[h]) >= fabs(v) ? (s[h] - t) + v : (v - t) + s[h];
+            s[h] = t;
+        }
+    phi[2 * j] = s[0] + c[0];
+    phi[2 * j + 1] = s[1] + c[1];
+}
+
+int direct_slices(int64_t n_src, int64_t n_tgt)
+{
+    // Enough (block, slice) pairs for about eight waves per SIMD, slices of
+    // at least 32 sources, at most 1024 slices.
+    const int64_t lanes = ((n_tgt + 255) / 256) * 256;
+    int64_t want = (256 * 4 * 8 * 64 + lanes - 1) / lanes;
+    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>(1024, (n_src + 31) / 32));
+    return (int)std::max<int64_t>(1, std::min(want, cap));
+}
+
 void launch_direct(const double *src, int64_t n_src, const double *tgt, int64_t n_tgt, const double *u,
-                   double *phi, hipStream_t s)
+                   double *phi, double *part, int slices, hipStream_t s)
 {
     if (n_tgt <= 0) return;
-    hipLaunchKernelGGL(k_direct, dim3((unsigned)((n_tgt + 255) / 256)), dim3(256), 0, s, src, n_src, tgt,
-                       n_tgt, u, phi);
+    const int64_t slice = slices > 1 ? (n_src + slices - 1) / slices : std::max<int64_t>(n_src, 1);
+    const unsigned tb = (unsigned)((n_tgt + 255) / 256);
+    hipLaunchKernelGGL(k_direct, dim3(tb, (unsigned)slices), dim3(256), 0, s, src, n_src, tgt, n_tgt, u, slice,
+                       slices > 1 ? part : phi);
+    if (slices > 1)
+        hipLaunchKernelGGL(k_direct_reduce, dim3(tb), dim3(256), 0, s, part, n_tgt, slices, phi);
 }
 
 void batch_near_fp64(const EvalJob *jobs, const BatchMap &m, hipStream_t s)

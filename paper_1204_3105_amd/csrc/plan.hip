@@ -298,6 +298,23 @@ static void release(PlanImpl *P)
     if (P->own_stream && P->stream) hipStreamDestroy(P->stream);
 }
 
+// Hand a block used on stream s back to the pool behind a fence recorded on
+// s (or after waiting for s if no event can be made).
+static void put_fenced(void *p, size_t bytes, hipStream_t s)
+{
+    auto fence = std::make_shared<Fence>();
+    if (hipEventCreateWithFlags(&fence->ev, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(fence->ev, s) != hipSuccess) {
+        (void)hipGetLastError();
+        fence.reset();
+        hipStreamSynchronize(s);
+    } else {
+        std::lock_guard<std::mutex> lk(g_pool_mu);
+        fence->id = ++g_fence_id;
+    }
+    pool_put(p, bytes, fence);
+}
+
 int64_t plan_device_bytes(const Plan *P) { return ((const PlanImpl *)P)->device_bytes; }
 
 // ------------------------------------------------------------ rules
@@ -653,9 +670,20 @@ fmm_status fmm_direct(const double *src, int64_t n_src, const double *tgt, int64
     if (opt && opt->struct_size != sizeof(fmm_options)) return fail(FMM_E_INVALID, "bad options struct size");
     if (n_tgt == 0) return FMM_OK;
     const bool dev = opt && opt->device_pointers;
+    const int slices = direct_slices(n_src, n_tgt);
+    const size_t bpart = slices > 1 ? 16 * (size_t)slices * (size_t)n_tgt : 0;
     if (dev) {
-        launch_direct(src, n_src, tgt, n_tgt, u, phi, (hipStream_t)opt->stream);
-        FMM_HIP_CHECK(hipGetLastError());
+        // The partial sums live in a pool block used in stream order and
+        // handed back behind a fence, so the call does not wait.
+        hipStream_t s = (hipStream_t)opt->stream;
+        int err = 0;
+        std::vector<uint64_t> waited;
+        double *part = bpart ? (double *)dev_alloc(bpart, &err, &waited, s) : nullptr;
+        if (err) return fail(FMM_E_NOMEM, "device allocation failed (direct)");
+        launch_direct(src, n_src, tgt, n_tgt, u, phi, part, slices, s);
+        const hipError_t e = hipGetLastError();
+        if (part) put_fenced(part, bpart, s);
+        FMM_HIP_CHECK(e);
         return FMM_OK;
     }
     for (int64_t i = 0; i < 2 * n_src; ++i)
@@ -669,6 +697,7 @@ fmm_status fmm_direct(const double *src, int64_t n_src, const double *tgt, int64
     const size_t bu = 8 * (size_t)std::max<int64_t>(n_src, 1);
     double *ds = (double *)dev_alloc(bs, &err), *dt = (double *)dev_alloc(bt, &err);
     double *du = (double *)dev_alloc(bu, &err), *dp = (double *)dev_alloc(bt, &err);
+    double *part = bpart ? (double *)dev_alloc(bpart, &err) : nullptr;
     fmm_status st = FMM_OK;
     if (err) {
         st = fail(FMM_E_NOMEM, "device allocation failed (direct)");
@@ -677,7 +706,7 @@ fmm_status fmm_direct(const double *src, int64_t n_src, const double *tgt, int64
                hipMemcpyAsync(du, u, 8 * n_src, hipMemcpyHostToDevice, s) != hipSuccess) {
         st = fail(FMM_E_DEVICE, "host to device copy failed (direct)");
     } else {
-        launch_direct(ds, n_src, dt, n_tgt, du, dp, s);
+        launch_direct(ds, n_src, dt, n_tgt, du, dp, part, slices, s);
         if (hipGetLastError() != hipSuccess ||
             hipMemcpyAsync(phi, dp, bt, hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
@@ -688,6 +717,7 @@ fmm_status fmm_direct(const double *src, int64_t n_src, const double *tgt, int64
     dev_free(dt, bt);
     dev_free(du, bu);
     dev_free(dp, bt);
+    dev_free(part, bpart);
     hipStreamDestroy(s);
     return st;
 }
