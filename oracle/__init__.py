@@ -105,6 +105,10 @@ def lib():
         L.orc_fmm.restype = C.c_int32
         L.orc_fmm.argtypes = [_G, C.c_int32, C.c_int64, _D, _D, _D, C.c_int64, _D, _D, _D,
                               C.c_int32, _D]
+        L.orc_fmm_field.restype = C.c_int32
+        L.orc_fmm_field.argtypes = [_G, C.c_int32, C.c_int64, _D, _D, _D, C.c_int64, _D, _D, _D, _D,
+                                    C.c_int32, _D]
+        L.orc_direct_field.argtypes = [C.c_int64, _D, _D, _D, C.c_int64, _D, _D, _D, C.c_int32]
         L.orc_upward_level.restype = C.c_int64
         L.orc_upward_level.argtypes = [_G, C.c_int32, C.c_int64, _D, _D, _D, C.c_int32, _I64, _D]
         _lib = L
@@ -303,6 +307,31 @@ def fmm(g: Geom, p: int, xs, ys, u, xt, yt, nthreads=0, times=None) -> np.ndarra
         raise ValueError("bad arguments (rc=%d)" % rc)
     if times is not None:
         times[:] = list(tbuf)
+    return _cplx_out(out)
+
+
+def fmm_field(g: Geom, p: int, xs, ys, u, xt, yt, nthreads=0):
+    """Full FP64 FMM returning (Phi, Phi') in target order; Phi' is the
+    derivative in y (the local expansion's derivative plus the near sum of
+    u_i / (y - x_i))."""
+    xs, ys, u, xt, yt = map(_d, (xs, ys, u, xt, yt))
+    out = np.zeros(2 * len(xt))
+    fld = np.zeros(2 * len(xt))
+    rc = lib().orc_fmm_field(C.byref(g), int(p), len(xs), _pd(xs), _pd(ys), _pd(u), len(xt), _pd(xt),
+                             _pd(yt), _pd(out), _pd(fld), int(nthreads), None)
+    if rc == 2:
+        raise ValueError("point outside the root")
+    if rc:
+        raise ValueError("bad arguments (rc=%d)" % rc)
+    return _cplx_out(out), _cplx_out(fld)
+
+
+def direct_field(xs, ys, u, xt, yt, nthreads=0) -> np.ndarray:
+    """sum_i u_i / (y_j - x_i), coincident pairs skipped."""
+    xs, ys, u, xt, yt = map(_d, (xs, ys, u, xt, yt))
+    out = np.zeros(2 * len(xt))
+    lib().orc_direct_field(len(xs), _pd(xs), _pd(ys), _pd(u), len(xt), _pd(xt), _pd(yt), _pd(out),
+                           int(nthreads))
     return _cplx_out(out)
 
 

@@ -729,6 +729,18 @@ static cplx op_l2p(int p, const cplx *b, cplx c, cplx y)
     return s;
 }
 
+/* Derivative of the local expansion at y: sum_{l>=1} l b_l (y - c)^(l-1)
+ * (the field output, d/dy of the L2P sum). */
+static cplx op_l2p_deriv(int p, const cplx *b, cplx c, cplx y)
+{
+    cplx w = y - c, pw = 1.0, s = 0.0;
+    for (int l = 1; l <= p; ++l) {
+        s += (double)l * b[l] * pw;
+        pw *= w;
+    }
+    return s;
+}
+
 /* Evaluate a multipole expansion at a point (test use). */
 static cplx op_mpole_eval(int p, const cplx *a, cplx c, cplx y)
 {
@@ -842,6 +854,26 @@ void orc_direct_principal(int64_t ns, const double *xs, const double *ys, const 
         }
         phi[2 * j] = re.s + re.c;
         phi[2 * j + 1] = im.s + im.c;
+    }
+}
+
+/* Field Phi'(y_j) = sum_i u_i / (y_j - x_i) (the derivative of eq. 2 in
+ * y), coincident pairs skipped, compensated sums. */
+void orc_direct_field(int64_t ns, const double *xs, const double *ys, const double *u, int64_t nt,
+                      const double *xt, const double *yt, double *out, int32_t nthreads)
+{
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < nt; ++j) {
+        nsum re = {0, 0}, im = {0, 0};
+        for (int64_t i = 0; i < ns; ++i) {
+            if (xs[i] == xt[j] && ys[i] == yt[j]) continue;
+            cplx q = u[i] / CMPLX(xt[j] - xs[i], yt[j] - ys[i]);
+            nadd(&re, creal(q));
+            nadd(&im, cimag(q));
+        }
+        out[2 * j] = re.s + re.c;
+        out[2 * j + 1] = im.s + im.c;
     }
 }
 
@@ -999,9 +1031,9 @@ static int64_t find_cell(const cells *c, int64_t key)
  * doubles) receives the wall time of: keys+tree, P2M+M2M, M2L, L2L,
  * L2P+P2P, total.  Returns 0, 1 on bad arguments, 2 if a point lies
  * outside the root. */
-int32_t orc_fmm(const orc_geom *g, int32_t p, int64_t ns, const double *xs, const double *ys,
-                const double *u, int64_t nt, const double *xt, const double *yt, double *phi,
-                int32_t nthreads, double *times)
+static int32_t fmm_run(const orc_geom *g, int32_t p, int64_t ns, const double *xs, const double *ys,
+                       const double *u, int64_t nt, const double *xt, const double *yt, double *phi,
+                       double *field, int32_t nthreads, double *times)
 {
     if (p < 1 || p > 60 || g->L < 0 || ns < 0 || nt < 0) return 1;
     set_threads(nthreads);
@@ -1117,7 +1149,7 @@ int32_t orc_fmm(const orc_geom *g, int32_t p, int64_t ns, const double *xs, cons
             int64_t j = tk[m].idx;
             cplx y = CMPLX(xt[j], yt[j]);
             cplx far = op_l2p(p, lc[L] + c * P1, CMPLX(cx, cy), y);
-            nsum re = {0, 0}, im = {0, 0};
+            nsum re = {0, 0}, im = {0, 0}, fre = {0, 0}, fim = {0, 0};
             for (int q = 0; q < nn; ++q) {
                 int64_t s = find_cell(&sc[L], nb[q]);
                 if (s < 0) continue;
@@ -1127,10 +1159,20 @@ int32_t orc_fmm(const orc_geom *g, int32_t p, int64_t ns, const double *xs, cons
                     cplx lg = log_canon(CMPLX(xt[j] - xs[i], yt[j] - ys[i]));
                     nadd(&re, u[i] * creal(lg));
                     nadd(&im, u[i] * cimag(lg));
+                    if (field) {
+                        cplx fq = u[i] / CMPLX(xt[j] - xs[i], yt[j] - ys[i]);
+                        nadd(&fre, creal(fq));
+                        nadd(&fim, cimag(fq));
+                    }
                 }
             }
             phi[2 * j] = creal(far) + (re.s + re.c);
             phi[2 * j + 1] = cimag(far) + (im.s + im.c);
+            if (field) {
+                cplx fd = op_l2p_deriv(p, lc[L] + c * P1, CMPLX(cx, cy), y);
+                field[2 * j] = creal(fd) + (fre.s + fre.c);
+                field[2 * j + 1] = cimag(fd) + (fim.s + fim.c);
+            }
         }
     }
     double t5 = now_s();
@@ -1158,6 +1200,23 @@ int32_t orc_fmm(const orc_geom *g, int32_t p, int64_t ns, const double *xs, cons
     free(sidx);
     free(bt);
     return 0;
+}
+
+int32_t orc_fmm(const orc_geom *g, int32_t p, int64_t ns, const double *xs, const double *ys,
+                const double *u, int64_t nt, const double *xt, const double *yt, double *phi,
+                int32_t nthreads, double *times)
+{
+    return fmm_run(g, p, ns, xs, ys, u, nt, xt, yt, phi, NULL, nthreads, times);
+}
+
+/* As orc_fmm, and the field Phi'(y_j) (2*nt interleaved, caller's order):
+ * the derivative of the leaf's local expansion plus sum u_i / (y_j - x_i)
+ * over the same near sources. */
+int32_t orc_fmm_field(const orc_geom *g, int32_t p, int64_t ns, const double *xs, const double *ys,
+                      const double *u, int64_t nt, const double *xt, const double *yt, double *phi,
+                      double *field, int32_t nthreads, double *times)
+{
+    return fmm_run(g, p, ns, xs, ys, u, nt, xt, yt, phi, field, nthreads, times);
 }
 
 /* Multipole coefficients of every source-occupied cell at level l after the
