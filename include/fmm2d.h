@@ -131,6 +131,16 @@ fmm_status fmm_plan(fmm_tiling tiling, const double *src, int64_t n_src, const d
  * Allocates nothing.  n_src = 0 gives Phi = 0. */
 fmm_status fmm_eval(fmm_plan_t plan, const double *u, double *phi);
 
+/* As fmm_eval, and also the field Phi'(y_j) = sum_i u_i / (y_j - x_i), the
+ * derivative of eq. 2 in y (branch-free): the derivative of each target
+ * leaf's local expansion plus the near-field terms u_i / (y_j - x_i) over the
+ * same near lists, coincident pairs skipped (same precision policy as the
+ * potential).  field: 2*n_tgt doubles (complex128, caller's target order),
+ * host or device like phi.  The plan takes 16 B per target more on the first
+ * call.  Errors as fmm_eval; FMM_E_NOMEM if the field buffers cannot be
+ * allocated. */
+fmm_status fmm_eval_field(fmm_plan_t plan, const double *u, double *phi, double *field);
+
 /* Summary of a plan.  info->n_cells holds lmax+1 valid entries. */
 fmm_status fmm_plan_info_get(fmm_plan_t plan, fmm_plan_info *info);
 

@@ -52,6 +52,8 @@ struct BatchMap {
     int16_t job[kMaxBatch];       // job index of each entry
     int8_t aux[kMaxBatch];        // phase argument (level) of each entry
     double *phi_override;         // single-job output redirect (or null)
+    double *field_override;       // single-job field output, caller's order (or null: no field)
+    double *nfield;               // single-job near-field sums of the field, sorted order
 };
 
 __device__ __forceinline__ int batch_entry(const BatchMap &m, int64_t item)
@@ -108,7 +110,11 @@ EvalJob make_job(const Plan &P);
 // pass, M2L, L2L and the whole evaluation (recorded on s); ev[4]: fork to
 // the side stream, ev[5..6]: start and end of the P2P near field there.
 hipStream_t side_stream();   // per-device stream for the near field
+// field_single / nfield_single (a batch of one only): also evaluate the
+// field Phi' into field_single, with nfield_single (2 n_tgt doubles) for the
+// near-field part.
 void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_single, hipStream_t s,
-               hipStream_t side, hipEvent_t *ev);
+               hipStream_t side, hipEvent_t *ev, double *field_single = nullptr,
+               double *nfield_single = nullptr);
 
 }  // namespace fmm

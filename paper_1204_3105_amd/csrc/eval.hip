@@ -100,6 +100,7 @@ struct Launcher {
     const EvalJob *jobs;
     hipStream_t s;
     double *phi_single;
+    double *field_single, *nfield_single;
     BatchMap m;
     template <typename F>
     void add(int job, int aux, int64_t items, F &&flush)
@@ -119,6 +120,8 @@ struct Launcher {
         m.n = 0;
         m.pre[0] = 0;
         m.phi_override = phi_single;
+        m.field_override = field_single;
+        m.nfield = nfield_single;
     }
 };
 
@@ -140,9 +143,11 @@ hipStream_t side_stream()
 }
 
 void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_single, hipStream_t s,
-               hipStream_t side, hipEvent_t *ev)
+               hipStream_t side, hipEvent_t *ev, double *field_single, double *nfield_single)
 {
-    Launcher Lc{jobs_dev, s, n == 1 ? phi_single : nullptr, {}};
+    if (n != 1 || !nfield_single) field_single = nfield_single = nullptr;
+    if (!field_single) nfield_single = nullptr;
+    Launcher Lc{jobs_dev, s, n == 1 ? phi_single : nullptr, field_single, nfield_single, {}};
     Lc.reset();
     auto go = [&](auto &&launch) {
         if (Lc.m.n > 0) launch(Lc.m);
@@ -167,7 +172,7 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
         hipStreamWaitEvent(side, ev[4], 0);
         hipEventRecord(ev[5], side);
         {
-            Launcher Ls{jobs_dev, side, n == 1 ? phi_single : nullptr, {}};
+            Launcher Ls{jobs_dev, side, n == 1 ? phi_single : nullptr, field_single, nfield_single, {}};
             Ls.reset();
             auto f = [&](const BatchMap &m) { batch_near_fp64(jobs_dev, m, side); };
             for (int i = 0; i < n; ++i)

@@ -106,13 +106,18 @@ __device__ __forceinline__ double atan2_f64(double y, double x)
 // 8, at least 8, padded with zero-strength sources far away); the groups'
 // partial sums are added in group order.  Only slot 0, the leaf itself, can
 // hold a source at the target's exact position (equal points share a key),
-// so only rounds that include it test for zero separation.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_near_fp64(const EvalJob *__restrict__ jobs, BatchMap bm)
+// so only rounds that include it test for zero separation.  With FIELD the
+// kernel also sums u / (y - x) = u (dx - i dy) / r^2 into the field's near
+// sums (bm.nfield).
+template <bool FIELD>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 3 : 5, 8))) void k_near_fp64(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
-    __shared__ double shx[kNearSlots * 9], shy[kNearSlots * 9], shu[kNearSlots * 9];
+    constexpr int kStage = kNearSlots * 9;   // g (cl + 1) <= 117 for every g
+    __shared__ double shbuf[3 * kStage];
     __shared__ int32_t cbeg[kNearSlots], cend[kNearSlots], cum[kNearSlots + 1];
-    double(*red)[64] = reinterpret_cast<double(*)[64]>(shx);   // after the rounds (needs 128)
-    static_assert(kNearSlots * 9 * 3 >= 128, "reduction buffer");
+    double *const shx = shbuf, *const shy = shbuf + kStage, *const shu = shbuf + 2 * kStage;
+    double(*red)[64] = reinterpret_cast<double(*)[64]>(shbuf);   // after the rounds
+    static_assert(3 * kStage >= 4 * 64, "reduction buffer");
     const int lane = threadIdx.x;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
         const int e = batch_entry(bm, item);
@@ -148,7 +153,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
         }
         __syncthreads();
 
-        double re = 0.0, im = 0.0;
+        double re = 0.0, im = 0.0, fr = 0.0, fi = 0.0;
         // This lane's group sums the slice [pos, hi) of the item's sources
         // listed cell after cell; k is the cell holding pos, base its index.
         const int32_t total = cum[nw];
@@ -192,13 +197,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
                     const double at = atan2_f64(dy, live ? dx : 1.0);
                     re += live ? su[j] * (0.5 * lg) : 0.0;
                     im += live ? su[j] * at : 0.0;
+                    if (FIELD) {
+                        const double w = live ? div_f64(su[j], r2) : 0.0;
+                        fr = fma(w, dx, fr);
+                        fi = fma(-w, dy, fi);
+                    }
                 }
             } else {
                 for (int j = 0; j < padn; ++j) {
                     const double dx = y0 - sx[j], dy = y1 - sy[j];
                     const double u = su[j];
-                    re += u * (0.5 * ln_f64(dx * dx + dy * dy));
+                    const double r2 = dx * dx + dy * dy;
+                    re += u * (0.5 * ln_f64(r2));
                     im += u * atan2_f64(dy, dx);
+                    if (FIELD) {
+                        const double w = div_f64(u, r2);
+                        fr = fma(w, dx, fr);
+                        fi = fma(-w, dy, fi);
+                    }
                 }
             }
             __syncthreads();
@@ -214,23 +230,38 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
         }
         red[0][lane] = re;   // the last round's barrier freed the staging buffers
         red[1][lane] = im;
+        if (FIELD) {
+            red[2][lane] = fr;
+            red[3][lane] = fi;
+        }
         __syncthreads();
         if (grp == 0) {
-            double sr = 0.0, si = 0.0;
+            double sr = 0.0, si = 0.0, sfr = 0.0, sfi = 0.0;
             for (int q = 0; q < g; ++q) {
                 sr += red[0][q * m + tau];
                 si += red[1][q * m + tau];
+                if (FIELD) {
+                    sfr += red[2][q * m + tau];
+                    sfi += red[3][q * m + tau];
+                }
             }
             J.nsum[2 * t] = sr;   // sorted order: L2P adds the far field and un-permutes
             J.nsum[2 * t + 1] = si;
+            if (FIELD) {
+                bm.nfield[2 * t] = sfr;
+                bm.nfield[2 * t + 1] = sfi;
+            }
         }
     }
 }
 
 // L2P: phi (caller's order) = near sum (sorted order) + the target leaf's
-// local expansion, FP64 Horner (same items).
+// local expansion, FP64 Horner (same items).  With FIELD also the field:
+// near field sum + the expansion's derivative (Horner carries both; the
+// radius scaling contributes a factor 1/ell).
 // The leaf's coefficient row is staged in LDS by the whole wave first, so the
 // Horner loop reads broadcast LDS instead of a chain of dependent loads.
+template <bool FIELD>
 __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
     static_assert(kChunk <= 64, "one item per wave");
@@ -254,8 +285,14 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
         if (lane >= kChunk || t >= J.te[gid]) continue;
         const double inv = 1.0 / J.scale[J.L];
         const double zr = (J.tx[t] - J.cx[gid]) * inv, zi = (J.ty[t] - J.cy[gid]) * inv;
-        double fr = row[2 * J.p], fi = row[2 * J.p + 1];
+        double fr = row[2 * J.p], fi = row[2 * J.p + 1], dr = 0.0, di = 0.0;
         for (int m = J.p - 1; m >= 0; --m) {
+            if (FIELD) {
+                const double ndr = dr * zr - di * zi + fr;
+                const double ndi = dr * zi + di * zr + fi;
+                dr = ndr;
+                di = ndi;
+            }
             const double nr = fr * zr - fi * zi + row[2 * m];
             const double ni = fr * zi + fi * zr + row[2 * m + 1];
             fr = nr;
@@ -264,6 +301,10 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
         const int64_t o = J.tperm[t];
         phi[2 * o] = J.nsum[2 * t] + fr;
         phi[2 * o + 1] = J.nsum[2 * t + 1] + fi;
+        if (FIELD) {
+            bm.field_override[2 * o] = bm.nfield[2 * t] + dr * inv;
+            bm.field_override[2 * o + 1] = bm.nfield[2 * t + 1] + di * inv;
+        }
     }
 }
 
@@ -365,13 +406,18 @@ void launch_direct(const double *src, int64_t n_src, const double *tgt, int64_t 
 void batch_near_fp64(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
 {
     if (m.n <= 0 || m.pre[m.n] <= 0) return;
-    hipLaunchKernelGGL(k_near_fp64, dim3(persistent_grid(m.pre[m.n], kNearWavesPerCU)), dim3(64), 0, s, jobs, m);
+    const dim3 grid(persistent_grid(m.pre[m.n], kNearWavesPerCU));
+    if (m.nfield) hipLaunchKernelGGL(k_near_fp64<true>, grid, dim3(64), 0, s, jobs, m);
+    else hipLaunchKernelGGL(k_near_fp64<false>, grid, dim3(64), 0, s, jobs, m);
 }
 
 void batch_l2p(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
 {
     if (m.n <= 0 || m.pre[m.n] <= 0) return;
-    hipLaunchKernelGGL(k_l2p, dim3(persistent_grid(m.pre[m.n], 64)), dim3(64), 0, s, jobs, m);
+    if (m.field_override)
+        hipLaunchKernelGGL(k_l2p<true>, dim3(persistent_grid(m.pre[m.n], 64)), dim3(64), 0, s, jobs, m);
+    else
+        hipLaunchKernelGGL(k_l2p<false>, dim3(persistent_grid(m.pre[m.n], 64)), dim3(64), 0, s, jobs, m);
 }
 
 }  // namespace fmm

@@ -48,13 +48,22 @@ __device__ __forceinline__ float atan2_f32(float y, float x)
 // stages the next chunk of its slice (within one cell) in LDS (64/g sources rounded
 // down to a multiple of 8, at least 8; padded to a multiple of 8 with
 // zero-strength sources far away) and sums it; the groups' partial sums of a
-// target are added in group order at the end.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_near_mixed(const EvalJob *__restrict__ jobs, BatchMap bm)
+// target are added in group order at the end.  With FIELD the kernel also
+// sums u / (y - x) = u (dx - i dy) / r^2 into the field's near sums
+// (bm.nfield): the separation is formed in FP64 from the absolute
+// coordinates (staged beside the FP32 data), since 1/r amplifies the
+// rounding of FP32 offsets for close pairs, then rounded to FP32 for r^2,
+// the hardware reciprocal and the same compensated sums; a pair is skipped
+// only when its FP64 coordinates are equal.
+template <bool FIELD>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 5 : 7, 8))) void k_near_mixed(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
-    // g (cl + 1) <= 117 for every g: 64 (g = 1), 66, 51, 68, 45, ..., 117 (g = 13)
-    __shared__ float4 sh[kNearSlots * 9];
+    // g (cl + 1) <= 117 for every g: 64 (g = 1), 66, 51, 68, 45, ..., 117 (g = 13);
+    // at least 128 entries so that the reduction (4 x 64 doubles) fits
+    __shared__ float4 sh[kNearSlots * 9 > 128 ? kNearSlots * 9 : 128];
     __shared__ int32_t cbeg[kNearSlots], cend[kNearSlots], cum[kNearSlots + 1];
     __shared__ float cdx[kNearSlots], cdy[kNearSlots];
+    __shared__ double2 shd[FIELD ? kNearSlots * 9 : 1];
     double(*red)[64] = reinterpret_cast<double(*)[64]>(sh);   // after the rounds
     const int lane = threadIdx.x;
     const float half_ln2 = 0.34657359027997264f;
@@ -74,6 +83,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void
         const bool in = grp < g;
         const int32_t t = st + tau;
         const float tlx = in ? J.txl[t] : 0.0f, tly = in ? J.tyl[t] : 0.0f;
+        const double tx = FIELD && in ? J.tx[t] : 0.0, ty = FIELD && in ? J.ty[t] : 0.0;
         const double tcx = J.cx[gid], tcy = J.cy[gid];
 
         // Near-cell table (slot 0 is the leaf itself); an absent cell has an
@@ -106,16 +116,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void
         __syncthreads();
 
         float rs = 0.0f, rc = 0.0f, is = 0.0f, ic = 0.0f;
-        // Kahan step for both sums.
+        float frs = 0.0f, frc = 0.0f, fis = 0.0f, fic = 0.0f;
+        // Kahan step for a sum s with compensation c.
+        auto kahan = [](float &s, float &c, float v) {
+            const float y = v - c;
+            const float t = s + y;
+            c = (t - s) - y;
+            s = t;
+        };
         auto acc = [&](float vr, float vi) {
-            const float yr = vr - rc;
-            const float tr = rs + yr;
-            rc = (tr - rs) - yr;
-            rs = tr;
-            const float yi = vi - ic;
-            const float ti = is + yi;
-            ic = (ti - is) - yi;
-            is = ti;
+            kahan(rs, rc, vr);
+            kahan(is, ic, vi);
         };
         // This lane's group sums the slice [pos, hi) of the item's sources
         // listed cell after cell; k is the cell holding pos, base its index.
@@ -126,6 +137,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void
         while (k + 1 < nw && cum[k + 1] <= pos) ++k;
         int32_t base = cbeg[k] + (pos - cum[k]);
         const float4 *gsh = sh + (in ? grp : 0) * stride;
+        const double2 *gshd = shd + (FIELD && in ? grp * stride : 0);
         for (;;) {
             const bool busy = pos < hi;
             if (!__any(busy)) break;
@@ -147,6 +159,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void
                         v = make_float4(J.sxl[i], J.syl[i], u * half_ln2, u);
                     }
                     w[j] = v;
+                    if (FIELD) {
+                        double2 d = make_double2(1e18, 1e18);
+                        if (j < n) d = make_double2(J.sx[base + j], J.sy[base + j]);
+                        shd[grp * stride + j] = d;
+                    }
                 }
             }
             __syncthreads();
@@ -161,13 +178,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void
                     const float lg = __log2f(live ? r2 : 1.0f);
                     const float at = atan2_f32(dy, dx);
                     acc(live ? sv.z * lg : 0.0f, live ? sv.w * at : 0.0f);
+                    if (FIELD) {
+                        const double2 sd = gshd[j];
+                        const bool on = tx != sd.x || ty != sd.y;
+                        const float ex = (float)(tx - sd.x), ey = (float)(ty - sd.y);
+                        const float w = on ? sv.w * __builtin_amdgcn_rcpf(fmaf(ex, ex, fmaf(ey, ey, 1e-37f))) : 0.0f;
+                        kahan(frs, frc, w * ex);
+                        kahan(fis, fic, -w * ey);
+                    }
                 }
             } else {
                 // Distinct leaves: separations are nonzero; the 1e-37 inside
                 // r^2 only keeps a pair closer than FP32 resolution finite.
                 // Eight pairs are summed plainly, then Kahan-added.
                 for (int j = 0; j < padn; j += 8) {
-                    float pr = 0.0f, pi = 0.0f;
+                    float pr = 0.0f, pi = 0.0f, qr = 0.0f, qi = 0.0f;
 #pragma unroll
                     for (int jj = 0; jj < 8; ++jj) {
                         const float4 sv = gsh[j + jj];
@@ -175,8 +200,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-37f));
                         pr = fmaf(sv.z, __log2f(r2), pr);
                         pi = fmaf(sv.w, atan2_f32(dy, dx), pi);
+                        if (FIELD) {
+                            const double2 sd = gshd[j + jj];
+                            const float ex = (float)(tx - sd.x), ey = (float)(ty - sd.y);
+                            const float w = sv.w * __builtin_amdgcn_rcpf(fmaf(ex, ex, fmaf(ey, ey, 1e-37f)));
+                            qr = fmaf(w, ex, qr);
+                            qi = fmaf(-w, ey, qi);
+                        }
                     }
                     acc(pr, pi);
+                    if (FIELD) {
+                        kahan(frs, frc, qr);
+                        kahan(fis, fic, qi);
+                    }
                 }
             }
             __syncthreads();
@@ -192,15 +228,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void
         }
         red[0][lane] = (double)rs - (double)rc;   // the last round's barrier freed sh
         red[1][lane] = (double)is - (double)ic;
+        if (FIELD) {
+            red[2][lane] = (double)frs - (double)frc;
+            red[3][lane] = (double)fis - (double)fic;
+        }
         __syncthreads();
         if (grp == 0) {
-            double re = 0.0, im = 0.0;
+            double re = 0.0, im = 0.0, fre = 0.0, fim = 0.0;
             for (int q = 0; q < g; ++q) {
                 re += red[0][q * m + tau];
                 im += red[1][q * m + tau];
+                if (FIELD) {
+                    fre += red[2][q * m + tau];
+                    fim += red[3][q * m + tau];
+                }
             }
             J.nsum[2 * t] = re;   // sorted order: L2P adds the far field and un-permutes
             J.nsum[2 * t + 1] = im;
+            if (FIELD) {
+                bm.nfield[2 * t] = fre;
+                bm.nfield[2 * t + 1] = fim;
+            }
         }
     }
 }
@@ -208,7 +256,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void
 void batch_near_mixed(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
 {
     if (m.n <= 0 || m.pre[m.n] <= 0) return;
-    hipLaunchKernelGGL(k_near_mixed, dim3(persistent_grid(m.pre[m.n], kNearWavesPerCU)), dim3(64), 0, s, jobs, m);
+    const dim3 grid(persistent_grid(m.pre[m.n], kNearWavesPerCU));
+    if (m.nfield) hipLaunchKernelGGL(k_near_mixed<true>, grid, dim3(64), 0, s, jobs, m);
+    else hipLaunchKernelGGL(k_near_mixed<false>, grid, dim3(64), 0, s, jobs, m);
 }
 
 }  // namespace fmm

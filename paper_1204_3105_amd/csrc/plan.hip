@@ -262,6 +262,8 @@ struct PlanImpl : Plan {
     int64_t n_items_cap = 0;
     void *scratch = nullptr;
     size_t scratch_sz = 0;
+    double *nfield = nullptr;     // near-field sums of the field (first field evaluation)
+    double *io_field = nullptr;   // host mode: field staging
 };
 
 template <typename T>
@@ -784,22 +786,30 @@ fmm_status fmm_plan(fmm_tiling tiling, const double *src, int64_t n_src, const d
     return FMM_OK;
 }
 
-fmm_status fmm_eval(fmm_plan_t plan, const double *u, double *phi)
+static fmm_status eval_impl(fmm_plan_t plan, const double *u, double *phi, double *field, bool want_field)
 {
     g_err.clear();
     if (!plan) return fail(FMM_E_INVALID, "null plan");
     PlanImpl *P = (PlanImpl *)(Plan *)plan;
-    if ((P->n_src > 0 && !u) || (P->n_tgt > 0 && !phi)) return fail(FMM_E_INVALID, "null array");
+    if ((P->n_src > 0 && !u) || (P->n_tgt > 0 && (!phi || (want_field && !field))))
+        return fail(FMM_E_INVALID, "null array");
     hipStream_t s = P->stream;
-    const int L = P->geo.L;
     if (P->n_tgt == 0) return FMM_OK;
+    if (want_field && (!P->nfield || (!P->device_pointers && !P->io_field))) {
+        int err = 0;
+        if (!P->nfield) P->nfield = take<double>(P, 2 * P->n_tgt, &err);
+        if (!P->device_pointers && !P->io_field) P->io_field = take<double>(P, 2 * P->n_tgt, &err);
+        if (err) return fail(FMM_E_NOMEM, "device allocation failed (field buffers)");
+    }
     double *dphi = P->device_pointers ? phi : P->io_phi;
+    double *dfield = want_field ? (P->device_pointers ? field : P->io_field) : nullptr;
     const double *du = P->device_pointers ? u : P->io_u;
     if (!P->device_pointers && P->n_src)
         FMM_HIP_CHECK(hipMemcpyAsync(P->io_u, u, sizeof(double) * P->n_src, hipMemcpyHostToDevice, s));
     FMM_HIP_CHECK(hipEventRecord(P->ev[2], s));
     if (P->n_src == 0) {
         FMM_HIP_CHECK(hipMemsetAsync(dphi, 0, sizeof(double) * 2 * P->n_tgt, s));
+        if (dfield) FMM_HIP_CHECK(hipMemsetAsync(dfield, 0, sizeof(double) * 2 * P->n_tgt, s));
         FMM_HIP_CHECK(hipEventRecord(P->ev[3], s));
         FMM_HIP_CHECK(hipEventRecord(P->ev[4], s));
         FMM_HIP_CHECK(hipEventRecord(P->ev[5], s));
@@ -810,16 +820,30 @@ fmm_status fmm_eval(fmm_plan_t plan, const double *u, double *phi)
         EvalJob J = make_job(*P);
         batch_gather_u((const EvalJob *)P->job_dev, J, du, s);
         Plan *one = P;
-        run_batch(&one, 1, (const EvalJob *)P->job_dev, dphi, s, side_stream(), &P->ev[3]);
+        run_batch(&one, 1, (const EvalJob *)P->job_dev, dphi, s, side_stream(), &P->ev[3], dfield,
+                  dfield ? P->nfield : nullptr);
     }
     FMM_HIP_CHECK(hipGetLastError());
     P->evaluated = true;
     if (!P->device_pointers) {
         FMM_HIP_CHECK(hipMemcpyAsync(phi, P->io_phi, sizeof(double) * 2 * P->n_tgt,
                                      hipMemcpyDeviceToHost, s));
+        if (dfield)
+            FMM_HIP_CHECK(hipMemcpyAsync(field, P->io_field, sizeof(double) * 2 * P->n_tgt,
+                                         hipMemcpyDeviceToHost, s));
         FMM_HIP_CHECK(hipStreamSynchronize(s));
     }
     return FMM_OK;
+}
+
+fmm_status fmm_eval(fmm_plan_t plan, const double *u, double *phi)
+{
+    return eval_impl(plan, u, phi, nullptr, false);
+}
+
+fmm_status fmm_eval_field(fmm_plan_t plan, const double *u, double *phi, double *field)
+{
+    return eval_impl(plan, u, phi, field, true);
 }
 
 fmm_status fmm_plan_info_get(fmm_plan_t plan, fmm_plan_info *info)

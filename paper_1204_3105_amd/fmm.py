@@ -66,7 +66,8 @@ class Result(C.Structure):
 EXPORTED = ["fmm_options_default", "fmm_plan", "fmm_eval", "fmm_plan_info_get",
             "fmm_plan_export_points", "fmm_plan_export_level", "fmm_plan_destroy",
             "fmm_last_error", "fmm_order_for_eps", "fmm_server_create", "fmm_submit",
-            "fmm_poll", "fmm_server_drain", "fmm_server_destroy", "fmm_direct"]
+            "fmm_poll", "fmm_server_drain", "fmm_server_destroy", "fmm_direct",
+            "fmm_eval_field"]
 
 _lib = None
 
@@ -97,6 +98,8 @@ def lib():
                            C.POINTER(P)]
     L.fmm_plan.restype = C.c_int
     L.fmm_eval.argtypes = [P, P, P]
+    L.fmm_eval_field.argtypes = [P, P, P, P]
+    L.fmm_eval_field.restype = C.c_int
     L.fmm_eval.restype = C.c_int
     L.fmm_plan_info_get.argtypes = [P, C.POINTER(PlanInfo)]
     L.fmm_plan_info_get.restype = C.c_int
@@ -237,6 +240,33 @@ class Plan:
         _check(L.fmm_eval(self._plan, C.c_void_p(u.ctypes.data) if self.n_src else None,
                           C.c_void_p(res.ctypes.data) if self.n_tgt else None))
         return res
+
+    def eval_field(self, u, out=None, field_out=None):
+        """(Phi, Phi') for strengths u; Phi'(y) = sum u_i / (y - x_i).  Host:
+        complex128 ndarrays.  Device: complex128 CUDA tensors (or fills the
+        given ones)."""
+        L = lib()
+        if self.device:
+            import torch
+            u = u.contiguous()
+            if u.dtype != torch.float64 or not u.is_cuda or u.numel() != self.n_src:
+                raise TypeError("u must be a float64 CUDA tensor of n_src elements")
+            if out is None:
+                out = torch.empty(self.n_tgt, dtype=torch.complex128, device=u.device)
+            if field_out is None:
+                field_out = torch.empty(self.n_tgt, dtype=torch.complex128, device=u.device)
+            _check(L.fmm_eval_field(self._plan, C.c_void_p(u.data_ptr()), C.c_void_p(out.data_ptr()),
+                                    C.c_void_p(field_out.data_ptr())))
+            return out, field_out
+        u = np.ascontiguousarray(u, dtype=np.float64)
+        if len(u) != self.n_src:
+            raise ValueError("u must have n_src elements")
+        res = np.empty(self.n_tgt, dtype=np.complex128) if out is None else out
+        fld = np.empty(self.n_tgt, dtype=np.complex128) if field_out is None else field_out
+        _check(L.fmm_eval_field(self._plan, C.c_void_p(u.ctypes.data) if self.n_src else None,
+                                C.c_void_p(res.ctypes.data) if self.n_tgt else None,
+                                C.c_void_p(fld.ctypes.data) if self.n_tgt else None))
+        return res, fld
 
     # -------------------------------------------------------------- info
     def info(self) -> dict:

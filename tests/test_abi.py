@@ -62,6 +62,7 @@ def test_options_default_and_validation(F):
     o.struct_size = 3
     assert lib.fmm_plan(0, pts, 2, pts, 2, 1e-6, C.byref(o), C.byref(plan)) == 1
     assert lib.fmm_eval(None, None, None) == 1
+    assert lib.fmm_eval_field(None, None, None, None) == 1
     lib.fmm_plan_destroy(None)
 
 
