@@ -66,8 +66,8 @@ def parse():
     ap.add_argument("--check", type=int, default=2048, help="targets sampled for the error check")
     ap.add_argument("--cpu-sample", type=int, default=2048)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--compare-fp64", action="store_true",
-                    help="also time the plain FP64 form (reported under extra)")
+    ap.add_argument("--no-compare-fp64", dest="compare_fp64", action="store_false",
+                    help="skip timing the plain FP64 form (reported under extra by default)")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests in the serving stream (0 = skip the serving leg)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -211,6 +211,27 @@ def serve_bench(F, nreq, load, leaf):
     }
 
 
+def m2l_mfma(infos, tilings):
+    """M2L against the dense BF16 MFMA peak, per tiling: algorithmic flops
+    (8 (p+1)^2 per E4 pair: a complex (p+1) x (p+1) matrix-vector product) and
+    issued MFMA flops (six BF16 split products of a real 2(p+1) x 2p block per
+    pair, padded to 16-row tiles and 32-deep k-blocks) over the M2L stage time
+    (events around the M2L launches; the stage runs beside the near field)."""
+    out = {}
+    for t in tilings:
+        inf = infos[t]
+        p = inf[-1]["p"]
+        pairs = inf[-1]["n_m2l_pairs"]
+        ms = float(np.mean([i["stage_ms"][1] for i in inf]))
+        mt, kb = (2 * (p + 1) + 15) // 16, (2 * p + 31) // 32
+        alg = 8.0 * (p + 1) ** 2 * pairs
+        issued = 6.0 * 2.0 * (16 * mt) * (32 * kb) * pairs
+        out[t] = {"stage_ms": ms, "pairs": pairs, "alg_tflops": alg / (ms * 1e-3) / 1e12,
+                  "issued_tflops": issued / (ms * 1e-3) / 1e12, "peak_tflops": MFMA_BF16_PEAK / 1e12,
+                  "frac_issued": issued / (ms * 1e-3) / MFMA_BF16_PEAK}
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -270,13 +291,18 @@ def main():
             "targets_per_s_plan_eval_gpu": a.n / (np.mean([i["plan_ms"] + i["eval_ms"] for i in inf]) * 1e-3),
         }
     extra = {"per_tiling": per_tiling}
+    if prec_used == "mixed":
+        extra["m2l_mfma"] = m2l_mfma(infos, tilings)
     errs = error_check(oracle, w, outs, infos, tilings, a.check)
     extra["errors"] = errs
 
     if a.compare_fp64 and prec_used != "fp64":
         wall64, infos64 = timed(F, torch, pts, u, tilings, a.eps, "fp64", a.leaf, a.steps, 1, outs)
         extra["fp64_form"] = {"value": len(tilings) * a.n * a.steps / wall64,
-                              "ms_per_step": wall64 / a.steps * 1e3}
+                              "ms_per_step": wall64 / a.steps * 1e3,
+                              "errors": error_check(oracle, w, outs, infos64, tilings, a.check)}
+        print("bench: plain FP64 form %.4g targets/s" % extra["fp64_form"]["value"], file=sys.stderr,
+              flush=True)
 
     if a.serve_requests > 0:
         print("bench: serving stream (%d requests) ..." % a.serve_requests, file=sys.stderr, flush=True)
