@@ -54,6 +54,7 @@ struct BatchMap {
     double *phi_override;         // single-job output redirect (or null)
     double *field_override;       // single-job field output, caller's order (or null: no field)
     double *nfield;               // single-job near-field sums of the field, sorted order
+    const double *u_in;           // single-job strengths in the caller's order: P2M gathers them
 };
 
 __device__ __forceinline__ int batch_entry(const BatchMap &m, int64_t item)
@@ -75,6 +76,13 @@ __device__ __forceinline__ int level_of(const EvalJob &J, int64_t gid)
 constexpr int kNearWavesPerCU = 128;
 
 // Persistent-grid size for a phase with `items` work items.
+// The far-field passes (M2M, M2L, L2L) form a chain of small, latency-bound
+// launches that share the SIMDs with the long-running near-field waves on
+// the side stream.  Their waves raise their issue priority so the chain is
+// not slowed to the near field's share of each SIMD; the near field fills
+// the remaining issue slots.
+__device__ __forceinline__ void far_field_priority() { __builtin_amdgcn_s_setprio(2); }
+
 inline unsigned persistent_grid(int64_t items, int per_cu)
 {
     int64_t cap = (int64_t)256 * per_cu;
@@ -113,8 +121,10 @@ hipStream_t side_stream();   // per-device stream for the near field
 // field_single / nfield_single (a batch of one only): also evaluate the
 // field Phi' into field_single, with nfield_single (2 n_tgt doubles) for the
 // near-field part.
+// u_single (a batch of one only): the strengths in the caller's order,
+// gathered by P2M; otherwise the jobs' sorted strengths are already filled.
 void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_single, hipStream_t s,
                hipStream_t side, hipEvent_t *ev, double *field_single = nullptr,
-               double *nfield_single = nullptr);
+               double *nfield_single = nullptr, const double *u_single = nullptr);
 
 }  // namespace fmm

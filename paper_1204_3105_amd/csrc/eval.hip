@@ -5,7 +5,8 @@
 //   (the E4 lists), L2L from level 2 down to L, then L2P per target leaf.
 //   The P2P near field depends on none of these and runs on a side stream
 //   once P2M is done; L2P waits for it and adds the far field to its sums.
-//   Strengths are gathered into sorted order by the caller.
+//   Strengths are gathered into sorted order by P2M (a single plan) or by
+//   the caller (a batch).
 // Each phase is one launch (per kernel variant) covering every plan of the
 // batch that has work in it; level-wise phases pair plans by their distance
 // from the leaves (M2M) or from the top (L2L), so plans of different depth
@@ -122,6 +123,7 @@ struct Launcher {
         m.phi_override = phi_single;
         m.field_override = field_single;
         m.nfield = nfield_single;
+        m.u_in = nullptr;
     }
 };
 
@@ -143,7 +145,8 @@ hipStream_t side_stream()
 }
 
 void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_single, hipStream_t s,
-               hipStream_t side, hipEvent_t *ev, double *field_single, double *nfield_single)
+               hipStream_t side, hipEvent_t *ev, double *field_single, double *nfield_single,
+               const double *u_single)
 {
     if (n != 1 || !nfield_single) field_single = nfield_single = nullptr;
     if (!field_single) nfield_single = nullptr;
@@ -158,9 +161,13 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
 
     int pmax = 1;
     for (int i = 0; i < n; ++i) pmax = std::max(pmax, plans[i]->p);
-    // P2M
+    // P2M (gathers the strengths of a single plan on the way)
     {
-        auto f = [&](const BatchMap &m) { batch_p2m(jobs_dev, m, pmax, s); };
+        auto f = [&](const BatchMap &m) {
+            BatchMap mu = m;
+            mu.u_in = n == 1 ? u_single : nullptr;
+            batch_p2m(jobs_dev, mu, pmax, s);
+        };
         for (int i = 0; i < n; ++i) Lc.add(i, 0, plans[i]->lev[plans[i]->geo.L].n, f);
         go(f);
     }

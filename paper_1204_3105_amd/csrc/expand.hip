@@ -81,60 +81,89 @@ void batch_gather_u(const EvalJob *jobs_d, const EvalJob &J, const double *u, hi
 }
 
 // ------------------------------------------------------------------ P2M
-// One wave per leaf.  Each lane takes one source of a 64-source chunk and
-// writes its terms -u w^k / k (k = 1..p) to LDS; then lanes sum the rows of
-// that table (lane r owns row r: Re/Im of one coefficient), so every
-// coefficient is a plain sum over the chunk in source order.
+// One wave per leaf.  The leaf's sources are loaded 64 at a time, one per
+// lane, all loads in flight together; they are then taken 16 at a time: the
+// wave's four 16-lane quarters read the same 16 sources from their owner
+// lanes (cross-lane reads), and quarter q writes the terms -u w^k / k of the
+// coefficients k = q (mod 4) (w^k stepped by w^4) to an LDS table with a
+// row per Re/Im coefficient and a column per source; then lane r sums row r
+// (and r + 64) over the 16 columns in source order.  With bm.u_in (a single
+// plan) the strengths are gathered here from the caller's order,
+// u = u_in[sperm[i]], and stored in sorted order (FP64, and FP32 for the
+// mixed near field) for the near-field kernels.
+constexpr int kP2MChunk = 16;
+constexpr int kP2MStride = kP2MChunk + 1;   // odd stride: conflict-free row reads
+
+__device__ __forceinline__ double lane_read(double v, int src)
+{
+    const int lo = __shfl(__double2loint(v), src), hi = __shfl(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
 __global__ __launch_bounds__(64) void k_p2m(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
-    constexpr int kChunkS = 32;
-    constexpr int kStride = kChunkS + 1;   // odd stride: conflict-free row reads
-    extern __shared__ double tab[];          // 2 (pmax + 1) rows of kStride
+    extern __shared__ double tab[];          // 2 (pmax + 1) rows of kP2MStride
     __shared__ double invk[kMaxP + 1];       // 1/k
     const int lane = threadIdx.x;
+    const int src_lane = lane & (kP2MChunk - 1), q = lane / kP2MChunk;
     for (int k = lane; k <= kMaxP; k += 64) invk[k] = k ? 1.0 / (double)k : 0.0;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
         const int e = batch_entry(bm, item);
         const EvalJob &J = jobs[bm.job[e]];
         const int64_t gid = J.leaf_off + (item - bm.pre[e]);
         const int32_t b = J.sb[gid], en = J.se[gid];
-        const int P1 = J.p + 1, R = 2 * P1;
+        const int p = J.p, P1 = p + 1, R = 2 * P1;
         double *row = J.mp + gid * 2 * P1;
         const double inv = 1.0 / J.scale[J.L];
         const double c0 = J.cx[gid], c1 = J.cy[gid];
+        const bool gather = bm.u_in != nullptr, mixed = J.prec == FMM_PREC_MIXED;
         double acc = 0.0, acc2 = 0.0;   // rows lane and lane + 64
-        for (int32_t base = b; base < en; base += kChunkS) {
-            // lanes 0..31 each take a source; lanes 32..63 take the odd
-            // coefficients of the same source (halves the serial chain)
-            const int src_lane = lane & (kChunkS - 1), half = lane / kChunkS;
-            const int32_t i = base + src_lane;
-            const bool ok = i < en;
-            const double u = ok ? J.su[i] : 0.0;
-            const cd w = ok ? cd{(J.sx[i] - c0) * inv, (J.sy[i] - c1) * inv} : cd{0.0, 0.0};
-            const cd w2 = cmul(w, w);
-            __syncthreads();
-            if (half == 0) {
-                tab[0 * kStride + src_lane] = u;
-                tab[1 * kStride + src_lane] = 0.0;
+        for (int32_t blk = b; blk < en; blk += 64) {
+            // this lane's source of the 64-block
+            const int32_t i = blk + lane;
+            double ul = 0.0, wxl = 0.0, wyl = 0.0;
+            if (i < en) {
+                if (gather) {
+                    ul = bm.u_in[J.sperm[i]];
+                    J.su[i] = ul;
+                    if (mixed) J.suf[i] = (float)ul;
+                } else {
+                    ul = J.su[i];
+                }
+                wxl = (J.sx[i] - c0) * inv;
+                wyl = (J.sy[i] - c1) * inv;
             }
-            cd pw = half ? w : cmul(w, w);   // w^1 or w^2
-            for (int k = 1 + (half ? 0 : 1); k <= J.p; k += 2) {
-                const double f = -u * invk[k];
-                tab[(2 * k) * kStride + src_lane] = pw.x * f;
-                tab[(2 * k + 1) * kStride + src_lane] = pw.y * f;
-                pw = cmul(pw, w2);
-            }
-            __syncthreads();
-            const int n = en - base < kChunkS ? en - base : kChunkS;
-            if (lane < R) {
-                double s = 0.0;
-                for (int j = 0; j < n; ++j) s += tab[lane * kStride + j];
-                acc += s;
-            }
-            if (lane + 64 < R) {
-                double s = 0.0;
-                for (int j = 0; j < n; ++j) s += tab[(lane + 64) * kStride + j];
-                acc2 += s;
+            const int nb = en - blk < 64 ? en - blk : 64;
+            for (int c = 0; c < nb; c += kP2MChunk) {
+                const int from = c + src_lane;
+                const double u = lane_read(ul, from);
+                const cd w = {lane_read(wxl, from), lane_read(wyl, from)};   // zero past the end
+                const cd w2 = cmul(w, w);
+                const cd w4 = cmul(w2, w2);
+                __syncthreads();
+                if (q == 0) {
+                    tab[0 * kP2MStride + src_lane] = u;
+                    tab[1 * kP2MStride + src_lane] = 0.0;
+                }
+                cd pw = q == 0 ? w4 : (q == 1 ? w : (q == 2 ? w2 : cmul(w2, w)));   // w^q, w^4 for q = 0
+                for (int k = q == 0 ? 4 : q; k <= p; k += 4) {
+                    const double f = -u * invk[k];
+                    tab[(2 * k) * kP2MStride + src_lane] = pw.x * f;
+                    tab[(2 * k + 1) * kP2MStride + src_lane] = pw.y * f;
+                    pw = cmul(pw, w4);
+                }
+                __syncthreads();
+                const int n = nb - c < kP2MChunk ? nb - c : kP2MChunk;
+                if (lane < R) {
+                    double s = 0.0;
+                    for (int j = 0; j < n; ++j) s += tab[lane * kP2MStride + j];
+                    acc += s;
+                }
+                if (lane + 64 < R) {
+                    double s = 0.0;
+                    for (int j = 0; j < n; ++j) s += tab[(lane + 64) * kP2MStride + j];
+                    acc2 += s;
+                }
             }
         }
         if (lane < R) row[lane] = acc;
@@ -145,7 +174,7 @@ __global__ __launch_bounds__(64) void k_p2m(const EvalJob *__restrict__ jobs, Ba
 void batch_p2m(const EvalJob *jobs, const BatchMap &m, int pmax, hipStream_t s)
 {
     if (m.n <= 0 || m.pre[m.n] <= 0) return;
-    const size_t lds = (size_t)2 * (pmax + 1) * 33 * sizeof(double);
+    const size_t lds = (size_t)2 * (pmax + 1) * kP2MStride * sizeof(double);
     hipLaunchKernelGGL(k_p2m, dim3(persistent_grid(m.pre[m.n], 64)), dim3(64), lds, s, jobs, m);
 }
 
@@ -156,6 +185,7 @@ void batch_p2m(const EvalJob *jobs, const BatchMap &m, int pmax, hipStream_t s)
 // w = (c_child - c_parent)/ell_l, rho = ell_(l+1)/ell_l.
 __global__ __launch_bounds__(64) void k_m2m(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
+    far_field_priority();
     __shared__ cd wp[kMaxP + 1];
     __shared__ cd ac[kMaxP + 1];
     __shared__ double rp[kMaxP + 1];
@@ -231,6 +261,7 @@ void batch_m2m(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
 // w = (c_child - c_parent)/ell_(l-1), rho = ell_l/ell_(l-1).
 __global__ __launch_bounds__(64) void k_l2l(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
+    far_field_priority();
     __shared__ cd wp[kMaxP + 1];
     __shared__ cd bp[kMaxP + 1];
     const int m = threadIdx.x;
@@ -288,6 +319,7 @@ void batch_l2l(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
 template <int PM, int GS>
 __global__ __launch_bounds__(256) void k_m2m_lanes(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
+    far_field_priority();
     const int64_t total = bm.pre[bm.n] * GS;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
@@ -361,6 +393,7 @@ __global__ __launch_bounds__(256) void k_m2m_lanes(const EvalJob *__restrict__ j
 template <int PM>
 __global__ __launch_bounds__(256) void k_l2l_lanes(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
+    far_field_priority();
     for (int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; item < bm.pre[bm.n];
          item += (int64_t)gridDim.x * blockDim.x) {
         const int e = batch_entry(bm, item);
@@ -445,6 +478,7 @@ void batch_l2l_lanes(const EvalJob *jobs, const BatchMap &m, int pm, hipStream_t
 //   b~_m += delta^(-m) [ -a_0/m + sum_k C(m+k-1, k-1) g_k ]
 __global__ __launch_bounds__(64) void k_m2l_block(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
+    far_field_priority();
     __shared__ cd gk[kMaxP + 1];
     __shared__ cd np[kMaxP + 1];   // (-1/delta)^k
     __shared__ double a0s;

@@ -137,6 +137,7 @@ void launch_m2l_tables(Plan &P, int pm, double *base, hipStream_t s)
 template <int PM>
 __global__ __launch_bounds__(64) void k_m2l_lanes(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
+    far_field_priority();
     constexpr int CH = 8;   // outputs per pass over the slots
     __shared__ double H[PM * PM];   // H[(m-1)*PM + (k-1)] = C(m+k-1, k-1)
     __shared__ double invm[PM + 1];

@@ -285,6 +285,7 @@ int mixed_setup(Plan &P)
 template <int MT, int KB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_m2l_bf16x3(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
+    far_field_priority();
     constexpr int NA = MT * KB * 3 * 64;   // bf16x8 vectors of one slot's matrix
     constexpr int NR = 32 * MT;            // output rows (>= 2(p+1))
     constexpr int PER = (NA + 255) / 256;  // staging vectors per thread
@@ -450,6 +451,7 @@ void mixed_pointers(const Plan &P, const __bf16 **tab, const int32_t **tiles, co
 // MFMA B-operand layout: thread per (cell, k-block, lane group q).
 __global__ __launch_bounds__(256) void k_split_mp(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
+    far_field_priority();
     for (int64_t item = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; item < bm.pre[bm.n];
          item += (int64_t)gridDim.x * blockDim.x) {
         const int e = batch_entry(bm, item);

@@ -195,8 +195,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 3 : 
                     const bool live = r2 > 0.0;
                     const double lg = ln_f64(live ? r2 : 1.0);
                     const double at = atan2_f64(dy, live ? dx : 1.0);
-                    re += live ? su[j] * (0.5 * lg) : 0.0;
-                    im += live ? su[j] * at : 0.0;
+                    re = fma(live ? su[j] : 0.0, 0.5 * lg, re);
+                    im = fma(live ? su[j] : 0.0, at, im);
                     if (FIELD) {
                         const double w = live ? div_f64(su[j], r2) : 0.0;
                         fr = fma(w, dx, fr);
@@ -208,8 +208,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 3 : 
                     const double dx = y0 - sx[j], dy = y1 - sy[j];
                     const double u = su[j];
                     const double r2 = dx * dx + dy * dy;
-                    re += u * (0.5 * ln_f64(r2));
-                    im += u * atan2_f64(dy, dx);
+                    re = fma(u, 0.5 * ln_f64(r2), re);
+                    im = fma(u, atan2_f64(dy, dx), im);
                     if (FIELD) {
                         const double w = div_f64(u, r2);
                         fr = fma(w, dx, fr);
@@ -277,33 +277,47 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
         const int64_t gid = J.leaf_off + li;
         const int P1 = J.p + 1;
         const double *b = J.lc + gid * 2 * P1;
+        // The lane's target data is requested before the row is staged, so
+        // all of the item's loads are in flight together.
+        const int32_t t = st + lane;
+        const bool inb = lane < kChunk && t < J.n_tgt;
+        const double tx = inb ? J.tx[t] : 0.0, ty = inb ? J.ty[t] : 0.0;
+        const double n0 = inb ? J.nsum[2 * t] : 0.0, n1 = inb ? J.nsum[2 * t + 1] : 0.0;
+        const int64_t o = inb ? J.tperm[t] : 0;
+        double f0 = 0.0, f1 = 0.0;
+        if (FIELD && inb) {
+            f0 = bm.nfield[2 * t];
+            f1 = bm.nfield[2 * t + 1];
+        }
+        const int32_t te = J.te[gid];
+        const double cx = J.cx[gid], cy = J.cy[gid];
         __syncthreads();
         if (lane < 2 * P1) row[lane] = b[lane];
         if (lane + 64 < 2 * P1) row[lane + 64] = b[lane + 64];
         __syncthreads();
-        const int32_t t = st + lane;
-        if (lane >= kChunk || t >= J.te[gid]) continue;
+        if (!inb || t >= te) continue;
         const double inv = 1.0 / J.scale[J.L];
-        const double zr = (J.tx[t] - J.cx[gid]) * inv, zi = (J.ty[t] - J.cy[gid]) * inv;
+        const double zr = (tx - cx) * inv, zi = (ty - cy) * inv;
         double fr = row[2 * J.p], fi = row[2 * J.p + 1], dr = 0.0, di = 0.0;
+        // Explicit FMAs: the value's arithmetic is the same with and
+        // without the derivative beside it.
         for (int m = J.p - 1; m >= 0; --m) {
             if (FIELD) {
-                const double ndr = dr * zr - di * zi + fr;
-                const double ndi = dr * zi + di * zr + fi;
+                const double ndr = fma(dr, zr, fma(-di, zi, fr));
+                const double ndi = fma(dr, zi, fma(di, zr, fi));
                 dr = ndr;
                 di = ndi;
             }
-            const double nr = fr * zr - fi * zi + row[2 * m];
-            const double ni = fr * zi + fi * zr + row[2 * m + 1];
+            const double nr = fma(fr, zr, fma(-fi, zi, row[2 * m]));
+            const double ni = fma(fr, zi, fma(fi, zr, row[2 * m + 1]));
             fr = nr;
             fi = ni;
         }
-        const int64_t o = J.tperm[t];
-        phi[2 * o] = J.nsum[2 * t] + fr;
-        phi[2 * o + 1] = J.nsum[2 * t + 1] + fi;
+        phi[2 * o] = n0 + fr;
+        phi[2 * o + 1] = n1 + fi;
         if (FIELD) {
-            bm.field_override[2 * o] = bm.nfield[2 * t] + dr * inv;
-            bm.field_override[2 * o + 1] = bm.nfield[2 * t + 1] + di * inv;
+            bm.field_override[2 * o] = f0 + dr * inv;
+            bm.field_override[2 * o + 1] = f1 + di * inv;
         }
     }
 }

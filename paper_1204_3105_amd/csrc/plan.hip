@@ -817,11 +817,9 @@ static fmm_status eval_impl(fmm_plan_t plan, const double *u, double *phi, doubl
         FMM_HIP_CHECK(hipEventRecord(P->ev[8], s));
         FMM_HIP_CHECK(hipEventRecord(P->ev[9], s));
     } else {
-        EvalJob J = make_job(*P);
-        batch_gather_u((const EvalJob *)P->job_dev, J, du, s);
         Plan *one = P;
         run_batch(&one, 1, (const EvalJob *)P->job_dev, dphi, s, side_stream(), &P->ev[3], dfield,
-                  dfield ? P->nfield : nullptr);
+                  dfield ? P->nfield : nullptr, du);
     }
     FMM_HIP_CHECK(hipGetLastError());
     P->evaluated = true;
