@@ -194,9 +194,13 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
         hipEventRecord(ev[6], side);
     }
 
-    // Translation kernel variants: lane form for orders up to 48 (register
-    // arrays of PM + 1 coefficients), block form beyond.
+    // Translation kernel variants: M2M and L2L take the block form (a wave
+    // per cell, a lane per coefficient: few registers, so its waves find
+    // room beside the near field's) for the base-4 tilings and for orders
+    // above 48; the septree's seven children per parent take the lane form
+    // (a lane per parent-child pair, coefficients in registers).
     const int pms[] = {0, 8, 16, 24, 32, 40, 48};
+    auto shift_pm = [](const Plan &P) { return base_of(P.geo.tiling) == 4 ? 0 : P.m2l_pm; };
     // M2M, step k: level L_i - 1 - k; lane groups of 4 (base 4) or 8 (base 7).
     for (int k = 0; k < maxL; ++k)
         for (int pm : pms)
@@ -209,7 +213,7 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
                 for (int i = 0; i < n; ++i) {
                     const Plan &P = *plans[i];
                     const int l = P.geo.L - 1 - k;
-                    if (l < 1 || P.m2l_pm != pm || (pm && (base_of(P.geo.tiling) > 4 ? 8 : 4) != gs)) continue;
+                    if (l < 1 || shift_pm(P) != pm || (pm && (base_of(P.geo.tiling) > 4 ? 8 : 4) != gs)) continue;
                     Lc.add(i, l, P.lev[l].n, f);
                 }
                 go(f);
@@ -270,7 +274,7 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
                 else batch_l2l_lanes(jobs_dev, m, pm, s);
             };
             for (int i = 0; i < n; ++i)
-                if (plans[i]->geo.L >= l && plans[i]->m2l_pm == pm) Lc.add(i, l, plans[i]->lev[l].n, f);
+                if (plans[i]->geo.L >= l && shift_pm(*plans[i]) == pm) Lc.add(i, l, plans[i]->lev[l].n, f);
             go(f);
         }
     hipEventRecord(ev[2], s);

@@ -149,9 +149,11 @@ struct Plan {
 // ------------------------------------------------------------------ kernels
 // keys.hip
 void launch_bbox(const double *pts, int64_t n, double *partial, int nblocks, hipStream_t s);
-void launch_bbox_final(const double *partial, int nparts, double *out4, hipStream_t s);
+// Also sets *zero (if not null) to 0.
+void launch_bbox_final(const double *partial, int nparts, double *out4, int32_t *zero, hipStream_t s);
+// Also clears zero[0 .. n_zero).
 void launch_keys(const GeoParams &g, const double *pts, int64_t n, uint32_t *key, int32_t *idx,
-                 int32_t *bad_count, hipStream_t s);
+                 int32_t *bad_count, int32_t *zero, int64_t n_zero, hipStream_t s);
 void launch_gather_points(const double *pts, const int32_t *perm, int64_t n, double *x, double *y,
                           hipStream_t s);
 
@@ -168,7 +170,8 @@ void launch_mark_cells(const GeoParams &g, const LevelInfo *lev, const uint32_t 
 void launch_flags_to_ids(int32_t *flags, int64_t n, hipStream_t s);
 void launch_compact(const GeoParams &g, const LevelInfo *lev, int64_t dense_total,
                     const int32_t *flags, const int32_t *ids, int32_t *dense, uint32_t *cell_key,
-                    uint8_t *occ, int32_t *sb, int32_t *se, int32_t *tb, int32_t *te, hipStream_t s);
+                    uint8_t *occ, int32_t *sb, int32_t *se, int32_t *tb, int32_t *te, double *zero,
+                    int n_zero, hipStream_t s);   // also clears zero[0 .. n_zero)
 void launch_gather_bounds(const LevelInfo *lev, int L, const int32_t *ids, const int32_t *total,
                           const int32_t *bad, int32_t *out, hipStream_t s);
 void launch_cell_ranges(const GeoParams &g, const LevelInfo *lev, const uint32_t *key, int64_t n,

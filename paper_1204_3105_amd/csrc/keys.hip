@@ -63,9 +63,12 @@ __global__ void k_bbox(const double *__restrict__ pts, int64_t n, double *__rest
     }
 }
 
-__global__ void k_bbox_final(const double *__restrict__ partial, int nparts, double *__restrict__ out)
+__global__ void k_bbox_final(const double *__restrict__ partial, int nparts, double *__restrict__ out,
+                             int32_t *__restrict__ zero)
 {
-    // One block of 256 threads reduces the partial boxes.
+    // One block of 256 threads reduces the partial boxes; it also clears
+    // the out-of-domain counter that the key kernel increments.
+    if (zero && threadIdx.x == 0) *zero = 0;
     double mnx = INFINITY, mxx = -INFINITY, mny = INFINITY, mxy = -INFINITY, bad = 0.0;
     for (int k = threadIdx.x; k < nparts; k += blockDim.x) {
         mnx = fmin(mnx, partial[5 * k]);
@@ -109,9 +112,9 @@ void launch_bbox(const double *pts, int64_t n, double *partial, int nblocks, hip
     hipLaunchKernelGGL(k_bbox, dim3(nblocks), dim3(256), 0, s, pts, n, partial);
 }
 
-void launch_bbox_final(const double *partial, int nparts, double *out4, hipStream_t s)
+void launch_bbox_final(const double *partial, int nparts, double *out4, int32_t *zero, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, partial, nparts, out4);
+    hipLaunchKernelGGL(k_bbox_final, dim3(1), dim3(256), 0, s, partial, nparts, out4, zero);
 }
 
 // ------------------------------------------------------------------ keys
@@ -257,9 +260,10 @@ __device__ int64_t key_tri(const GeoParams &g, double x, double y)
 
 __global__ void k_keys(GeoParams g, const double *__restrict__ pts, int64_t n,
                        uint32_t *__restrict__ key, int32_t *__restrict__ idx,
-                       int32_t *__restrict__ bad)
+                       int32_t *__restrict__ bad, int32_t *__restrict__ zero, int64_t n_zero)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n_zero) zero[i] = 0;   // the cell-flag map, cleared on the way
     if (i >= n) return;
     double x = pts[2 * i], y = pts[2 * i + 1];
     int64_t k;
@@ -278,12 +282,13 @@ __global__ void k_keys(GeoParams g, const double *__restrict__ pts, int64_t n,
 }
 
 void launch_keys(const GeoParams &g, const double *pts, int64_t n, uint32_t *key, int32_t *idx,
-                 int32_t *bad_count, hipStream_t s)
+                 int32_t *bad_count, int32_t *zero, int64_t n_zero, hipStream_t s)
 {
-    if (n <= 0) return;
-    int64_t nb = (n + 255) / 256;
+    const int64_t m = n > n_zero ? n : n_zero;
+    if (m <= 0) return;
+    int64_t nb = (m + 255) / 256;
     hipLaunchKernelGGL(k_keys, dim3((unsigned)nb), dim3(256), 0, s, g, pts, n, key, idx,
-                       bad_count);
+                       bad_count, zero, n_zero);
 }
 
 __global__ void k_gather_points(const double *__restrict__ pts, const int32_t *__restrict__ perm,

@@ -450,11 +450,13 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     double *bbp = take<double>(P, 5 * 2 * nbb, &err);
     if (err) return fail(FMM_E_NOMEM, "device allocation failed (bbox)");
     // The source and target partial boxes are reduced together.
+    int32_t *bad = take<int32_t>(P, 4, &err);   // out-of-domain count, cleared by the bbox pass
+    if (err) return fail(FMM_E_NOMEM, "device allocation failed (bbox)");
     launch_bbox(dsrc, n_src, bbp, nbb, s);
-    launch_bbox(dtgt, same ? 0 : n_tgt, bbp + 5 * nbb, nbb, s);
+    if (!same) launch_bbox(dtgt, n_tgt, bbp + 5 * nbb, nbb, s);
     Readback *rb = readback();
     if (!rb) return fail(FMM_E_DEVICE, "pinned readback buffer unavailable");
-    launch_bbox_final(bbp, 2 * nbb, (double *)rb->dev, s);
+    launch_bbox_final(bbp, same ? nbb : 2 * nbb, (double *)rb->dev, bad, s);
     FMM_HIP_CHECK(spin_wait(P->ev[10], s));
     double hb[5];
     memcpy(hb, (const void *)rb->host, sizeof(hb));
@@ -498,20 +500,10 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
         P->tx = take<double>(P, M, &err);
         P->ty = take<double>(P, M, &err);
     }
-    int32_t *bad = take<int32_t>(P, 4, &err);
     size_t rtmp = std::max(radix_tmp_bytes(N), radix_tmp_bytes(M));
     char *sort_tmp = take<char>(P, (int64_t)rtmp, &err);
     if (err) return fail(FMM_E_NOMEM, "device allocation failed (keys)");
-    FMM_HIP_CHECK(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
-    launch_keys(g, dsrc, N, P->skey, P->sperm, bad, s);
-    if (!same) launch_keys(g, dtgt, M, P->tkey, P->tperm, bad, s);
-    int bits = key_bits(g);
-    radix_sort(P->skey, P->sperm, N, bits, sort_tmp, s);
-    if (!same) radix_sort(P->tkey, P->tperm, M, bits, sort_tmp, s);
-    launch_gather_points(dsrc, P->sperm, N, P->sx, P->sy, s);
-    if (!same) launch_gather_points(dtgt, P->tperm, M, P->tx, P->ty, s);
-
-    // Levels: dense key spaces.
+    // Levels: dense key spaces; the key pass clears their occupancy flags.
     int64_t dense_total = 0;
     for (int l = 0; l <= g.L; ++l) {
         int64_t K = 1;
@@ -522,11 +514,19 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     }
     P->dense_total = dense_total;
     int32_t *flags = take<int32_t>(P, 2 * dense_total + 1, &err);
+    if (err) return fail(FMM_E_NOMEM, "device allocation failed (levels)");
+    launch_keys(g, dsrc, N, P->skey, P->sperm, bad, flags, dense_total, s);
+    if (!same) launch_keys(g, dtgt, M, P->tkey, P->tperm, bad, nullptr, 0, s);
+    int bits = key_bits(g);
+    radix_sort(P->skey, P->sperm, N, bits, sort_tmp, s);
+    if (!same) radix_sort(P->tkey, P->tperm, M, bits, sort_tmp, s);
+    launch_gather_points(dsrc, P->sperm, N, P->sx, P->sy, s);
+    if (!same) launch_gather_points(dtgt, P->tperm, M, P->tx, P->ty, s);
+
     P->dense = take<int32_t>(P, dense_total, &err);
     char *scan_tmp = take<char>(P, (int64_t)scan_tmp_bytes(std::max<int64_t>(dense_total, 256 * 1024)) + 4096, &err);
     int32_t *total = take<int32_t>(P, 4, &err);
     if (err) return fail(FMM_E_NOMEM, "device allocation failed (levels)");
-    FMM_HIP_CHECK(hipMemsetAsync(flags, 0, sizeof(int32_t) * dense_total, s));
     if (same) {
         launch_mark_cells(g, P->lev, P->skey, N, 3, flags, s);   // both occupancy bits at once
     } else {
@@ -581,8 +581,10 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     P->counts = take<int32_t>(P, 8, &err);
     if (err) return fail(FMM_E_NOMEM, "device allocation failed (cells)");
 
+    // Compaction also clears the root's local expansion: only a one-level
+    // tree reads a local expansion that no M2L writes.
     launch_compact(g, P->lev, dense_total, flags, ids, P->dense, P->cell_key, P->cell_occ, P->sb,
-                   P->se, same ? nullptr : P->tb, same ? nullptr : P->te, s);
+                   P->se, same ? nullptr : P->tb, same ? nullptr : P->te, P->lc, 2 * (P->p + 1), s);
     launch_cell_ranges(g, P->lev, P->skey, N, P->dense, P->sb, P->se, s);
     if (!same) launch_cell_ranges(g, P->lev, P->tkey, M, P->dense, P->tb, P->te, s);
     launch_cell_geometry(g, P->lev, P->n_cells, P->cell_key, P->dense, P->sb, P->se, P->tb, P->te,
@@ -592,8 +594,6 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     launch_near_items(P->lev, g.L, P->tb, P->te, ncount, s);
     scan_exclusive(ncount, ncount, P->lev[g.L].n, P->counts + 0, scan_tmp, s);
     launch_near_items_fill(P->lev, g.L, P->tb, P->te, ncount, P->work_near, s);
-    // Only a one-level tree reads a local expansion that no M2L writes.
-    FMM_HIP_CHECK(hipMemsetAsync(P->lc, 0, sizeof(double) * 2 * (P->p + 1), s));
     P->m2l_pm = m2l_pm_for(P->p);
     if (P->m2l_pm > 0 && g.L >= 1) {
         double *tab = take<double>(P, (int64_t)m2l_table_doubles(*P, P->m2l_pm), &err);

@@ -108,6 +108,44 @@ __global__ void k_scan_apply(const int32_t *__restrict__ in, int32_t *__restrict
     }
 }
 
+// One block of 1024 threads for short arrays (up to 32 Ki elements): the
+// array is read with coalesced loads (all in flight together) into LDS,
+// where thread t scans the 32 consecutive elements from 32 t after a block
+// scan of the run totals; the result leaves LDS with coalesced stores.  LDS
+// index i + i/32 keeps both access patterns free of bank conflicts.
+constexpr int kScanSmallRun = 32;
+constexpr int64_t kScanSmall = 1024 * kScanSmallRun;
+__global__ __launch_bounds__(1024) void k_scan_small(const int32_t *__restrict__ in, int32_t *__restrict__ out,
+                                                     int64_t n, int32_t *__restrict__ total)
+{
+    __shared__ int32_t sh[kScanSmall + kScanSmall / 32];
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < kScanSmallRun; ++k) {
+        const int i = k * 1024 + t;
+        sh[i + (i >> 5)] = i < n ? in[i] : 0;
+    }
+    __syncthreads();
+    int32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kScanSmallRun; ++k) acc += sh[33 * t + k];
+    int32_t tot;
+    int32_t off = block_excl_scan(acc, &tot);   // synchronizes the block
+#pragma unroll
+    for (int k = 0; k < kScanSmallRun; ++k) {
+        const int32_t v = sh[33 * t + k];
+        sh[33 * t + k] = off;
+        off += v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kScanSmallRun; ++k) {
+        const int i = k * 1024 + t;
+        if (i < n) out[i] = sh[i + (i >> 5)];
+    }
+    if (t == 0 && total) *total = tot;
+}
+
 size_t scan_tmp_bytes(int64_t n)
 {
     int64_t tiles = (n + kScanTile - 1) / kScanTile;
@@ -118,8 +156,11 @@ size_t scan_tmp_bytes(int64_t n)
 void scan_exclusive(const int32_t *in, int32_t *out, int64_t n, int32_t *total, void *tmp,
                     hipStream_t s)
 {
+    if (n <= kScanSmall) {
+        hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(1024), 0, s, in, out, n, total);
+        return;
+    }
     int64_t tiles = (n + kScanTile - 1) / kScanTile;
-    if (tiles == 0) tiles = 1;
     int32_t *sums = (int32_t *)tmp;
     hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)tiles), dim3(kScanThreads), 0, s, in, n,
                        sums);

@@ -109,9 +109,11 @@ __device__ __forceinline__ int level_of_cell(const Levels &s, int64_t gid)
 __global__ void k_compact(Levels s, const int32_t *__restrict__ flags, const int32_t *__restrict__ ids,
                           int64_t n, int32_t *__restrict__ dense, uint32_t *__restrict__ cell_key,
                           uint8_t *__restrict__ occ, int32_t *__restrict__ sb, int32_t *__restrict__ se,
-                          int32_t *__restrict__ tb, int32_t *__restrict__ te)
+                          int32_t *__restrict__ tb, int32_t *__restrict__ te, double *__restrict__ zero,
+                          int n_zero)
 {
     int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (j < n_zero) zero[j] = 0.0;   // cleared on the way (see launch_compact)
     if (j >= n) return;
     int32_t f = flags[j];
     if (!f) {
@@ -129,11 +131,13 @@ __global__ void k_compact(Levels s, const int32_t *__restrict__ flags, const int
 
 void launch_compact(const GeoParams &g, const LevelInfo *lev, int64_t dense_total,
                     const int32_t *flags, const int32_t *ids, int32_t *dense, uint32_t *cell_key,
-                    uint8_t *occ, int32_t *sb, int32_t *se, int32_t *tb, int32_t *te, hipStream_t s)
+                    uint8_t *occ, int32_t *sb, int32_t *se, int32_t *tb, int32_t *te, double *zero,
+                    int n_zero, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_compact, dim3((unsigned)((dense_total + 255) / 256)), dim3(256), 0, s,
+    const int64_t m = dense_total > n_zero ? dense_total : n_zero;
+    hipLaunchKernelGGL(k_compact, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
                        make_levels(g, lev), flags, ids, dense_total, dense, cell_key, occ, sb, se,
-                       tb, te);
+                       tb, te, zero, n_zero);
 }
 
 // out[l] = first cell id of level l (l = 0..L), out[L+1] = cell count,
