@@ -70,6 +70,8 @@ def parse():
                     help="skip timing the plain FP64 form (reported under extra by default)")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests in the serving stream (0 = skip the serving leg)")
+    ap.add_argument("--clustered-n", type=int, default=4 << 20,
+                    help="points per side of the clustered-input leg (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 512 MiB device copy first (HBM counter calibration)")
     ap.add_argument("--serve-load", type=float, default=0.7,
@@ -211,6 +213,50 @@ def serve_bench(F, nreq, load, leaf):
     }
 
 
+def clustered_leg(F, torch, orc, n, reps=3, nsample=64):
+    """Clustered sources, separate uniform targets (n each; 8 Gaussians,
+    sigma 0.02, N(0,1) strengths), eps 1e-6, mixed: the uniform-depth tree at
+    the mean-occupancy level and at the cost-model level (depth="cost"),
+    plan + evaluate wall time (median of reps), chosen level, and for the
+    cost rule the error on sampled targets against the oracle."""
+    from paper_1204_3105_amd import inputs
+    w = inputs.gaussian_mixture(n, n, seed=3)
+    dev = torch.device("cuda:0")
+    src = torch.tensor(w.xs + 1j * w.ys, dtype=torch.complex128, device=dev)
+    tgt = torch.tensor(w.xt + 1j * w.yt, dtype=torch.complex128, device=dev)
+    u = torch.tensor(w.u, dtype=torch.float64, device=dev)
+    out = torch.empty(n, dtype=torch.complex128, device=dev)
+    idx = inputs.subsample(n, nsample, 5)
+    res = {}
+    for t in ("quad", "sept", "tri"):
+        row = {}
+        for rule in ("mean", "cost"):
+            ts = []
+            for r in range(reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                plan = F.Plan(t, src=src, tgt=tgt, eps=1e-6, precision="mixed", depth=rule)
+                plan.eval(u, out=out)
+                torch.cuda.synchronize()
+                if r:
+                    ts.append((time.perf_counter() - t0) * 1e3)
+                inf = plan.info()
+                plan.close()
+            row[rule] = {"lmax": inf["lmax"], "ms": float(np.median(ts)), "n_near_pairs": inf["n_near_pairs"],
+                         "n_m2l_pairs": inf["n_m2l_pairs"]}
+            if rule == "cost":
+                g = orc.geom(t, inf["lmax"], *inf["geometry"])
+                ref = orc.fmm(g, inf["p"], w.xs, w.ys, w.u, w.xt[idx], w.yt[idx])
+                phi = out.cpu().numpy()[idx]
+                row[rule]["rel_l2_vs_oracle"] = float(np.linalg.norm(phi - ref) / np.linalg.norm(ref))
+        row["speedup"] = row["mean"]["ms"] / row["cost"]["ms"]
+        res[t] = row
+        print("bench: clustered %s: mean rule L=%d %.2f ms, cost rule L=%d %.2f ms" % (
+            t, row["mean"]["lmax"], row["mean"]["ms"], row["cost"]["lmax"], row["cost"]["ms"]),
+            file=sys.stderr, flush=True)
+    return res
+
+
 def m2l_mfma(infos, tilings):
     """M2L against the dense BF16 MFMA peak, per tiling: algorithmic flops
     (8 (p+1)^2 per E4 pair: a complex (p+1) x (p+1) matrix-vector product) and
@@ -310,6 +356,9 @@ def main():
         print("bench: serving p50 %.2f ms p99 %.2f ms" % (extra["serving"]["p50_ms"],
                                                           extra["serving"]["p99_ms"]),
               file=sys.stderr, flush=True)
+
+    if a.clustered_n > 0:
+        extra["clustered"] = clustered_leg(F, torch, oracle, a.clustered_n)
 
     cpu = None
     if not a.no_cpu_baseline:

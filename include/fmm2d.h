@@ -74,6 +74,17 @@ typedef enum {
 
 typedef struct fmm_plan_s *fmm_plan_t;
 
+/* Leaf-level rule when neither lmax nor a geometry is given.
+ * FMM_DEPTH_MEAN: the smallest level whose mean occupancy (points over the
+ *   bounding box's area in leaves) is at most leaf_size (the paper's uniform
+ *   per-cell population, Sec. 9).
+ * FMM_DEPTH_COST: for clustered inputs; starting from the mean rule's level
+ *   L0, the levels L0..L0+3 (base^level <= 2^24) are priced from the points'
+ *   occupancy histogram (near-field pairs, occupied leaves, M2L pairs) and
+ *   the cheapest is taken.  The tree is still the paper's uniform-depth tree;
+ *   one more short readback at plan time. */
+typedef enum { FMM_DEPTH_MEAN = 0, FMM_DEPTH_COST = 1 } fmm_depth_rule;
+
 /* Plan options.  Call fmm_options_default first, then override fields. */
 typedef struct {
     uint32_t struct_size;    /* sizeof(fmm_options)                           */
@@ -90,7 +101,8 @@ typedef struct {
                                 centroid and leaf circumradius                */
     void *stream;            /* hipStream_t for device-pointer calls          */
     int32_t device_pointers; /* 1 = all data pointers are device pointers     */
-    int32_t reserved;
+    int32_t depth_rule;      /* fmm_depth_rule, used when lmax < 0 and no
+                                explicit geometry (FMM_DEPTH_MEAN)            */
 } fmm_options;
 
 /* Read-only summary of a plan. */

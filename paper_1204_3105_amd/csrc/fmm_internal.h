@@ -151,6 +151,14 @@ struct Plan {
 void launch_bbox(const double *pts, int64_t n, double *partial, int nblocks, hipStream_t s);
 // Also sets *zero (if not null) to 0.
 void launch_bbox_final(const double *partial, int nparts, double *out4, int32_t *zero, hipStream_t s);
+// Depth statistics: occupancy histogram of every stride-th point's key at a
+// trial leaf level; per coarser level, sum over cells of sources x targets
+// and the occupied-cell counts (out[0..2], accumulated); a short device copy.
+void launch_depth_hist(const GeoParams &g, const double *pts, int64_t n, int64_t stride, uint32_t *hist,
+                       hipStream_t s);
+void launch_depth_stats(const uint32_t *hs, const uint32_t *ht, int64_t ncells, int64_t span,
+                        unsigned long long *out, hipStream_t s);
+void launch_copy_u64(const unsigned long long *a, int n, unsigned long long *b, hipStream_t s);
 // Also clears zero[0 .. n_zero).
 void launch_keys(const GeoParams &g, const double *pts, int64_t n, uint32_t *key, int32_t *idx,
                  int32_t *bad_count, int32_t *zero, int64_t n_zero, hipStream_t s);

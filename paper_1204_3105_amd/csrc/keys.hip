@@ -258,6 +258,82 @@ __device__ int64_t key_tri(const GeoParams &g, double x, double y)
     return key;
 }
 
+__device__ __forceinline__ int64_t key_of(const GeoParams &g, double x, double y)
+{
+    if (g.tiling == kQuad) return key_quad(g, x, y);
+    if (g.tiling == kSept) return key_sept(g, x, y);
+    return key_tri(g, x, y);
+}
+
+// ------------------------------------------------------------------ depth statistics
+// Occupancy histogram at a trial leaf level (one counter per key) of every
+// stride-th point.
+__global__ void k_depth_hist(GeoParams g, const double *__restrict__ pts, int64_t n, int64_t stride,
+                             uint32_t *__restrict__ hist)
+{
+    const int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * stride;
+    if (i >= n) return;
+    const int64_t k = key_of(g, pts[2 * i], pts[2 * i + 1]);
+    if (k >= 0) atomicAdd(&hist[k], 1u);
+}
+
+// For one coarser level: cell c covers the trial-level keys [c span, (c+1)
+// span) (keys are digit prefixes).  Accumulates sum_c s_c t_c, the source-
+// and the target-occupied cell counts (64-bit integer atomics: exact).
+__global__ __launch_bounds__(256) void k_depth_stats(const uint32_t *__restrict__ hs, const uint32_t *__restrict__ ht,
+                                                      int64_t ncells, int64_t span, unsigned long long *__restrict__ out)
+{
+    __shared__ unsigned long long part[3][4];
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    unsigned long long v[3] = {0, 0, 0};
+    if (c < ncells) {
+        unsigned long long s = 0, t = 0;
+        for (int64_t j = c * span; j < (c + 1) * span; ++j) {
+            s += hs[j];
+            t += ht[j];
+        }
+        v[0] = s * t;
+        v[1] = s ? 1 : 0;
+        v[2] = t ? 1 : 0;
+    }
+    // block sums first: three atomics per block
+    for (int q = 0; q < 3; ++q) {
+        for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
+        if ((threadIdx.x & 63) == 0) part[q][threadIdx.x >> 6] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        unsigned long long a = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) a += part[threadIdx.x][w];
+        if (a) atomicAdd(&out[threadIdx.x], a);
+    }
+}
+
+__global__ void k_copy_u64(const unsigned long long *__restrict__ a, int n, unsigned long long *__restrict__ b)
+{
+    if ((int)threadIdx.x < n) b[threadIdx.x] = a[threadIdx.x];
+}
+
+void launch_depth_hist(const GeoParams &g, const double *pts, int64_t n, int64_t stride, uint32_t *hist,
+                       hipStream_t s)
+{
+    if (n <= 0) return;
+    const int64_t m = (n + stride - 1) / stride;
+    hipLaunchKernelGGL(k_depth_hist, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, g, pts, n, stride, hist);
+}
+
+void launch_depth_stats(const uint32_t *hs, const uint32_t *ht, int64_t ncells, int64_t span,
+                        unsigned long long *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_depth_stats, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, s, hs, ht, ncells,
+                       span, out);
+}
+
+void launch_copy_u64(const unsigned long long *a, int n, unsigned long long *b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy_u64, dim3(1), dim3(256), 0, s, a, n, b);
+}
+
 __global__ void k_keys(GeoParams g, const double *__restrict__ pts, int64_t n,
                        uint32_t *__restrict__ key, int32_t *__restrict__ idx,
                        int32_t *__restrict__ bad, int32_t *__restrict__ zero, int64_t n_zero)
@@ -265,14 +341,7 @@ __global__ void k_keys(GeoParams g, const double *__restrict__ pts, int64_t n,
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n_zero) zero[i] = 0;   // the cell-flag map, cleared on the way
     if (i >= n) return;
-    double x = pts[2 * i], y = pts[2 * i + 1];
-    int64_t k;
-    if (g.tiling == kQuad)
-        k = key_quad(g, x, y);
-    else if (g.tiling == kSept)
-        k = key_sept(g, x, y);
-    else
-        k = key_tri(g, x, y);
+    int64_t k = key_of(g, pts[2 * i], pts[2 * i + 1]);
     if (k < 0) {
         atomicAdd(bad, 1);
         k = 0;

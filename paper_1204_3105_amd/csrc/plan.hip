@@ -425,6 +425,89 @@ static float elapsed(hipEvent_t a, hipEvent_t b)
 }
 
 // ------------------------------------------------------------ plan
+// Depth by a cost model (fmm_options.depth_rule = FMM_DEPTH_COST).  From the
+// points' occupancy histogram at a trial level Lc = L0 + 2 (L0 from the mean
+// rule; base^Lc <= 2^24), each candidate leaf level l in [L0, Lc] is priced
+// as a uniform-depth tree: near-field pairs ~ (near slots) sum_c s_c t_c over
+// the level's cells (from every m-th point, m making at most 2^20 samples,
+// scaled back), a cost per occupied leaf (near-field item, L2P, shifts),
+// and M2L pairs ~ (E4 slots) min(source cells, target cells) per level added
+// below L0; the cheapest level wins (ties: the shallower).  The weights are
+// per-unit times measured on this GPU for the mixed and the FP64 forms.
+static int depth_trial_level(int tiling, int L0)
+{
+    const int cap = tiling == kSept ? std::min(8, (int)(sizeof(kSeptInscribed) / sizeof(double)) - 1) : 12;
+    return std::max(L0, std::min(L0 + 2, cap));
+}
+
+// Scratch bytes of the depth statistics (the histogram, then 3 counters per
+// level); the plan lends its sort scratch, which the sort uses later.
+static size_t depth_scratch_bytes(int tiling, int L0, bool same)
+{
+    const int Lc = depth_trial_level(tiling, L0);
+    int64_t K = 1;
+    for (int i = 0; i < Lc; ++i) K *= base_of(tiling);
+    return sizeof(uint32_t) * (size_t)K * (same ? 1 : 2) + 256 + sizeof(unsigned long long) * 3 * (Lc - L0 + 1);
+}
+
+static fmm_status depth_by_cost(PlanImpl *P, int tiling, const BBox &bb, int64_t N, int64_t M, const double *dsrc,
+                                const double *dtgt, bool same, const fmm_options &o, int p, int L0, Readback *rb,
+                                char *scratch, int *out_L)
+{
+    *out_L = L0;
+    hipStream_t s = P->stream;
+    const int base = base_of(tiling);
+    const int Lc = depth_trial_level(tiling, L0);
+    if (Lc <= L0) return FMM_OK;
+    GeoParams gc;
+    choose_geometry(tiling, bb, std::max(N, M), o.leaf_size, Lc, gc);
+    int64_t K = 1;
+    for (int i = 0; i < Lc; ++i) K *= base;
+    const int nl = Lc - L0 + 1;
+    const size_t hb = sizeof(uint32_t) * (size_t)K * (same ? 1 : 2), ab = sizeof(unsigned long long) * 3 * nl;
+    uint32_t *hist = (uint32_t *)scratch;
+    unsigned long long *acc = (unsigned long long *)(scratch + ((hb + 255) & ~(size_t)255));
+    uint32_t *hs = hist, *ht = same ? hist : hist + K;
+    // At most 2^20 sampled points per side (every m-th): counts are scaled
+    // back by m; occupied cells are those with a sampled point.
+    const int64_t ms = std::max<int64_t>(1, (N + (1 << 20) - 1) >> 20);
+    const int64_t mt = same ? ms : std::max<int64_t>(1, (M + (1 << 20) - 1) >> 20);
+    hipError_t e = hipMemsetAsync(hist, 0, hb, s);
+    if (e == hipSuccess) e = hipMemsetAsync(acc, 0, ab, s);
+    if (e == hipSuccess) {
+        launch_depth_hist(gc, dsrc, N, ms, hs, s);
+        if (!same) launch_depth_hist(gc, dtgt, M, mt, ht, s);
+        int64_t cells = 1, span = K;
+        for (int l = 0; l < L0; ++l) cells *= base, span /= base;
+        for (int l = L0; l <= Lc; ++l, cells *= base, span /= base)
+            launch_depth_stats(hs, ht, cells, span, acc + 3 * (l - L0), s);
+        launch_copy_u64(acc, 3 * nl, (unsigned long long *)rb->dev, s);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = spin_wait(P->ev[11], s);
+    if (e != hipSuccess) return fail(FMM_E_DEVICE, std::string("depth statistics failed: ") + hipGetErrorString(e));
+    unsigned long long st[3 * (kMaxL + 1)];
+    memcpy(st, (const void *)rb->host, sizeof(unsigned long long) * 3 * nl);
+    const ListTables t = build_tables(tiling);
+    const bool mixed = P->precision == FMM_PREC_MIXED;
+    const double q = (p + 1) / 23.0;
+    const double w_pair = mixed ? 1.1e-12 : 4.5e-12;
+    const double w_leaf = mixed ? 2.0e-9 : 2.5e-9;
+    const double w_m2l = (mixed ? 1.5e-10 : 1.0e-9) * q * q;
+    double best = 0.0, m2l = 0.0;
+    for (int l = L0; l <= Lc; ++l) {
+        const double pairs = (double)t.near_width * (double)st[3 * (l - L0)] * (double)ms * (double)mt;
+        const double cs = (double)st[3 * (l - L0) + 1], ct = (double)st[3 * (l - L0) + 2];
+        if (l > L0) m2l += (double)t.e4_width * std::min(cs, ct);
+        const double c = w_pair * pairs + w_leaf * (cs + ct) + w_m2l * m2l;
+        if (l == L0 || c < best) {
+            best = c;
+            *out_L = l;
+        }
+    }
+    return FMM_OK;
+}
+
 static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t n_src,
                              const double *tgt, int64_t n_tgt, double eps, const fmm_options &o)
 {
@@ -464,6 +547,7 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     if (n_src + n_tgt == 0) hb[0] = hb[2] = 0.0, hb[1] = hb[3] = 1.0;
 
     GeoParams &g = P->geo;
+    char *sort_tmp = nullptr;   // sort scratch (lent to the depth statistics first)
     if (o.has_geometry) {
         if (o.lmax < 0 || o.lmax > kMaxL) return fail(FMM_E_INVALID, "explicit geometry needs 0 <= lmax <= 16");
         if (!(o.geometry[2] > 0.0) || !isfinite(o.geometry[0]) || !isfinite(o.geometry[1]))
@@ -477,6 +561,17 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     } else {
         BBox bb{hb[0], hb[1], hb[2], hb[3]};
         choose_geometry(tiling, bb, std::max(n_src, n_tgt), o.leaf_size, o.lmax, g);
+        if (o.depth_rule == FMM_DEPTH_COST && o.lmax < 0 && n_src > 0 && n_tgt > 0) {
+            const int pp = o.p > 0 ? std::min(o.p, kMaxP) : order_for(tiling, eps);
+            const size_t need = std::max(radix_tmp_bytes(std::max(n_src, n_tgt)), depth_scratch_bytes(tiling, g.L, same));
+            sort_tmp = take<char>(P, (int64_t)need, &err);
+            if (err) return fail(FMM_E_NOMEM, "device allocation failed (depth statistics)");
+            int L = g.L;
+            const fmm_status st =
+                depth_by_cost(P, tiling, bb, n_src, n_tgt, dsrc, dtgt, same, o, pp, g.L, rb, sort_tmp, &L);
+            if (st != FMM_OK) return st;
+            if (L != g.L) choose_geometry(tiling, bb, std::max(n_src, n_tgt), o.leaf_size, L, g);
+        }
     }
     if (g.L > kMaxL || (tiling == kSept && g.L > 11))
         return fail(FMM_E_INVALID, "tree too deep for 32-bit keys");
@@ -500,8 +595,7 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
         P->tx = take<double>(P, M, &err);
         P->ty = take<double>(P, M, &err);
     }
-    size_t rtmp = std::max(radix_tmp_bytes(N), radix_tmp_bytes(M));
-    char *sort_tmp = take<char>(P, (int64_t)rtmp, &err);
+    if (!sort_tmp) sort_tmp = take<char>(P, (int64_t)std::max(radix_tmp_bytes(N), radix_tmp_bytes(M)), &err);
     if (err) return fail(FMM_E_NOMEM, "device allocation failed (keys)");
     // Levels: dense key spaces; the key pass clears their occupancy flags.
     int64_t dense_total = 0;
@@ -746,6 +840,7 @@ fmm_status fmm_plan(fmm_tiling tiling, const double *src, int64_t n_src, const d
     if (o.p > kMaxP) return fail(FMM_E_INVALID, "p above the supported maximum (60)");
     if (o.lmax > kMaxL) return fail(FMM_E_INVALID, "lmax above the supported maximum (16)");
     if (o.precision < 0 || o.precision > 2) return fail(FMM_E_INVALID, "bad precision");
+    if (o.depth_rule != FMM_DEPTH_MEAN && o.depth_rule != FMM_DEPTH_COST) return fail(FMM_E_INVALID, "bad depth_rule");
     PlanImpl *P = new PlanImpl();
     P->device_pointers = o.device_pointers != 0;
     P->n_src = n_src;

@@ -104,3 +104,15 @@ def test_direct_validation(F):
     assert lib.fmm_direct(pts, 2, pts, 2, u, phi, C.byref(o2)) == 1
     # no targets: nothing to do, no device needed
     assert lib.fmm_direct(pts, 2, None, 0, u, None, None) == 0
+
+
+def test_depth_rule_option(F):
+    lib = F.lib()
+    o = F.Options()
+    assert lib.fmm_options_default(C.byref(o)) == 0
+    assert o.depth_rule == 0
+    o.depth_rule = 5
+    plan = C.c_void_p()
+    pts = (C.c_double * 4)(0.1, 0.2, 0.3, 0.4)
+    assert lib.fmm_plan(0, pts, 2, pts, 2, 1e-6, C.byref(o), C.byref(plan)) == 1
+    assert b"depth" in lib.fmm_last_error()
