@@ -99,6 +99,66 @@ __device__ __forceinline__ double atan2_f64(double y, double x)
 }
 
 
+// ln(r2) and atan2(y, x) together, as ln_f64 and atan2_f64 but with one
+// reciprocal for both divisions: with D = (m + 1) den, R = 1/D (hardware
+// reciprocal, two Newton steps), s = (m - 1) den R and t = num (m + 1) R;
+// each quotient is within a few ulp, far below what the FP64 near field needs.
+__device__ __forceinline__ void ln_atan2_f64(double r2, double y, double x, double &lnr2, double &at)
+{
+    int e;
+    double m = frexp(r2, &e);
+    const bool lo = m < kSqrtHalf;
+    m = lo ? 2.0 * m : m;
+    e = lo ? e - 1 : e;
+    const double ax = fabs(x), ay = fabs(y);
+    const double mn = fmin(ax, ay), mx = fmax(ax, ay);
+    const bool red = mn > kTanPi12 * mx;
+    const double num = red ? fma(-kInvSqrt3, mx, mn) : mn;
+    const double den = red ? fma(kInvSqrt3, mn, mx) : mx;
+    const double mp1 = m + 1.0;
+    const double D = mp1 * den;
+    double R = __builtin_amdgcn_rcp(D);
+    R = fma(R, fma(-D, R, 1.0), R);
+    R = fma(R, fma(-D, R, 1.0), R);
+    const double s = ((m - 1.0) * den) * R;
+    const double t = (num * mp1) * R;
+    // ln r2 = e ln 2 + 2 atanh(s)
+    const double z = s * s;
+    double p = 1.0 / 21.0;
+    p = fma(p, z, 1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    const double lm = 2.0 * s + 2.0 * s * (z * p);
+    const double de = (double)e;
+    lnr2 = fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
+    // atan t, then the octant
+    const double w = t * t;
+    double q = -1.0 / 27.0;
+    q = fma(q, w, 1.0 / 25.0);
+    q = fma(q, w, -1.0 / 23.0);
+    q = fma(q, w, 1.0 / 21.0);
+    q = fma(q, w, -1.0 / 19.0);
+    q = fma(q, w, 1.0 / 17.0);
+    q = fma(q, w, -1.0 / 15.0);
+    q = fma(q, w, 1.0 / 13.0);
+    q = fma(q, w, -1.0 / 11.0);
+    q = fma(q, w, 1.0 / 9.0);
+    q = fma(q, w, -1.0 / 7.0);
+    q = fma(q, w, 1.0 / 5.0);
+    q = fma(q, w, -1.0 / 3.0);
+    double a = fma(t * w, q, t);
+    a = red ? kPi6Hi + (kPi6Lo + a) : a;
+    a = (ay > ax) ? kPi2Hi + (kPi2Lo - a) : a;
+    a = (x < 0.0) ? kPiHi + (kPiLo - a) : a;
+    at = (y < 0.0) ? -a : a;
+}
+
 // One wave per work item, laid out as the FP32 kernel: g = min(near slots,
 // 64/m) groups of m target lanes, group q summing the q-th of g equal slices
 // of the item's sources (listed cell after cell) in rounds of LDS-staged
@@ -193,8 +253,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 3 : 
                     const double dx = y0 - sx[j], dy = y1 - sy[j];
                     const double r2 = dx * dx + dy * dy;
                     const bool live = r2 > 0.0;
-                    const double lg = ln_f64(live ? r2 : 1.0);
-                    const double at = atan2_f64(dy, live ? dx : 1.0);
+                    double lg, at;
+                    ln_atan2_f64(live ? r2 : 1.0, dy, live ? dx : 1.0, lg, at);
                     re = fma(live ? su[j] : 0.0, 0.5 * lg, re);
                     im = fma(live ? su[j] : 0.0, at, im);
                     if (FIELD) {
@@ -204,12 +264,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 3 : 
                     }
                 }
             } else {
-                for (int j = 0; j < padn; ++j) {
+#pragma unroll 2
+                for (int j = 0; j < padn; ++j) {   // padn is a multiple of 8
                     const double dx = y0 - sx[j], dy = y1 - sy[j];
                     const double u = su[j];
                     const double r2 = dx * dx + dy * dy;
-                    re = fma(u, 0.5 * ln_f64(r2), re);
-                    im = fma(u, atan2_f64(dy, dx), im);
+                    double lg, at;
+                    ln_atan2_f64(r2, dy, dx, lg, at);
+                    re = fma(u, 0.5 * lg, re);
+                    im = fma(u, at, im);
                     if (FIELD) {
                         const double w = div_f64(u, r2);
                         fr = fma(w, dx, fr);
