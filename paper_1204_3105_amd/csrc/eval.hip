@@ -266,7 +266,8 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
     }
     hipEventRecord(ev[1], s);
 
-    // L2L, step k: level 2 + k.
+    // L2L, step k: level 2 + k; for the base-4 tilings up to the level above
+    // the leaves (L2P shifts the leaves' parents' expansions itself).
     for (int l = 2; l <= maxL; ++l)
         for (int pm : pms) {
             auto f = [&](const BatchMap &m) {
@@ -274,7 +275,9 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
                 else batch_l2l_lanes(jobs_dev, m, pm, s);
             };
             for (int i = 0; i < n; ++i)
-                if (plans[i]->geo.L >= l && shift_pm(*plans[i]) == pm) Lc.add(i, l, plans[i]->lev[l].n, f);
+                if ((plans[i]->geo.L > l || (plans[i]->geo.L == l && base_of(plans[i]->geo.tiling) != 4)) &&
+                    shift_pm(*plans[i]) == pm)
+                    Lc.add(i, l, plans[i]->lev[l].n, f);
             go(f);
         }
     hipEventRecord(ev[2], s);

@@ -319,7 +319,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 3 : 
 }
 
 // L2P: phi (caller's order) = near sum (sorted order) + the target leaf's
-// local expansion, FP64 Horner (same items).  With FIELD also the field:
+// local expansion, FP64 Horner (same items).  For the base-4 tilings, in a
+// tree of two or more levels, the leaf level's L2L is done here too: the leaf's row (written by
+// M2L) gets its parent's local expansion shifted to the leaf's centre,
+//   b~_m += rho^m sum_{k>=m} C(k, m) w^(k-m) b~par_k,
+// w = (c_leaf - c_parent)/ell_(L-1), rho = ell_L/ell_(L-1) (lane m, powers
+// of w and the parent row in LDS), which saves that level's launch and a
+// pass over the leaves' rows.  With FIELD also the field:
 // near field sum + the expansion's derivative (Horner carries both; the
 // radius scaling contributes a factor 1/ell).
 // The leaf's coefficient row is staged in LDS by the whole wave first, so the
@@ -327,8 +333,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 3 : 
 template <bool FIELD>
 __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
-    static_assert(kChunk <= 64, "one item per wave");
+    static_assert(kChunk <= 64 && kMaxP + 1 <= 64, "one item per wave, a lane per coefficient");
     __shared__ double row[2 * (kMaxP + 1)];
+    __shared__ double bpr[kMaxP + 1], bpi[kMaxP + 1], wpr[kMaxP + 1], wpi[kMaxP + 1];
     const int lane = threadIdx.x;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
         const int e = batch_entry(bm, item);
@@ -354,9 +361,45 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
         }
         const int32_t te = J.te[gid];
         const double cx = J.cx[gid], cy = J.cy[gid];
+        const bool shift = J.L >= 2 && J.base == 4;   // the septree's L2L keeps its lane form
         __syncthreads();
         if (lane < 2 * P1) row[lane] = b[lane];
         if (lane + 64 < 2 * P1) row[lane + 64] = b[lane + 64];
+        if (shift) {
+            // the leaf level's L2L
+            const int32_t par = J.parent[gid];
+            const double pinv = 1.0 / J.scale[J.L - 1];
+            if (lane < P1) {
+                bpr[lane] = J.lc[(int64_t)par * 2 * P1 + 2 * lane];
+                bpi[lane] = J.lc[(int64_t)par * 2 * P1 + 2 * lane + 1];
+            }
+            if (lane == 0) {
+                const double wr = (cx - J.cx[par]) * pinv, wi = (cy - J.cy[par]) * pinv;
+                double qr = 1.0, qi = 0.0;
+                for (int k = 0; k <= J.p; ++k) {
+                    wpr[k] = qr;
+                    wpi[k] = qi;
+                    const double nr = fma(qr, wr, -qi * wi), ni = fma(qr, wi, qi * wr);
+                    qr = nr;
+                    qi = ni;
+                }
+            }
+            __syncthreads();
+            if (lane < P1) {
+                double sr = 0.0, si = 0.0;
+                for (int k = lane; k <= J.p; ++k) {
+                    const double c = J.binom[k * kBinomStride + lane];
+                    const double ar = bpr[k], ai = bpi[k], xr = wpr[k - lane], xi = wpi[k - lane];
+                    sr = fma(c, fma(ar, xr, -ai * xi), sr);
+                    si = fma(c, fma(ar, xi, ai * xr), si);
+                }
+                const double rho = J.scale[J.L] * pinv;
+                double rm = 1.0;
+                for (int j = 0; j < lane; ++j) rm *= rho;
+                row[2 * lane] = fma(sr, rm, row[2 * lane]);
+                row[2 * lane + 1] = fma(si, rm, row[2 * lane + 1]);
+            }
+        }
         __syncthreads();
         if (!inb || t >= te) continue;
         const double inv = 1.0 / J.scale[J.L];
