@@ -39,6 +39,7 @@ struct EvalJob {
     const __bf16 *mix_tab;
     const int32_t *mix_tiles, *mix_list;
     __bf16 *mix_b;   // split multipoles (mixed M2L B operands)
+    int mix_split;   // 1: P2M and the block-form M2M write mix_b as they write the multipoles
     // Device counts written at plan time: [0] near-field items, [1] mixed M2L
     // tiles.  Launches are sized by host upper bounds; kernels stop here.
     const int32_t *counts;
@@ -82,6 +83,30 @@ constexpr int kNearWavesPerCU = 128;
 // not slowed to the near field's share of each SIMD; the near field fills
 // the remaining issue slots.
 __device__ __forceinline__ void far_field_priority() { __builtin_amdgcn_s_setprio(2); }
+
+// BF16x3 split of an FP32 value: x = h + m + l (24 significand bits).
+__device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l)
+{
+    h = (__bf16)x;
+    const float r1 = x - (float)h;
+    m = (__bf16)r1;
+    const float r2 = r1 - (float)m;
+    l = (__bf16)r2;
+}
+
+// The mixed M2L's B operand of one cell: value i (0 <= i < 32 KB) of the
+// real coefficient vector (Re, Im of a~_1 .. a~_p, zero beyond 2p), split in
+// three and stored in the layout [cell][k-block][part][lane group q] bf16x8.
+__device__ __forceinline__ void store_split(__bf16 *mix_b, int64_t cell, int KB, int i, double v)
+{
+    const int kb = i / 32, q = (i % 32) / 8, j = i % 8;
+    __bf16 h, m, l;
+    split3((float)v, h, m, l);
+    __bf16 *o = mix_b + ((cell * KB + kb) * 12 + q) * 8 + j;
+    o[0] = h;
+    o[32] = m;
+    o[64] = l;
+}
 
 inline unsigned persistent_grid(int64_t items, int per_cu)
 {

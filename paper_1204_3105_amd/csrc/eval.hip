@@ -90,6 +90,7 @@ EvalJob make_job(const Plan &P)
         mixed_pointers(P, &J.mix_tab, &J.mix_tiles, &J.mix_list, &J.mix_b, &MT, &KB);
         J.MT = MT;
         J.KB = KB;
+        J.mix_split = P.mixed_tiles > 0 && base_of(P.geo.tiling) == 4 ? 1 : 0;
     }
     return J;
 }
@@ -224,6 +225,7 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
         for (int i = 0; i < n; ++i) {
             const Plan &P = *plans[i];
             if (P.precision != FMM_PREC_MIXED || P.mixed_tiles == 0) continue;
+            if (base_of(P.geo.tiling) == 4) continue;   // P2M and M2M wrote the splits
             Lc.add(i, 0, (P.n_cells - P.lev[1].cell_off) * 4 * ((2 * P.p + 31) / 32), f);
         }
         go(f);

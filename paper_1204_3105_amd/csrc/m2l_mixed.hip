@@ -83,15 +83,6 @@ struct SlotCounts {
     int v[kMaxGroups];
 };
 
-__device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l)
-{
-    h = (__bf16)x;
-    const float r1 = x - (float)h;
-    m = (__bf16)r1;
-    const float r2 = r1 - (float)m;
-    l = (__bf16)r2;
-}
-
 // Build the split matrices: block per (table level, group, slot, mt, kb),
 // lane per MFMA lane.
 __global__ __launch_bounds__(64) void k_build_mixed_tables(int p, int MT, int KB, int G, int S, int pm,
