@@ -51,6 +51,7 @@ static fmm_status fail(fmm_status st, const std::string &msg)
 struct Fence {
     hipEvent_t ev = nullptr;
     uint64_t id = 0;
+    hipStream_t stream = nullptr;   // the stream the event was recorded on
     ~Fence()
     {
         if (ev) hipEventDestroy(ev);
@@ -89,12 +90,21 @@ void *dev_alloc(size_t bytes, int *err, std::vector<uint64_t> *waited, hipStream
     std::shared_ptr<Fence> fence;
     {
         std::lock_guard<std::mutex> lk(g_pool_mu);
-        int best = -1;
+        // Among blocks of a fitting size, prefer one that needs no wait (no
+        // fence, a fence on this stream, or one already passed), so plans on
+        // different streams do not wait for each other's work; then the
+        // smallest.
+        int best = -1, best_rank = 3;
         for (int i = 0; i < (int)g_pool.size(); ++i) {
             const PoolBlock &b = g_pool[i];
-            if (b.device == dev && b.bytes >= bytes && b.bytes <= 2 * bytes &&
-                (best < 0 || b.bytes < g_pool[best].bytes))
+            if (b.device != dev || b.bytes < bytes || b.bytes > 2 * bytes) continue;
+            int rank = 0;
+            if (b.fence && !(waited && b.fence->stream == stream))
+                rank = hipEventQuery(b.fence->ev) == hipSuccess ? 1 : 2;
+            if (best < 0 || rank < best_rank || (rank == best_rank && b.bytes < g_pool[best].bytes)) {
                 best = i;
+                best_rank = rank;
+            }
         }
         if (best >= 0) {
             p = g_pool[best].p;
@@ -283,6 +293,7 @@ static void release(PlanImpl *P)
     std::shared_ptr<Fence> fence;
     if (!P->own_stream && !P->allocs.empty()) {
         fence = std::make_shared<Fence>();
+        fence->stream = P->stream;
         if (hipEventCreateWithFlags(&fence->ev, hipEventDisableTiming) != hipSuccess ||
             hipEventRecord(fence->ev, P->stream) != hipSuccess) {
             (void)hipGetLastError();
@@ -305,6 +316,7 @@ static void release(PlanImpl *P)
 static void put_fenced(void *p, size_t bytes, hipStream_t s)
 {
     auto fence = std::make_shared<Fence>();
+    fence->stream = s;
     if (hipEventCreateWithFlags(&fence->ev, hipEventDisableTiming) != hipSuccess ||
         hipEventRecord(fence->ev, s) != hipSuccess) {
         (void)hipGetLastError();
