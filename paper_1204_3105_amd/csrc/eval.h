@@ -45,6 +45,11 @@ struct EvalJob {
     const int32_t *counts;
     double *phi;    // output, caller's target order, 2 n_tgt doubles
     double *nsum;   // near-field sums, sorted target order, 2 n_tgt doubles
+    // Second-side near sums of the symmetric near field (targets = sources,
+    // mixed): one FP32 (re, im) per (point, lower neighbour, its chunk), at
+    // [((near slot - 1) * kSymChunks + chunk) * n_tgt + point]; null when
+    // the plan cannot take that path.
+    float2 *bside;
 };
 
 struct BatchMap {
@@ -130,6 +135,7 @@ void batch_split_mp(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_near_fp64(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_l2p(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_near_mixed(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
+void batch_near_mixed_sym(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 
 // Host view of one plan for batching: its descriptor (host copy) and the
 // device copy.

@@ -85,6 +85,7 @@ EvalJob make_job(const Plan &P)
     J.binom = P.binom;
     J.phi = P.phi_int;
     J.nsum = P.nsum;
+    J.bside = P.bside;
     if (P.precision == FMM_PREC_MIXED && P.mixed) {
         int MT, KB;
         mixed_pointers(P, &J.mix_tab, &J.mix_tiles, &J.mix_list, &J.mix_b, &MT, &KB);
@@ -187,9 +188,17 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
                 if (plans[i]->precision != FMM_PREC_MIXED) Ls.add(i, 0, plans[i]->n_work_near, f);
             if (Ls.m.n > 0) f(Ls.m);
             Ls.reset();
+            // mixed: the symmetric form where the targets are the sources
+            // (not for the field, which L2P then reads without second sides)
+            auto sym = [&](const Plan &P) { return P.bside != nullptr && nfield_single == nullptr; };
+            auto gs = [&](const BatchMap &m) { batch_near_mixed_sym(jobs_dev, m, side); };
+            for (int i = 0; i < n; ++i)
+                if (plans[i]->precision == FMM_PREC_MIXED && sym(*plans[i])) Ls.add(i, 0, plans[i]->n_work_near, gs);
+            if (Ls.m.n > 0) gs(Ls.m);
+            Ls.reset();
             auto g = [&](const BatchMap &m) { batch_near_mixed(jobs_dev, m, side); };
             for (int i = 0; i < n; ++i)
-                if (plans[i]->precision == FMM_PREC_MIXED) Ls.add(i, 0, plans[i]->n_work_near, g);
+                if (plans[i]->precision == FMM_PREC_MIXED && !sym(*plans[i])) Ls.add(i, 0, plans[i]->n_work_near, g);
             if (Ls.m.n > 0) g(Ls.m);
         }
         hipEventRecord(ev[6], side);

@@ -30,6 +30,9 @@ constexpr int kMaxSlots = 42;     // largest E4 list (septree)
 constexpr int kNearSlots = 13;    // largest closed neighbourhood (triangles)
 constexpr int kMaxGroups = 8;     // M2L target groups (triangle: 4 types x 2)
 constexpr int kChunk = 64;        // targets per near-field work item (at most)
+// A leaf with at most this many chunks of kChunk targets evaluates the pairs
+// with its higher-indexed neighbours for both sides (mixed, targets = sources).
+constexpr int kSymChunks = 2;
 
 enum Tiling { kQuad = 0, kSept = 1, kTri = 2 };
 
@@ -96,6 +99,9 @@ struct Plan {
     float *txl = nullptr, *tyl = nullptr;
     double *su = nullptr;                   // strengths in sorted order
     float *suf = nullptr;
+    // mixed precision with targets = sources: the symmetric near field's
+    // second-side sums, [(near slot - 1) * kSymChunks + chunk][point]
+    float2 *bside = nullptr;
 
     // cells
     LevelInfo lev[kMaxL + 1]{};

@@ -336,6 +336,7 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
     static_assert(kChunk <= 64 && kMaxP + 1 <= 64, "one item per wave, a lane per coefficient");
     __shared__ double row[2 * (kMaxP + 1)];
     __shared__ double bpr[kMaxP + 1], bpi[kMaxP + 1], wpr[kMaxP + 1], wpi[kMaxP + 1];
+    __shared__ int8_t bsn[kNearSlots];   // chunks of each lower neighbour that wrote second sides
     const int lane = threadIdx.x;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
         const int e = batch_entry(bm, item);
@@ -362,7 +363,20 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
         const int32_t te = J.te[gid];
         const double cx = J.cx[gid], cy = J.cy[gid];
         const bool shift = J.L >= 2 && J.base == 4;   // the septree's L2L keeps its lane form
+        // With the symmetric near field, each lower neighbour (by cell id)
+        // with at most kSymChunks chunks left this leaf's second-side sums,
+        // one per chunk of it.
+        const bool two = J.bside != nullptr && bm.nfield == nullptr;
         __syncthreads();
+        if (two && lane < J.nw) {
+            int nch = 0;
+            const int32_t c = lane ? J.near[li * J.nw + lane] : -1;
+            if (c >= 0 && c < gid) {
+                nch = (J.se[c] - J.sb[c] + kChunk - 1) / kChunk;
+                if (nch > kSymChunks) nch = 0;
+            }
+            bsn[lane] = (int8_t)nch;
+        }
         if (lane < 2 * P1) row[lane] = b[lane];
         if (lane + 64 < 2 * P1) row[lane + 64] = b[lane + 64];
         if (shift) {
@@ -402,6 +416,14 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
         }
         __syncthreads();
         if (!inb || t >= te) continue;
+        double n0s = n0, n1s = n1;
+        if (two)
+            for (int k = 1; k < J.nw; ++k)
+                for (int ch = 0; ch < bsn[k]; ++ch) {
+                    const float2 v = J.bside[(int64_t)((k - 1) * kSymChunks + ch) * J.n_tgt + t];
+                    n0s += (double)v.x;
+                    n1s += (double)v.y;
+                }
         const double inv = 1.0 / J.scale[J.L];
         const double zr = (tx - cx) * inv, zi = (ty - cy) * inv;
         double fr = row[2 * J.p], fi = row[2 * J.p + 1], dr = 0.0, di = 0.0;
@@ -419,8 +441,8 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
             fr = nr;
             fi = ni;
         }
-        phi[2 * o] = n0 + fr;
-        phi[2 * o + 1] = n1 + fi;
+        phi[2 * o] = n0s + fr;
+        phi[2 * o + 1] = n1s + fi;
         if (FIELD) {
             bm.field_override[2 * o] = f0 + dr * inv;
             bm.field_override[2 * o + 1] = f1 + di * inv;

@@ -11,6 +11,8 @@
 // summed pairs) and stored in FP64 for the far field to be added to.  The
 // 1e18 padding sources have zero strength: their terms are exact zeros.
 // A pair with a zero separation is skipped (bitwise-equal points).
+#include <type_traits>
+
 #include "eval.h"
 
 namespace fmm {
@@ -22,13 +24,13 @@ static constexpr float kAtanPoly[8] = {9.999999114e-01f, -3.333209348e-01f, 1.99
                                        2.455700589e-02f, -4.780421207e-03f};
 static constexpr float kPi = 3.14159265358979324f, kPi2 = 1.57079632679489662f;
 
-// atan2 on the principal branch (-pi, pi]; y = -0 is treated as +0 and
-// (0, 0) gives 0.  t = min/max of |x|, |y| (the max floored so that t stays
-// finite), then the octant is restored.
-__device__ __forceinline__ float atan2_f32(float y, float x)
+// |atan2(y, x)| in [0, pi]: t = min/max of |x|, |y| (the max floored so
+// that t stays finite), then the octant within the upper half plane.
+__device__ __forceinline__ float atan2_abs(float y, float x, float &mn)
 {
     const float ax = fabsf(x), ay = fabsf(y);
-    const float mn = fminf(ax, ay), mx = fmaxf(fmaxf(ax, ay), 1e-30f);
+    mn = fminf(ax, ay);
+    const float mx = fmaxf(fmaxf(ax, ay), 1e-30f);
     const float t = mn * __builtin_amdgcn_rcpf(mx);
     const float z = t * t;
     float p = kAtanPoly[7];
@@ -36,8 +38,57 @@ __device__ __forceinline__ float atan2_f32(float y, float x)
     for (int k = 6; k >= 0; --k) p = fmaf(p, z, kAtanPoly[k]);
     float a = t * p;
     a = (ay > ax) ? kPi2 - a : a;
-    a = (x < 0.0f) ? kPi - a : a;
+    return (x < 0.0f) ? kPi - a : a;
+}
+
+// The FP32 offsets carry a vertical separation with an absolute error of
+// at most 9 * 2^-24 of the leaf scale (two offsets within a leaf, the
+// leaf-to-leaf offset and one rounded sum), enough to give a tiny dy the
+// wrong sign or make it zero.  Near the negative real axis that moves the
+// pair across the logarithm's principal branch cut, and its argument jumps
+// by 2 pi.  So where |dy| is below 2^-19 of the scale (about one pair in
+// 10^6), the sign is taken from the FP64 coordinates instead: +1, -1, or +0
+// when they are equal (the principal branch's arg = pi).  The hot loops
+// take the FP32 sign and only keep each lane's smallest |dy|; a round in
+// which some lane saw |dy| below the bound is gone over again for those
+// pairs, and the argument terms are corrected by the difference.
+__device__ __forceinline__ float dy_sign_fp64(const EvalJob &J, int32_t t, int32_t i)
+{
+    const double a = J.ty[t], b = J.sy[i];
+    return a > b ? 1.0f : (a < b ? -1.0f : 0.0f);
+}
+
+// atan2 on the principal branch (-pi, pi]; y = -0 is treated as +0 and
+// (0, 0) gives 0.
+__device__ __forceinline__ float atan2_abs(float y, float x)
+{
+    float mn;
+    return atan2_abs(y, x, mn);
+}
+
+__device__ __forceinline__ float atan2_f32(float y, float x, float &mn)
+{
+    const float a = atan2_abs(y, x, mn);
     return (y < 0.0f) ? -a : a;
+}
+
+__device__ __forceinline__ float atan2_f32(float y, float x)
+{
+    float mn;
+    return atan2_f32(y, x, mn);
+}
+
+// Running minimum of non-negative floats kept as their bit patterns (which
+// order as unsigned integers): one integer min, no NaN handling.
+__device__ __forceinline__ void keep_min(uint32_t &w, float v) { w = min(w, __float_as_uint(v)); }
+
+// arg with the sign of s taken for the sign of dy (s = -0 as +0); a = |arg|.
+__device__ __forceinline__ float signed_arg(float a, float s) { return s < 0.0f ? -a : a; }
+// arg of the reverse pair, -(dx, dy): pi - a for s <= 0, a - pi for s > 0.
+__device__ __forceinline__ float reverse_arg(float a, float s)
+{
+    const float pm = kPi - a;
+    return s <= 0.0f ? pm : -pm;
 }
 
 // One wave per work item: a target leaf and up to 64 of its targets.  With m
@@ -85,6 +136,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 5 : 
         const float tlx = in ? J.txl[t] : 0.0f, tly = in ? J.tyl[t] : 0.0f;
         const double tx = FIELD && in ? J.tx[t] : 0.0, ty = FIELD && in ? J.ty[t] : 0.0;
         const double tcx = J.cx[gid], tcy = J.cy[gid];
+        const float dtol = (float)(J.scale[J.L] * 0x1p-19);
 
         // Near-cell table (slot 0 is the leaf itself); an absent cell has an
         // empty range.
@@ -169,6 +221,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 5 : 
             __syncthreads();
             const float ax = tlx - (busy ? cdx[k] : 0.0f);
             const float ay = tly - (busy ? cdy[k] : 0.0f);
+            float worst = 1e30f;   // smallest |dy| of the round
             if (self_round) {
                 for (int j = 0; j < padn; ++j) {
                     const float4 sv = gsh[j];
@@ -177,6 +230,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 5 : 
                     const bool live = r2 > 0.0f;
                     const float lg = __log2f(live ? r2 : 1.0f);
                     const float at = atan2_f32(dy, dx);
+                    worst = fminf(worst, fabsf(dy));
                     acc(live ? sv.z * lg : 0.0f, live ? sv.w * at : 0.0f);
                     if (FIELD) {
                         const double2 sd = gshd[j];
@@ -200,6 +254,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 5 : 
                         const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-37f));
                         pr = fmaf(sv.z, __log2f(r2), pr);
                         pi = fmaf(sv.w, atan2_f32(dy, dx), pi);
+                        worst = fminf(worst, fabsf(dy));
                         if (FIELD) {
                             const double2 sd = gshd[j + jj];
                             const float ex = (float)(tx - sd.x), ey = (float)(ty - sd.y);
@@ -212,6 +267,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 5 : 
                     if (FIELD) {
                         kahan(frs, frc, qr);
                         kahan(fis, fic, qi);
+                    }
+                }
+            }
+            if (__any(worst < dtol)) {
+                // pairs near the branch cut: the argument's sign from FP64
+                if (worst < dtol && busy) {
+                    for (int j = 0; j < n; ++j) {
+                        const float4 sv = gsh[j];
+                        const float dx = ax - sv.x, dy = ay - sv.y;
+                        if (!(fabsf(dy) < dtol)) continue;
+                        if (self_round && !(fmaf(dx, dx, dy * dy) > 0.0f)) continue;   // skipped pair
+                        const float a = atan2_abs(dy, dx);
+                        const float d = signed_arg(a, dy_sign_fp64(J, t, base + j)) - signed_arg(a, dy);
+                        acc(0.0f, sv.w * d);
                     }
                 }
             }
@@ -251,6 +320,297 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 5 : 
             }
         }
     }
+}
+
+// ------------------------------------------------------------ symmetric form
+// For a plan whose targets are its sources.  The pair of distinct
+// neighbouring leaves {A, B}, A the lower cell id, is evaluated once, by A's
+// items, when A has at most kSymChunks chunks: one log2 r^2 and one argument
+// serve both directions, since on the principal branch
+//     arg(x_b - y_a) = arg(y_a - x_b) - pi  (arg > 0),  + pi  (arg <= 0),
+// i.e. pi - |arg| for dy <= 0 and |arg| - pi for dy > 0 (dy = -0 taken as
+// +0).  A's sums stay in registers; B's are reduced over
+// the wave and stored, one FP32 (re, im) per (B point, A chunk), in the plan's
+// second-side array, which L2P adds in a fixed order.  The leaf itself, and
+// a neighbour pair whose lower leaf has more chunks, are evaluated for one
+// side (by both leaves' items).
+//
+// Lane layout: an 8 x 8 tile, row i = lane / 8, column j = lane % 8.  The
+// item's targets (up to 64) sit in registers in eight blocks of eight
+// (target 8 blk + i in row i, the same in every column); each round the
+// columns take the next eight sources of one cell (source j in column j,
+// padded with zero-strength sources far away), and each lane evaluates its
+// (target, source) pair for every target block.  The next round's sources
+// are loaded during the current one.  A lane adds its terms plainly in
+// FP32 (one per round and target block); every kFlush rounds A's partial
+// sums are reduced over the columns and added to FP64 sums in LDS, so a
+// plain FP32 sum never spans more than kFlush terms, whatever the leaf
+// sizes.  B's sums (at most 64 terms) are reduced over the rows in FP32.
+enum : int8_t { kCellSkip = 0, kCellOne = 1, kCellSym = 2 };
+
+// A value that is the same in every lane, moved to a scalar register.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// A load through a pointer known to address global memory: the compiler
+// then waits for it by count (flat loads are waited for all at once).
+template <typename T>
+__device__ __forceinline__ T gload(const T *p, int64_t i)
+{
+    return ((const __attribute__((address_space(1))) T *)p)[i];
+}
+constexpr int kFlush = 8;
+
+// v + (v of the lane given by a DPP pattern): quad_perm [1,0,3,2] (lane ^ 1),
+// quad_perm [2,3,0,1] (lane ^ 2), row_half_mirror (lane 7 - lane within 8).
+template <int CTRL>
+__device__ __forceinline__ float add_dpp(float v)
+{
+    return v + __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_near_mixed_sym(const EvalJob *__restrict__ jobs, BatchMap bm)
+{
+    __shared__ int32_t cbeg[kNearSlots], cend[kNearSlots], cslot[kNearSlots];
+    __shared__ float cdx[kNearSlots], cdy[kNearSlots];
+    __shared__ int8_t cmode[kNearSlots];
+    __shared__ double sre[64], sim[64];   // A's sums, target 8 blk + row
+    const int lane = threadIdx.x, row = lane >> 3, col = lane & 7;
+    const float half_ln2 = 0.34657359027997264f;
+    for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
+        const int e = batch_entry(bm, item);
+        const EvalJob &J = jobs[bm.job[e]];
+        const int64_t it = item - bm.pre[e];
+        if (it >= J.counts[0]) continue;
+        // (item values are the same in every lane: kept in scalar registers
+        // so that the loops below branch on the scalar unit)
+        const int32_t li = uniform(J.work_near[2 * it]), st = uniform(J.work_near[2 * it + 1]);
+        const int64_t gid = J.leaf_off + li;
+        const int nw = uniform(J.nw);
+        const int32_t tb = uniform(J.tb[gid]), te = uniform(J.te[gid]);
+        const int m = min(kChunk, te - st);
+        const int nblk = (m + 7) >> 3;
+        const int chunk = (st - tb) / kChunk;
+        const bool own_sym = (te - tb + kChunk - 1) / kChunk <= kSymChunks;
+        const float dtol = (float)(J.scale[J.L] * 0x1p-19);
+
+        // Cell table: range, offset from this leaf's centre, and how the
+        // cell's pairs are taken.  Slot 0 is the leaf itself.
+        __syncthreads();   // the previous item is done with the LDS
+        sre[lane] = sim[lane] = 0.0;
+        if (lane < nw) {
+            const int32_t c = J.near[li * nw + lane];
+            int32_t b0 = 0, e0 = 0, slot = 0;
+            int8_t mode = kCellSkip;
+            float dx = 0.0f, dy = 0.0f;
+            if (c >= 0) {
+                b0 = J.sb[c];
+                e0 = J.se[c];
+                dx = (float)(J.cx[c] - J.cx[gid]);
+                dy = (float)(J.cy[c] - J.cy[gid]);
+                mode = kCellOne;
+                if (lane > 0 && c > gid && own_sym) {
+                    // this leaf's slot in the neighbour's list (the
+                    // neighbour relation is symmetric; one-sided otherwise)
+                    const int64_t lb = c - J.leaf_off;
+                    int k2 = 1;
+                    while (k2 < nw && J.near[lb * nw + k2] != (int32_t)gid) ++k2;
+                    if (k2 < nw) {
+                        mode = kCellSym;
+                        slot = (k2 - 1) * kSymChunks + chunk;
+                    }
+                } else if (lane > 0 && c < gid && (e0 - b0 + kChunk - 1) / kChunk <= kSymChunks) {
+                    // the neighbour's items evaluate the pair (if this leaf
+                    // is in its list, which the symmetric relation ensures)
+                    mode = kCellSkip;
+                }
+            }
+            if (mode == kCellSkip) e0 = b0;
+            cbeg[lane] = b0;
+            cend[lane] = e0;
+            cslot[lane] = slot;
+            cdx[lane] = dx;
+            cdy[lane] = dy;
+            cmode[lane] = mode;
+        }
+        __syncthreads();
+
+        float ax[8], ay[8], au[8], ar[8], ai[8];
+        // A's partial sums of each target block: over the columns (DPP),
+        // then column 0 adds them to the FP64 sums.
+        auto flush = [&]() {
+#pragma unroll
+            for (int blk = 0; blk < 8; ++blk) {
+                if (blk < nblk) {
+                    float vr = ar[blk], vi = ai[blk];
+                    vr = add_dpp<0xB1>(vr);
+                    vi = add_dpp<0xB1>(vi);
+                    vr = add_dpp<0x4E>(vr);
+                    vi = add_dpp<0x4E>(vi);
+                    vr = add_dpp<0x141>(vr);
+                    vi = add_dpp<0x141>(vi);
+                    if (col == 0) {
+                        sre[8 * blk + row] += (double)vr;
+                        sim[8 * blk + row] += (double)vi;
+                    }
+                    ar[blk] = ai[blk] = 0.0f;
+                }
+            }
+        };
+#pragma unroll
+        for (int blk = 0; blk < 8; ++blk) {
+            const int q = 8 * blk + row;
+            const bool ok = q < m;
+            ax[blk] = ok ? J.txl[st + q] : 0.0f;
+            ay[blk] = ok ? J.tyl[st + q] : 0.0f;
+            au[blk] = ok ? J.suf[st + q] : 0.0f;
+            ar[blk] = ai[blk] = 0.0f;
+        }
+        // This lane's source of round (k, b): its loads are issued a round
+        // ahead (from a valid index), and the values are formed -- coordinates
+        // relative to this leaf's centre, or the padding source where out of
+        // range -- only when the round starts.
+        struct Src {
+            float lx, ly, lw, ox, oy;
+            bool ok;
+        };
+        auto fetch = [&](int k, int32_t b) {
+            Src r;
+            const int kk = k < nw ? k : 0;
+            const int32_t i = b + col;
+            r.ok = k < nw && i < cend[kk];
+            const int32_t ic = r.ok ? i : 0;
+            r.lx = gload(J.sxl, ic);
+            r.ly = gload(J.syl, ic);
+            r.lw = gload((const float *)J.suf, ic);
+            r.ox = cdx[kk];
+            r.oy = cdy[kk];
+            return r;
+        };
+        auto next_cell = [&](int k) {
+            while (k < nw && uniform(cbeg[k]) >= uniform(cend[k])) ++k;
+            return k;
+        };
+        int k = next_cell(0);
+        int32_t b = k < nw ? uniform(cbeg[k]) : 0;
+        Src nxt = fetch(k, b);
+        int rounds = 0;
+        while (k < nw) {
+            const int32_t ce = uniform(cend[k]);
+            int k2 = k;
+            int32_t b2 = b + 8;
+            if (b2 >= ce) {
+                k2 = next_cell(k + 1);
+                b2 = k2 < nw ? uniform(cbeg[k2]) : 0;
+            }
+            const float sx = nxt.ok ? nxt.lx + nxt.ox : 1e18f;
+            const float sy = nxt.ok ? nxt.ly + nxt.oy : 1e18f;
+            const float su = nxt.ok ? nxt.lw : 0.0f;
+            nxt = fetch(k2, b2);
+            // smallest min(|dx|, |dy|) of the round (bits), a cheap bound
+            // for the smallest |dy|
+            uint32_t worst = 0x7f800000u;
+            // pairs near the branch cut: the argument's sign from FP64 (the
+            // B-side term only for a symmetric cell)
+            auto fix_cut = [&](bool two, float &bi) {
+                if (!(__uint_as_float(worst) < dtol)) return;
+#pragma unroll
+                for (int blk = 0; blk < 8; ++blk) {
+                    const int q = 8 * blk + row;
+                    if (blk < nblk && q < m && b + col < ce) {
+                        const float dx = ax[blk] - sx, dy = ay[blk] - sy;
+                        if (fabsf(dy) < dtol && (two || fmaf(dx, dx, dy * dy) > 0.0f)) {
+                            const float sg = dy_sign_fp64(J, st + q, b + col);
+                            const float a = atan2_abs(dy, dx);
+                            ai[blk] += su * (signed_arg(a, sg) - signed_arg(a, dy));
+                            if (two) bi += au[blk] * (reverse_arg(a, sg) - reverse_arg(a, dy));
+                        }
+                    }
+                }
+            };
+            if (uniform(cmode[k]) == kCellSym) {
+                float br = 0.0f, bi = 0.0f;
+                // the round for NB target blocks, a straight line of code
+                auto sym_round = [&](auto nb_const) {
+                    constexpr int NB = decltype(nb_const)::value;
+#pragma unroll
+                    for (int blk = 0; blk < NB; ++blk) {
+                        // distinct leaves: the 1e-37 only keeps a pair closer
+                        // than FP32 resolution finite
+                        const float dx = ax[blk] - sx, dy = ay[blk] - sy;
+                        const float lg = __log2f(fmaf(dx, dx, fmaf(dy, dy, 1e-37f)));
+                        float mn;
+                        const float a = atan2_abs(dy, dx, mn);
+                        const float th = signed_arg(a, dy);
+                        const float rth = reverse_arg(a, dy);
+                        keep_min(worst, mn);
+                        ar[blk] = fmaf(su, lg, ar[blk]);
+                        ai[blk] = fmaf(su, th, ai[blk]);
+                        br = fmaf(au[blk], lg, br);
+                        bi = fmaf(au[blk], rth, bi);
+                    }
+                };
+                switch (nblk) {
+                case 1: sym_round(std::integral_constant<int, 1>{}); break;
+                case 2: sym_round(std::integral_constant<int, 2>{}); break;
+                case 3: sym_round(std::integral_constant<int, 3>{}); break;
+                case 4: sym_round(std::integral_constant<int, 4>{}); break;
+                case 5: sym_round(std::integral_constant<int, 5>{}); break;
+                case 6: sym_round(std::integral_constant<int, 6>{}); break;
+                case 7: sym_round(std::integral_constant<int, 7>{}); break;
+                default: sym_round(std::integral_constant<int, 8>{}); break;
+                }
+                if (__any(__uint_as_float(worst) < dtol)) fix_cut(true, bi);
+#pragma unroll
+                for (int o = 8; o < 64; o <<= 1) {
+                    br += __shfl_xor(br, o);
+                    bi += __shfl_xor(bi, o);
+                }
+                const int32_t i = b + col;
+                if (row == 0 && i < ce)
+                    J.bside[(int64_t)uniform(cslot[k]) * J.n_tgt + i] = make_float2(br * half_ln2, bi);
+            } else {
+                // one side; a zero separation (the point itself, or an
+                // equal point) is skipped
+#pragma unroll
+                for (int blk = 0; blk < 8; ++blk) {
+                    if (blk >= nblk) continue;
+                    const float dx = ax[blk] - sx, dy = ay[blk] - sy;
+                    const float r2 = fmaf(dx, dx, dy * dy);
+                    const bool live = r2 > 0.0f;
+                    const float lg = __log2f(live ? r2 : 1.0f);
+                    float mn;
+                    const float th = atan2_f32(dy, dx, mn);
+                    const float w = live ? su : 0.0f;
+                    keep_min(worst, mn);
+                    ar[blk] = fmaf(w, lg, ar[blk]);
+                    ai[blk] = fmaf(w, th, ai[blk]);
+                }
+                if (__any(__uint_as_float(worst) < dtol)) {
+                    float unused = 0.0f;
+                    fix_cut(false, unused);
+                }
+            }
+            k = k2;
+            b = b2;
+            if (++rounds == kFlush) {
+                flush();
+                rounds = 0;
+            }
+        }
+        flush();
+        __syncthreads();
+        if (lane < m) {
+            J.nsum[2 * (st + lane)] = sre[lane] * 0.34657359027997264;   // ln 2 / 2
+            J.nsum[2 * (st + lane) + 1] = sim[lane];
+        }
+    }
+}
+
+void batch_near_mixed_sym(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
+{
+    if (m.n <= 0 || m.pre[m.n] <= 0) return;
+    const dim3 grid(persistent_grid(m.pre[m.n], kNearWavesPerCU));
+    hipLaunchKernelGGL(k_near_mixed_sym, grid, dim3(64), 0, s, jobs, m);
 }
 
 void batch_near_mixed(const EvalJob *jobs, const BatchMap &m, hipStream_t s)

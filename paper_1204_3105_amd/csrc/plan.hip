@@ -717,6 +717,8 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
             P->txl = take<float>(P, M, &err);
             P->tyl = take<float>(P, M, &err);
         }
+        if (same && N > 0)
+            P->bside = take<float2>(P, (int64_t)(nw - 1) * kSymChunks * N, &err);
         if (err) return fail(FMM_E_NOMEM, "device allocation failed (mixed)");
         launch_local_coords(P->sx, P->sy, P->skey, N, g, P->lev, P->dense, P->cx, P->cy, P->sxl,
                             P->syl, s);

@@ -77,3 +77,34 @@ def test_mixed_unit_disk_high_order(F, orc, tiling):
     e = rel(phi, ref)
     print("mixed disk %s p=%d rel_l2=%.3e" % (tiling, inf["p"], e), flush=True)
     assert e <= 1e-6
+
+
+@pytest.mark.parametrize("tiling", ["quad", "sept", "tri"])
+def test_mixed_symmetric_uneven_leaves(F, orc, tiling):
+    """Targets = sources, clustered, with 400 repeated points: leaves range
+    from a few to several hundred points, so the symmetric near field takes
+    the pairs whose lower leaf has at most two chunks of 64 targets for both
+    sides and the others one-sided from both leaves; coincident points are
+    skipped.  The leaf neighbour lists it relies on are symmetric."""
+    g = inputs.rng(41)
+    xs, ys = inputs.gaussian_mixture_points(g, 14000, 6, 0.03)
+    xs = np.concatenate([xs, xs[:400]])
+    ys = np.concatenate([ys, ys[:400]])
+    u = g.uniform(-1.0, 1.0, len(xs))
+    with F.Plan(tiling, xs, ys, eps=EPS, precision="mixed", leaf_size=160) as plan:
+        inf = plan.info()
+        phi = plan.eval(u)
+        lv = plan.export_level(inf["lmax"])
+    sizes = np.diff(lv["src_range"], axis=1).ravel()
+    big = int(np.sum(sizes > 128))
+    nb = {int(k): set(int(c) for c in row if c >= 0) for k, row in zip(lv["keys"], lv["near"])}
+    for a, row in nb.items():
+        for b in row:
+            assert a in nb[b], ("near lists not symmetric", a, b)
+    g2 = orc.geom(tiling, inf["lmax"], *inf["geometry"])
+    ref = orc.fmm(g2, inf["p"], xs, ys, u, xs, ys)
+    e = rel(phi, ref)
+    print("mixed symmetric %s L=%d leaves>128: %d of %d, rel_l2=%.3e" %
+          (tiling, inf["lmax"], big, len(sizes), e), flush=True)
+    assert big > 0
+    assert e <= EPS
