@@ -7,8 +7,9 @@ per step, leaf size 64, p from eps and each tiling's separation ratio.  A step
 is plan + eval for all three tilings with the points already resident in HBM.
 
 Prints one JSON line.  `value` = 3 * M * steps / wall time of the timed
-steps.  `roofline` covers the dominant kernel (the fused L2P + P2P near
-field), timed with HIP events on the stream it runs on.  `cpu_baseline` is
+steps.  `roofline` covers the dominant kernel (the P2P near field), timed
+with HIP events on the stream it runs on, as VALU lane-operations per second
+against the chip's VALU rate.  `cpu_baseline` is
 the CPU oracle timed on this host on a bounded sample of the same workload.
 """
 from __future__ import annotations
@@ -27,9 +28,36 @@ sys.path.insert(0, ROOT)
 # VALU lane-operations per second of one MI355X: 256 CUs x 4 SIMDs x 16 lanes
 # x 2.4 GHz (FP64 and non-packed FP32 issue at the same rate).
 LANE_OPS = 256 * 4 * 16 * 2.4e9
-# VALU instructions per source-target pair in the near-field inner loop of our
-# gfx950 build (counted from the kernels' AMD assembly; see the design notes).
+# VALU instructions per source-target pair in the near-field inner loops of
+# our gfx950 build (counted from the kernels' AMD assembly; see the design
+# notes): the one-sided kernels (FP64, and mixed with separate targets), and
+# the symmetric mixed kernel (targets = sources), where one evaluation of a
+# neighbour pair serves both of its sides and the leaf itself is one-sided.
 VALU_PER_PAIR = {"fp64": 104.0, "mixed": 31.0}
+VALU_SYM_EVAL = 33.0
+VALU_SYM_ONE_SIDED = 32.0
+SYM_CHUNKS = 2   # a leaf of at most 2 x 64 targets evaluates its pairs with higher leaves for both sides
+
+
+def near_valu_ops(lv, prec, same, n_pairs):
+    """VALU lane-operations of one near-field launch, from the plan's leaf
+    level (point counts and neighbour lists)."""
+    if prec != "mixed" or not same:
+        return n_pairs * VALU_PER_PAIR[prec]
+    keys = lv["keys"]
+    n = (lv["src_range"][:, 1] - lv["src_range"][:, 0]).astype(np.float64)
+    near = lv["near"]
+    a = np.repeat(np.arange(len(keys)), near.shape[1])
+    kb = near.ravel()
+    ok = kb >= 0
+    a, b = a[ok], np.searchsorted(keys, kb[ok])
+    upper = b > a
+    a, b = a[upper], b[upper]
+    sym = np.ceil(n[a] / 64.0) <= SYM_CHUNKS
+    prod = n[a] * n[b]
+    self_pairs = float(np.sum(n * n))
+    return (VALU_SYM_EVAL * float(np.sum(prod[sym]))
+            + VALU_SYM_ONE_SIDED * (self_pairs + 2.0 * float(np.sum(prod[~sym]))))
 HBM_PEAK = 8.0e12
 MFMA_BF16_PEAK = 2.5e15
 FP64_PEAK = 78.6e12
@@ -114,7 +142,13 @@ def timed(F, torch, pts, u, tilings, eps, prec, leaf, steps, warmup, outs, n_str
     kept = run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs, streams)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    infos = {t: [plan.info()] for t, plan in kept.items()}
+    infos = {}
+    for t, plan in kept.items():
+        inf = plan.info()
+        lv = plan.export_level(inf["lmax"])
+        inf["near_valu_ops"] = near_valu_ops(lv, inf["precision"], inf["targets_are_sources"],
+                                             inf["n_near_pairs"])
+        infos[t] = [inf]
     for plan in kept.values():
         plan.close()
     return t1 - t0, infos
@@ -328,12 +362,18 @@ def main():
     # passes, so its duration includes sharing the GPU with them).
     near_ms = np.mean([i["stage_ms"][3] for t in tilings for i in infos[t]])
     pairs = np.mean([i["n_near_pairs"] for t in tilings for i in infos[t]])
-    ach = pairs / (near_ms * 1e-3)
-    peak = LANE_OPS / VALU_PER_PAIR[prec_used]
-    traffic = committed_traffic("k_near_mixed") if prec_used == "mixed" else None
-    roofline = {"bound": "alu", "kernel": "near field (P2P)", "achieved": ach / 1e9,
-                "peak": peak / 1e9, "unit": "Gpair/s", "frac": ach / peak, "traffic": traffic,
-                "avg_launch_ms": float(near_ms), "pairs_per_launch": float(pairs)}
+    ops = np.mean([i["near_valu_ops"] for t in tilings for i in infos[t]])
+    ach = ops / (near_ms * 1e-3)
+    peak = LANE_OPS
+    sym = prec_used == "mixed" and all(i["targets_are_sources"] for t in tilings for i in infos[t])
+    kname = "k_near_mixed_sym" if sym else ("k_near_mixed" if prec_used == "mixed" else "k_near_fp64")
+    traffic = committed_traffic(kname) if prec_used == "mixed" else None
+    roofline = {"bound": "alu", "kernel": "near field (P2P), %s" % kname, "achieved": ach / 1e9,
+                "peak": peak / 1e9, "unit": "G VALU lane-op/s", "frac": ach / peak, "traffic": traffic,
+                "avg_launch_ms": float(near_ms), "pairs_per_launch": float(pairs),
+                "valu_ops_per_launch": float(ops),
+                "valu_per_pair": ({"symmetric_eval": VALU_SYM_EVAL, "one_sided": VALU_SYM_ONE_SIDED}
+                                  if sym else VALU_PER_PAIR[prec_used])}
 
     per_tiling = {}
     for t in tilings:

@@ -368,12 +368,13 @@ __device__ __forceinline__ float add_dpp(float v)
     return v + __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_near_mixed_sym(const EvalJob *__restrict__ jobs, BatchMap bm)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_near_mixed_sym(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
     __shared__ int32_t cbeg[kNearSlots], cend[kNearSlots], cslot[kNearSlots];
     __shared__ float cdx[kNearSlots], cdy[kNearSlots];
     __shared__ int8_t cmode[kNearSlots];
     __shared__ double sre[64], sim[64];   // A's sums, target 8 blk + row
+    __shared__ float4 sA[64];             // A's targets: offset x, y, strength
     const int lane = threadIdx.x, row = lane >> 3, col = lane & 7;
     const float half_ln2 = 0.34657359027997264f;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
@@ -397,6 +398,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
         // cell's pairs are taken.  Slot 0 is the leaf itself.
         __syncthreads();   // the previous item is done with the LDS
         sre[lane] = sim[lane] = 0.0;
+        {
+            const bool ok = lane < m;
+            sA[lane] = make_float4(ok ? J.txl[st + lane] : 0.0f, ok ? J.tyl[st + lane] : 0.0f,
+                                   ok ? J.suf[st + lane] : 0.0f, 0.0f);
+        }
         if (lane < nw) {
             const int32_t c = J.near[li * nw + lane];
             int32_t b0 = 0, e0 = 0, slot = 0;
@@ -434,7 +440,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
         }
         __syncthreads();
 
-        float ax[8], ay[8], au[8], ar[8], ai[8];
+        float ar[8], ai[8];
         // A's partial sums of each target block: over the columns (DPP),
         // then column 0 adds them to the FP64 sums.
         auto flush = [&]() {
@@ -457,14 +463,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
             }
         };
 #pragma unroll
-        for (int blk = 0; blk < 8; ++blk) {
-            const int q = 8 * blk + row;
-            const bool ok = q < m;
-            ax[blk] = ok ? J.txl[st + q] : 0.0f;
-            ay[blk] = ok ? J.tyl[st + q] : 0.0f;
-            au[blk] = ok ? J.suf[st + q] : 0.0f;
-            ar[blk] = ai[blk] = 0.0f;
-        }
+        for (int blk = 0; blk < 8; ++blk) ar[blk] = ai[blk] = 0.0f;
         // This lane's source of round (k, b): its loads are issued a round
         // ahead (from a valid index), and the values are formed -- coordinates
         // relative to this leaf's centre, or the padding source where out of
@@ -517,12 +516,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
                 for (int blk = 0; blk < 8; ++blk) {
                     const int q = 8 * blk + row;
                     if (blk < nblk && q < m && b + col < ce) {
-                        const float dx = ax[blk] - sx, dy = ay[blk] - sy;
+                        const float4 A = sA[8 * blk + row];
+                        const float dx = A.x - sx, dy = A.y - sy;
                         if (fabsf(dy) < dtol && (two || fmaf(dx, dx, dy * dy) > 0.0f)) {
                             const float sg = dy_sign_fp64(J, st + q, b + col);
                             const float a = atan2_abs(dy, dx);
                             ai[blk] += su * (signed_arg(a, sg) - signed_arg(a, dy));
-                            if (two) bi += au[blk] * (reverse_arg(a, sg) - reverse_arg(a, dy));
+                            if (two) bi += A.z * (reverse_arg(a, sg) - reverse_arg(a, dy));
                         }
                     }
                 }
@@ -536,7 +536,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
                     for (int blk = 0; blk < NB; ++blk) {
                         // distinct leaves: the 1e-37 only keeps a pair closer
                         // than FP32 resolution finite
-                        const float dx = ax[blk] - sx, dy = ay[blk] - sy;
+                        const float4 A = sA[8 * blk + row];
+                        const float dx = A.x - sx, dy = A.y - sy;
                         const float lg = __log2f(fmaf(dx, dx, fmaf(dy, dy, 1e-37f)));
                         float mn;
                         const float a = atan2_abs(dy, dx, mn);
@@ -545,8 +546,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
                         keep_min(worst, mn);
                         ar[blk] = fmaf(su, lg, ar[blk]);
                         ai[blk] = fmaf(su, th, ai[blk]);
-                        br = fmaf(au[blk], lg, br);
-                        bi = fmaf(au[blk], rth, bi);
+                        br = fmaf(A.z, lg, br);
+                        bi = fmaf(A.z, rth, bi);
                     }
                 };
                 switch (nblk) {
@@ -574,7 +575,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void
 #pragma unroll
                 for (int blk = 0; blk < 8; ++blk) {
                     if (blk >= nblk) continue;
-                    const float dx = ax[blk] - sx, dy = ay[blk] - sy;
+                    const float4 A = sA[8 * blk + row];
+                        const float dx = A.x - sx, dy = A.y - sy;
                     const float r2 = fmaf(dx, dx, dy * dy);
                     const bool live = r2 > 0.0f;
                     const float lg = __log2f(live ? r2 : 1.0f);
