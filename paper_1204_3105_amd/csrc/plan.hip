@@ -69,6 +69,16 @@ static size_t g_pool_cached = 0;
 static uint64_t g_fence_id = 0;
 static const size_t kPoolCap = (size_t)16 << 30;
 
+// hipEventQuery reports "not ready" as an error code, which the runtime keeps
+// as the thread's last error; clear exactly that, so that a later
+// hipGetLastError check sees only real failures.
+static hipError_t event_query(hipEvent_t ev)
+{
+    const hipError_t e = hipEventQuery(ev);
+    if (e == hipErrorNotReady && hipPeekAtLastError() == hipErrorNotReady) (void)hipGetLastError();
+    return e;
+}
+
 static size_t round_granule(size_t b) { return (b + ((size_t)2 << 20) - 1) & ~(((size_t)2 << 20) - 1); }
 
 static void drop_pool_locked()
@@ -100,7 +110,7 @@ void *dev_alloc(size_t bytes, int *err, std::vector<uint64_t> *waited, hipStream
             if (b.device != dev || b.bytes < bytes || b.bytes > 2 * bytes) continue;
             int rank = 0;
             if (b.fence && !(waited && b.fence->stream == stream))
-                rank = hipEventQuery(b.fence->ev) == hipSuccess ? 1 : 2;
+                rank = event_query(b.fence->ev) == hipSuccess ? 1 : 2;
             if (best < 0 || rank < best_rank || (rank == best_rank && b.bytes < g_pool[best].bytes)) {
                 best = i;
                 best_rank = rank;
@@ -259,7 +269,7 @@ static hipError_t spin_wait(hipEvent_t ev, hipStream_t s)
 {
     hipError_t e = hipEventRecord(ev, s);
     if (e != hipSuccess) return e;
-    while ((e = hipEventQuery(ev)) == hipErrorNotReady) {
+    while ((e = event_query(ev)) == hipErrorNotReady) {
     }
     return e;
 }

@@ -193,6 +193,15 @@ static void complete_batch(Server &S, std::vector<Req *> &batch)
     S.cv_done.notify_all();
 }
 
+// Whether the event has passed; a "not ready" answer is not kept as the
+// thread's last error (plan building checks that).
+static bool done_query(hipEvent_t ev)
+{
+    const hipError_t e = hipEventQuery(ev);
+    if (e == hipErrorNotReady && hipPeekAtLastError() == hipErrorNotReady) (void)hipGetLastError();
+    return e == hipSuccess;
+}
+
 static void scheduler(Server *Sp)
 {
     Server &S = *Sp;
@@ -200,7 +209,7 @@ static void scheduler(Server *Sp)
     for (;;) {
         bool progress = false;
         // 1. completion of the running batch
-        if (!S.running.empty() && hipEventQuery(S.done_ev) == hipSuccess) {
+        if (!S.running.empty() && done_query(S.done_ev)) {
             complete_batch(S, S.running);
             S.running.clear();
             progress = true;
@@ -235,7 +244,7 @@ static void scheduler(Server *Sp)
             progress = true;
             // Start evaluating as soon as the GPU is free.
             if (S.running.empty()) break;
-            if (hipEventQuery(S.done_ev) == hipSuccess) break;
+            if (done_query(S.done_ev)) break;
         }
         // 3. launch the next batch
         if (S.running.empty() && !S.planned.empty()) {
