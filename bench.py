@@ -34,8 +34,8 @@ LANE_OPS = 256 * 4 * 16 * 2.4e9
 # the symmetric mixed kernel (targets = sources), where one evaluation of a
 # neighbour pair serves both of its sides and the leaf itself is one-sided.
 VALU_PER_PAIR = {"fp64": 104.0, "mixed": 31.0}
-VALU_SYM_EVAL = 33.0
-VALU_SYM_ONE_SIDED = 32.0
+VALU_SYM_EVAL = 30.5
+VALU_SYM_ONE_SIDED = 30.0
 SYM_CHUNKS = 2   # a leaf of at most 2 x 64 targets evaluates its pairs with higher leaves for both sides
 
 

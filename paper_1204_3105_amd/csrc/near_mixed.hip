@@ -22,20 +22,27 @@ namespace fmm {
 static constexpr float kAtanPoly[8] = {9.999999114e-01f, -3.333209348e-01f, 1.997137453e-01f,
                                        -1.402941598e-01f, 9.942748199e-02f, -5.990455402e-02f,
                                        2.455700589e-02f, -4.780421207e-03f};
+// The same fit with seven terms (gen_atan_poly.py 6): max abs error 6.6e-7 in
+// FP32, for the symmetric kernel, where it saves an FMA per pair.
+static constexpr float kAtanPoly7[7] = {9.999994166e-01f, -3.332701317e-01f, 1.988731901e-01f,
+                                        -1.351216669e-01f, 8.435391630e-02f, -3.744282786e-02f,
+                                        8.006850172e-03f};
 static constexpr float kPi = 3.14159265358979324f, kPi2 = 1.57079632679489662f;
 
 // |atan2(y, x)| in [0, pi]: t = min/max of |x|, |y| (the max floored so
 // that t stays finite), then the octant within the upper half plane.
+template <int NC = 8>
 __device__ __forceinline__ float atan2_abs(float y, float x, float &mn)
 {
+    const float *c = NC == 8 ? kAtanPoly : kAtanPoly7;
     const float ax = fabsf(x), ay = fabsf(y);
     mn = fminf(ax, ay);
     const float mx = fmaxf(fmaxf(ax, ay), 1e-30f);
     const float t = mn * __builtin_amdgcn_rcpf(mx);
     const float z = t * t;
-    float p = kAtanPoly[7];
+    float p = c[NC - 1];
 #pragma unroll
-    for (int k = 6; k >= 0; --k) p = fmaf(p, z, kAtanPoly[k]);
+    for (int k = NC - 2; k >= 0; --k) p = fmaf(p, z, c[k]);
     float a = t * p;
     a = (ay > ax) ? kPi2 - a : a;
     return (x < 0.0f) ? kPi - a : a;
@@ -60,10 +67,11 @@ __device__ __forceinline__ float dy_sign_fp64(const EvalJob &J, int32_t t, int32
 
 // atan2 on the principal branch (-pi, pi]; y = -0 is treated as +0 and
 // (0, 0) gives 0.
+template <int NC = 8>
 __device__ __forceinline__ float atan2_abs(float y, float x)
 {
     float mn;
-    return atan2_abs(y, x, mn);
+    return atan2_abs<NC>(y, x, mn);
 }
 
 __device__ __forceinline__ float atan2_f32(float y, float x, float &mn)
@@ -90,6 +98,14 @@ __device__ __forceinline__ float reverse_arg(float a, float s)
     const float pm = kPi - a;
     return s <= 0.0f ? pm : -pm;
 }
+
+// The symmetric kernel's hot-loop forms, one bit-field insert each: the sign
+// of dy copied onto |arg| and onto pi - |arg| (the reverse argument is minus
+// the latter).  They differ from the two above only for dy = +-0, which the
+// branch-cut pass always revisits (|dy| is then below its bound) and
+// corrects against these same forms.
+__device__ __forceinline__ float fast_arg(float a, float dy) { return copysignf(a, dy); }
+__device__ __forceinline__ float fast_rev_neg(float a, float dy) { return copysignf(kPi - a, dy); }
 
 // One wave per work item: a target leaf and up to 64 of its targets.  With m
 // targets the wave runs g = min(near slots, 64/m) groups of m lanes (one
@@ -520,9 +536,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void
                         const float dx = A.x - sx, dy = A.y - sy;
                         if (fabsf(dy) < dtol && (two || fmaf(dx, dx, dy * dy) > 0.0f)) {
                             const float sg = dy_sign_fp64(J, st + q, b + col);
-                            const float a = atan2_abs(dy, dx);
-                            ai[blk] += su * (signed_arg(a, sg) - signed_arg(a, dy));
-                            if (two) bi += A.z * (reverse_arg(a, sg) - reverse_arg(a, dy));
+                            const float a = atan2_abs<7>(dy, dx);
+                            ai[blk] += su * (signed_arg(a, sg) - fast_arg(a, dy));
+                            if (two) bi += A.z * (reverse_arg(a, sg) + fast_rev_neg(a, dy));
                         }
                     }
                 }
@@ -540,14 +556,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void
                         const float dx = A.x - sx, dy = A.y - sy;
                         const float lg = __log2f(fmaf(dx, dx, fmaf(dy, dy, 1e-37f)));
                         float mn;
-                        const float a = atan2_abs(dy, dx, mn);
-                        const float th = signed_arg(a, dy);
-                        const float rth = reverse_arg(a, dy);
+                        const float a = atan2_abs<7>(dy, dx, mn);
                         keep_min(worst, mn);
                         ar[blk] = fmaf(su, lg, ar[blk]);
-                        ai[blk] = fmaf(su, th, ai[blk]);
+                        ai[blk] = fmaf(su, fast_arg(a, dy), ai[blk]);
                         br = fmaf(A.z, lg, br);
-                        bi = fmaf(A.z, rth, bi);
+                        bi = fmaf(-A.z, fast_rev_neg(a, dy), bi);
                     }
                 };
                 switch (nblk) {
@@ -581,7 +595,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void
                     const bool live = r2 > 0.0f;
                     const float lg = __log2f(live ? r2 : 1.0f);
                     float mn;
-                    const float th = atan2_f32(dy, dx, mn);
+                    const float th = fast_arg(atan2_abs<7>(dy, dx, mn), dy);
                     const float w = live ? su : 0.0f;
                     keep_min(worst, mn);
                     ar[blk] = fmaf(w, lg, ar[blk]);
