@@ -50,6 +50,7 @@ struct EvalJob {
     // [((near slot - 1) * kSymChunks + chunk) * n_tgt + point]; null when
     // the plan cannot take that path.
     float2 *bside;
+    double2 *bside64;   // the same for the FP64 symmetric near field
 };
 
 struct BatchMap {
@@ -113,6 +114,20 @@ __device__ __forceinline__ void store_split(__bf16 *mix_b, int64_t cell, int KB,
     o[64] = l;
 }
 
+// A value that is the same in every lane, moved to a scalar register.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// A load through a pointer known to address global memory: the compiler
+// then waits for it by count (flat loads are waited for all at once).
+template <typename T>
+__device__ __forceinline__ T gload(const T *p, int64_t i)
+{
+    return ((const __attribute__((address_space(1))) T *)p)[i];
+}
+
+// How a neighbour cell's pairs are taken by the symmetric near field.
+enum : int8_t { kCellSkip = 0, kCellOne = 1, kCellSym = 2 };
+
 inline unsigned persistent_grid(int64_t items, int per_cu)
 {
     int64_t cap = (int64_t)256 * per_cu;
@@ -136,6 +151,7 @@ void batch_near_fp64(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_l2p(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_near_mixed(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_near_mixed_sym(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
+void batch_near_fp64_sym(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 
 // Host view of one plan for batching: its descriptor (host copy) and the
 // device copy.

@@ -86,6 +86,7 @@ EvalJob make_job(const Plan &P)
     J.phi = P.phi_int;
     J.nsum = P.nsum;
     J.bside = P.bside;
+    J.bside64 = P.bside64;
     if (P.precision == FMM_PREC_MIXED && P.mixed) {
         int MT, KB;
         mixed_pointers(P, &J.mix_tab, &J.mix_tiles, &J.mix_list, &J.mix_b, &MT, &KB);
@@ -183,9 +184,17 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
         {
             Launcher Ls{jobs_dev, side, n == 1 ? phi_single : nullptr, field_single, nfield_single, {}};
             Ls.reset();
+            // FP64: the symmetric form where the targets are the sources
+            // (not for the field)
+            auto sym64 = [&](const Plan &P) { return P.bside64 != nullptr && nfield_single == nullptr; };
+            auto fs = [&](const BatchMap &m) { batch_near_fp64_sym(jobs_dev, m, side); };
+            for (int i = 0; i < n; ++i)
+                if (plans[i]->precision != FMM_PREC_MIXED && sym64(*plans[i])) Ls.add(i, 0, plans[i]->n_work_near, fs);
+            if (Ls.m.n > 0) fs(Ls.m);
+            Ls.reset();
             auto f = [&](const BatchMap &m) { batch_near_fp64(jobs_dev, m, side); };
             for (int i = 0; i < n; ++i)
-                if (plans[i]->precision != FMM_PREC_MIXED) Ls.add(i, 0, plans[i]->n_work_near, f);
+                if (plans[i]->precision != FMM_PREC_MIXED && !sym64(*plans[i])) Ls.add(i, 0, plans[i]->n_work_near, f);
             if (Ls.m.n > 0) f(Ls.m);
             Ls.reset();
             // mixed: the symmetric form where the targets are the sources

@@ -102,6 +102,7 @@ struct Plan {
     // mixed precision with targets = sources: the symmetric near field's
     // second-side sums, [(near slot - 1) * kSymChunks + chunk][point]
     float2 *bside = nullptr;
+    double2 *bside64 = nullptr;   // FP64 plans with targets = sources: the same in FP64
 
     // cells
     LevelInfo lev[kMaxL + 1]{};

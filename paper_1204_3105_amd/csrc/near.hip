@@ -11,6 +11,8 @@
 // sum_m b~_m ((y - c)/ell)^m, Horner) and writes Phi in the caller's order.
 #include <algorithm>
 
+#include <type_traits>
+
 #include "eval.h"
 
 namespace fmm {
@@ -366,7 +368,7 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
         // With the symmetric near field, each lower neighbour (by cell id)
         // with at most kSymChunks chunks left this leaf's second-side sums,
         // one per chunk of it.
-        const bool two = J.bside != nullptr && bm.nfield == nullptr;
+        const bool two = (J.bside != nullptr || J.bside64 != nullptr) && bm.nfield == nullptr;
         __syncthreads();
         if (two && lane < J.nw) {
             int nch = 0;
@@ -420,9 +422,16 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
         if (two)
             for (int k = 1; k < J.nw; ++k)
                 for (int ch = 0; ch < bsn[k]; ++ch) {
-                    const float2 v = J.bside[(int64_t)((k - 1) * kSymChunks + ch) * J.n_tgt + t];
-                    n0s += (double)v.x;
-                    n1s += (double)v.y;
+                    const int64_t at = (int64_t)((k - 1) * kSymChunks + ch) * J.n_tgt + t;
+                    if (J.bside64) {
+                        const double2 v = J.bside64[at];
+                        n0s += v.x;
+                        n1s += v.y;
+                    } else {
+                        const float2 v = J.bside[at];
+                        n0s += (double)v.x;
+                        n1s += (double)v.y;
+                    }
                 }
         const double inv = 1.0 / J.scale[J.L];
         const double zr = (tx - cx) * inv, zi = (ty - cy) * inv;
@@ -543,6 +552,256 @@ void launch_direct(const double *src, int64_t n_src, const double *tgt, int64_t 
                        slices > 1 ? part : phi);
     if (slices > 1)
         hipLaunchKernelGGL(k_direct_reduce, dim3(tb), dim3(256), 0, s, part, n_tgt, slices, phi);
+}
+
+// ------------------------------------------------------------ symmetric form
+// ln r2 with the arguments of the pair, (x, y), and of the reverse pair,
+// (-x, -y), both on the principal branch with a zero y read as +0: the
+// octant's last step is taken once for x and once for -x from the same
+// angle in [0, pi/2].
+__device__ __forceinline__ void ln_atan2_pair_f64(double r2, double y, double x, double &lnr2, double &at,
+                                                  double &atr)
+{
+    int e;
+    double m = frexp(r2, &e);
+    const bool lo = m < kSqrtHalf;
+    m = lo ? 2.0 * m : m;
+    e = lo ? e - 1 : e;
+    const double ax = fabs(x), ay = fabs(y);
+    const double mn = fmin(ax, ay), mx = fmax(ax, ay);
+    const bool red = mn > kTanPi12 * mx;
+    const double num = red ? fma(-kInvSqrt3, mx, mn) : mn;
+    const double den = red ? fma(kInvSqrt3, mn, mx) : mx;
+    const double mp1 = m + 1.0;
+    const double D = mp1 * den;
+    double R = __builtin_amdgcn_rcp(D);
+    R = fma(R, fma(-D, R, 1.0), R);
+    R = fma(R, fma(-D, R, 1.0), R);
+    const double s = ((m - 1.0) * den) * R;
+    const double t = (num * mp1) * R;
+    const double z = s * s;
+    double p = 1.0 / 21.0;
+    p = fma(p, z, 1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    const double lm = 2.0 * s + 2.0 * s * (z * p);
+    const double de = (double)e;
+    lnr2 = fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
+    const double w = t * t;
+    double q = -1.0 / 27.0;
+    q = fma(q, w, 1.0 / 25.0);
+    q = fma(q, w, -1.0 / 23.0);
+    q = fma(q, w, 1.0 / 21.0);
+    q = fma(q, w, -1.0 / 19.0);
+    q = fma(q, w, 1.0 / 17.0);
+    q = fma(q, w, -1.0 / 15.0);
+    q = fma(q, w, 1.0 / 13.0);
+    q = fma(q, w, -1.0 / 11.0);
+    q = fma(q, w, 1.0 / 9.0);
+    q = fma(q, w, -1.0 / 7.0);
+    q = fma(q, w, 1.0 / 5.0);
+    q = fma(q, w, -1.0 / 3.0);
+    double a = fma(t * w, q, t);
+    a = red ? kPi6Hi + (kPi6Lo + a) : a;
+    a = (ay > ax) ? kPi2Hi + (kPi2Lo - a) : a;
+    const double pa = kPiHi + (kPiLo - a);
+    const double af = (x < 0.0) ? pa : a, ab = (x > 0.0) ? pa : a;
+    at = (y < 0.0) ? -af : af;
+    atr = (y > 0.0) ? -ab : ab;
+}
+
+__device__ __forceinline__ double shfl_xor_f64(double v, int mask)
+{
+    const int lo = __shfl_xor(__double2loint(v), mask), hi = __shfl_xor(__double2hiint(v), mask);
+    return __hiloint2double(hi, lo);
+}
+
+// The FP64 near field for a plan whose targets are its sources, laid out as
+// the mixed symmetric kernel: a neighbour pair {A, B} (A the lower cell id,
+// with at most kSymChunks chunks) is evaluated once, by A's items, for both
+// sides; the leaf itself, and pairs whose lower leaf is larger, one-sided.
+// An 8 x 8 lane tile: A's targets (up to 64) in LDS in blocks of eight rows,
+// eight of a cell's sources per round in the columns (absolute coordinates,
+// loaded a round ahead), so every separation, and with it the sign of dy, is
+// exact.  Sums are FP64 throughout: A's in the lanes, reduced over the
+// columns at the end; B's reduced over the rows each round and stored per
+// (point, lower neighbour, its chunk) in bside64 for L2P.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_near_fp64_sym(const EvalJob *__restrict__ jobs, BatchMap bm)
+{
+    __shared__ int32_t cbeg[kNearSlots], cend[kNearSlots], cslot[kNearSlots];
+    __shared__ int8_t cmode[kNearSlots];
+    __shared__ double sax[64], say[64], sau[64];   // A's targets
+    const int lane = threadIdx.x, row = lane >> 3, col = lane & 7;
+    for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
+        const int e = batch_entry(bm, item);
+        const EvalJob &J = jobs[bm.job[e]];
+        const int64_t it = item - bm.pre[e];
+        if (it >= J.counts[0]) continue;
+        const int32_t li = uniform(J.work_near[2 * it]), st = uniform(J.work_near[2 * it + 1]);
+        const int64_t gid = J.leaf_off + li;
+        const int nw = uniform(J.nw);
+        const int32_t tb = uniform(J.tb[gid]), te = uniform(J.te[gid]);
+        const int m = min(kChunk, te - st);
+        const int nblk = (m + 7) >> 3;
+        const int chunk = (st - tb) / kChunk;
+        const bool own_sym = (te - tb + kChunk - 1) / kChunk <= kSymChunks;
+
+        __syncthreads();   // the previous item is done with the LDS
+        {
+            const bool ok = lane < m;
+            sax[lane] = ok ? J.tx[st + lane] : 0.0;
+            say[lane] = ok ? J.ty[st + lane] : 0.0;
+            sau[lane] = ok ? J.su[st + lane] : 0.0;
+        }
+        if (lane < nw) {
+            const int32_t c = J.near[li * nw + lane];
+            int32_t b0 = 0, e0 = 0, slot = 0;
+            int8_t mode = kCellSkip;
+            if (c >= 0) {
+                b0 = J.sb[c];
+                e0 = J.se[c];
+                mode = kCellOne;
+                if (lane > 0 && c > gid && own_sym) {
+                    const int64_t lb = c - J.leaf_off;
+                    int k2 = 1;
+                    while (k2 < nw && J.near[lb * nw + k2] != (int32_t)gid) ++k2;
+                    if (k2 < nw) {
+                        mode = kCellSym;
+                        slot = (k2 - 1) * kSymChunks + chunk;
+                    }
+                } else if (lane > 0 && c < gid && (e0 - b0 + kChunk - 1) / kChunk <= kSymChunks) {
+                    mode = kCellSkip;
+                }
+            }
+            if (mode == kCellSkip) e0 = b0;
+            cbeg[lane] = b0;
+            cend[lane] = e0;
+            cslot[lane] = slot;
+            cmode[lane] = mode;
+        }
+        __syncthreads();
+
+        double ar[8], ai[8];
+#pragma unroll
+        for (int blk = 0; blk < 8; ++blk) ar[blk] = ai[blk] = 0.0;
+        struct Src {
+            double x, y, w;
+            bool ok;
+        };
+        auto fetch = [&](int k, int32_t b) {
+            Src r;
+            const int kk = k < nw ? k : 0;
+            const int32_t i = b + col;
+            r.ok = k < nw && i < cend[kk];
+            const int32_t ic = r.ok ? i : 0;
+            r.x = gload(J.sx, ic);
+            r.y = gload(J.sy, ic);
+            r.w = gload((const double *)J.su, ic);
+            return r;
+        };
+        auto next_cell = [&](int k) {
+            while (k < nw && uniform(cbeg[k]) >= uniform(cend[k])) ++k;
+            return k;
+        };
+        int k = next_cell(0);
+        int32_t b = k < nw ? uniform(cbeg[k]) : 0;
+        Src nxt = fetch(k, b);
+        while (k < nw) {
+            const int32_t ce = uniform(cend[k]);
+            int k2 = k;
+            int32_t b2 = b + 8;
+            if (b2 >= ce) {
+                k2 = next_cell(k + 1);
+                b2 = k2 < nw ? uniform(cbeg[k2]) : 0;
+            }
+            // padding: zero strength, far away
+            const double sx = nxt.ok ? nxt.x : 1e100, sy = nxt.ok ? nxt.y : 1e100;
+            const double su = nxt.ok ? nxt.w : 0.0;
+            nxt = fetch(k2, b2);
+            if (uniform(cmode[k]) == kCellSym) {
+                double br = 0.0, bi = 0.0;
+                auto sym_round = [&](auto nb_const) {
+                    constexpr int NB = decltype(nb_const)::value;
+#pragma unroll
+                    for (int blk = 0; blk < NB; ++blk) {
+                        const int q = 8 * blk + row;
+                        const double dx = sax[q] - sx, dy = say[q] - sy, u = sau[q];
+                        double lg, at, atr;
+                        ln_atan2_pair_f64(fma(dx, dx, dy * dy), dy, dx, lg, at, atr);
+                        ar[blk] = fma(su, lg, ar[blk]);
+                        ai[blk] = fma(su, at, ai[blk]);
+                        br = fma(u, lg, br);
+                        bi = fma(u, atr, bi);
+                    }
+                };
+                switch (nblk) {
+                case 1: sym_round(std::integral_constant<int, 1>{}); break;
+                case 2: sym_round(std::integral_constant<int, 2>{}); break;
+                case 3: sym_round(std::integral_constant<int, 3>{}); break;
+                case 4: sym_round(std::integral_constant<int, 4>{}); break;
+                case 5: sym_round(std::integral_constant<int, 5>{}); break;
+                case 6: sym_round(std::integral_constant<int, 6>{}); break;
+                case 7: sym_round(std::integral_constant<int, 7>{}); break;
+                default: sym_round(std::integral_constant<int, 8>{}); break;
+                }
+#pragma unroll
+                for (int o = 8; o < 64; o <<= 1) {
+                    br += shfl_xor_f64(br, o);
+                    bi += shfl_xor_f64(bi, o);
+                }
+                const int32_t i = b + col;
+                if (row == 0 && i < ce)
+                    J.bside64[(int64_t)uniform(cslot[k]) * J.n_tgt + i] = make_double2(0.5 * br, bi);
+            } else {
+                // one side; a zero separation (the point itself, or an equal
+                // point) is skipped
+#pragma unroll
+                for (int blk = 0; blk < 8; ++blk) {
+                    if (blk >= nblk) continue;
+                    const int q = 8 * blk + row;
+                    const double dx = sax[q] - sx, dy = say[q] - sy;
+                    const double r2 = fma(dx, dx, dy * dy);
+                    const bool live = r2 > 0.0;
+                    double lg, at;
+                    ln_atan2_f64(live ? r2 : 1.0, dy, live ? dx : 1.0, lg, at);
+                    const double w = live ? su : 0.0;
+                    ar[blk] = fma(w, lg, ar[blk]);
+                    ai[blk] = fma(w, at, ai[blk]);
+                }
+            }
+            k = k2;
+            b = b2;
+        }
+        // A's sums over the columns; column 0 writes
+#pragma unroll
+        for (int blk = 0; blk < 8; ++blk) {
+            if (blk >= nblk) continue;
+            double vr = ar[blk], vi = ai[blk];
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) {
+                vr += shfl_xor_f64(vr, o);
+                vi += shfl_xor_f64(vi, o);
+            }
+            const int q = 8 * blk + row;
+            if (col == 0 && q < m) {
+                J.nsum[2 * (st + q)] = 0.5 * vr;
+                J.nsum[2 * (st + q) + 1] = vi;
+            }
+        }
+    }
+}
+
+void batch_near_fp64_sym(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
+{
+    if (m.n <= 0 || m.pre[m.n] <= 0) return;
+    const dim3 grid(persistent_grid(m.pre[m.n], kNearWavesPerCU));
+    hipLaunchKernelGGL(k_near_fp64_sym, grid, dim3(64), 0, s, jobs, m);
 }
 
 void batch_near_fp64(const EvalJob *jobs, const BatchMap &m, hipStream_t s)

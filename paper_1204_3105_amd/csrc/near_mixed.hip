@@ -362,18 +362,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 5 : 
 // sums are reduced over the columns and added to FP64 sums in LDS, so a
 // plain FP32 sum never spans more than kFlush terms, whatever the leaf
 // sizes.  B's sums (at most 64 terms) are reduced over the rows in FP32.
-enum : int8_t { kCellSkip = 0, kCellOne = 1, kCellSym = 2 };
 
-// A value that is the same in every lane, moved to a scalar register.
-__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
-// A load through a pointer known to address global memory: the compiler
-// then waits for it by count (flat loads are waited for all at once).
-template <typename T>
-__device__ __forceinline__ T gload(const T *p, int64_t i)
-{
-    return ((const __attribute__((address_space(1))) T *)p)[i];
-}
 constexpr int kFlush = 8;
 
 // v + (v of the lane given by a DPP pattern): quad_perm [1,0,3,2] (lane ^ 1),
@@ -384,7 +374,7 @@ __device__ __forceinline__ float add_dpp(float v)
     return v + __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(7, 8))) void k_near_mixed_sym(const EvalJob *__restrict__ jobs, BatchMap bm)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_near_mixed_sym(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
     __shared__ int32_t cbeg[kNearSlots], cend[kNearSlots], cslot[kNearSlots];
     __shared__ float cdx[kNearSlots], cdy[kNearSlots];

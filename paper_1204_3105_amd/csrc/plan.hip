@@ -752,6 +752,8 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     }
     P->phi_int = take<double>(P, 2 * std::max<int64_t>(M, 1), &err);
     P->nsum = take<double>(P, 2 * std::max<int64_t>(M, 1), &err);
+    if (P->precision != FMM_PREC_MIXED && same && N > 0)
+        P->bside64 = take<double2>(P, (int64_t)(nw - 1) * kSymChunks * N, &err);
     if (P->lev[g.L].n == 0 || M == 0) FMM_HIP_CHECK(hipMemsetAsync(P->counts, 0, sizeof(int32_t), s));
     P->job_dev = take<EvalJob>(P, 1, &err);
     if (err) return fail(FMM_E_NOMEM, "device allocation failed (descriptor)");

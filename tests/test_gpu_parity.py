@@ -193,3 +193,28 @@ def test_invalid_inputs(F):
         F.Plan("quad", bad, w.ys, eps=1e-6)
     with pytest.raises(F.FMMError):
         F.Plan("quad", w.xs, w.ys, eps=1e-6, geometry=(0.5, 0.5, 0.1), lmax=2)
+
+
+@pytest.mark.parametrize("tiling", TILES)
+def test_fp64_symmetric_uneven_leaves(F, orc, tiling):
+    """FP64, targets = sources, clustered with leaf 160 and 400 repeated
+    points: the symmetric near field takes neighbour pairs whose lower leaf
+    has at most two chunks of 64 targets once for both sides and the rest
+    one-sided; coincident points are skipped.  Same bar as every FP64
+    potential."""
+    g = inputs.rng(43)
+    xs, ys = inputs.gaussian_mixture_points(g, 12000, 6, 0.03)
+    xs = np.concatenate([xs, xs[:400]])
+    ys = np.concatenate([ys, ys[:400]])
+    u = g.uniform(-1.0, 1.0, len(xs))
+    with F.Plan(tiling, xs, ys, p=12, precision="fp64", leaf_size=160) as plan:
+        inf = plan.info()
+        phi = plan.eval(u)
+        lv = plan.export_level(inf["lmax"])
+    big = int(np.sum(np.diff(lv["src_range"], axis=1) > 128))
+    g2 = orc.geom(tiling, inf["lmax"], *inf["geometry"])
+    ref = orc.fmm(g2, inf["p"], xs, ys, u, xs, ys)
+    e = rel(phi, ref)
+    say("fp64 symmetric %s L=%d leaves>128: %d, rel_l2=%.3e" % (tiling, inf["lmax"], big, e))
+    assert big > 0
+    assert e <= 1e-12
