@@ -34,15 +34,15 @@ LANE_OPS = 256 * 4 * 16 * 2.4e9
 # the symmetric mixed kernel (targets = sources), where one evaluation of a
 # neighbour pair serves both of its sides and the leaf itself is one-sided.
 VALU_PER_PAIR = {"fp64": 104.0, "mixed": 31.0}
-VALU_SYM_EVAL = 30.5
-VALU_SYM_ONE_SIDED = 30.0
+VALU_SYM_EVAL = {"mixed": 30.5, "fp64": 92.0}
+VALU_SYM_ONE_SIDED = {"mixed": 30.0, "fp64": 104.0}
 SYM_CHUNKS = 2   # a leaf of at most 2 x 64 targets evaluates its pairs with higher leaves for both sides
 
 
 def near_valu_ops(lv, prec, same, n_pairs):
     """VALU lane-operations of one near-field launch, from the plan's leaf
     level (point counts and neighbour lists)."""
-    if prec != "mixed" or not same:
+    if not same:
         return n_pairs * VALU_PER_PAIR[prec]
     keys = lv["keys"]
     n = (lv["src_range"][:, 1] - lv["src_range"][:, 0]).astype(np.float64)
@@ -56,8 +56,8 @@ def near_valu_ops(lv, prec, same, n_pairs):
     sym = np.ceil(n[a] / 64.0) <= SYM_CHUNKS
     prod = n[a] * n[b]
     self_pairs = float(np.sum(n * n))
-    return (VALU_SYM_EVAL * float(np.sum(prod[sym]))
-            + VALU_SYM_ONE_SIDED * (self_pairs + 2.0 * float(np.sum(prod[~sym]))))
+    return (VALU_SYM_EVAL[prec] * float(np.sum(prod[sym]))
+            + VALU_SYM_ONE_SIDED[prec] * (self_pairs + 2.0 * float(np.sum(prod[~sym]))))
 HBM_PEAK = 8.0e12
 MFMA_BF16_PEAK = 2.5e15
 FP64_PEAK = 78.6e12
@@ -365,14 +365,15 @@ def main():
     ops = np.mean([i["near_valu_ops"] for t in tilings for i in infos[t]])
     ach = ops / (near_ms * 1e-3)
     peak = LANE_OPS
-    sym = prec_used == "mixed" and all(i["targets_are_sources"] for t in tilings for i in infos[t])
-    kname = "k_near_mixed_sym" if sym else ("k_near_mixed" if prec_used == "mixed" else "k_near_fp64")
+    sym = all(i["targets_are_sources"] for t in tilings for i in infos[t])
+    kname = ("k_near_mixed" if prec_used == "mixed" else "k_near_fp64") + ("_sym" if sym else "")
     traffic = committed_traffic(kname) if prec_used == "mixed" else None
     roofline = {"bound": "alu", "kernel": "near field (P2P), %s" % kname, "achieved": ach / 1e9,
                 "peak": peak / 1e9, "unit": "G VALU lane-op/s", "frac": ach / peak, "traffic": traffic,
                 "avg_launch_ms": float(near_ms), "pairs_per_launch": float(pairs),
                 "valu_ops_per_launch": float(ops),
-                "valu_per_pair": ({"symmetric_eval": VALU_SYM_EVAL, "one_sided": VALU_SYM_ONE_SIDED}
+                "valu_per_pair": ({"symmetric_eval": VALU_SYM_EVAL[prec_used],
+                                   "one_sided": VALU_SYM_ONE_SIDED[prec_used]}
                                   if sym else VALU_PER_PAIR[prec_used])}
 
     per_tiling = {}
