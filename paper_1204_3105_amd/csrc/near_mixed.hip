@@ -382,6 +382,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     __shared__ double sre[64], sim[64];   // A's sums, target 8 blk + row
     __shared__ float4 sA[64];             // A's targets: offset x, y, strength
     const int lane = threadIdx.x, row = lane >> 3, col = lane & 7;
+    const int perm16 = (lane ^ 16) << 2, perm32 = (lane ^ 32) << 2;   // ds_bpermute byte addresses
     const float half_ln2 = 0.34657359027997264f;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
         const int e = batch_entry(bm, item);
@@ -446,30 +447,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
         }
         __syncthreads();
 
-        float ar[8], ai[8];
-        // A's partial sums of each target block: over the columns (DPP),
-        // then column 0 adds them to the FP64 sums.
-        auto flush = [&]() {
-#pragma unroll
-            for (int blk = 0; blk < 8; ++blk) {
-                if (blk < nblk) {
-                    float vr = ar[blk], vi = ai[blk];
-                    vr = add_dpp<0xB1>(vr);
-                    vi = add_dpp<0xB1>(vi);
-                    vr = add_dpp<0x4E>(vr);
-                    vi = add_dpp<0x4E>(vi);
-                    vr = add_dpp<0x141>(vr);
-                    vi = add_dpp<0x141>(vi);
-                    if (col == 0) {
-                        sre[8 * blk + row] += (double)vr;
-                        sim[8 * blk + row] += (double)vi;
-                    }
-                    ar[blk] = ai[blk] = 0.0f;
-                }
-            }
-        };
-#pragma unroll
-        for (int blk = 0; blk < 8; ++blk) ar[blk] = ai[blk] = 0.0f;
         // This lane's source of round (k, b): its loads are issued a round
         // ahead (from a valid index), and the values are formed -- coordinates
         // relative to this leaf's centre, or the padding source where out of
@@ -495,49 +472,72 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
             while (k < nw && uniform(cbeg[k]) >= uniform(cend[k])) ++k;
             return k;
         };
-        int k = next_cell(0);
-        int32_t b = k < nw ? uniform(cbeg[k]) : 0;
-        Src nxt = fetch(k, b);
-        int rounds = 0;
-        while (k < nw) {
-            const int32_t ce = uniform(cend[k]);
-            int k2 = k;
-            int32_t b2 = b + 8;
-            if (b2 >= ce) {
-                k2 = next_cell(k + 1);
-                b2 = k2 < nw ? uniform(cbeg[k2]) : 0;
-            }
-            const float sx = nxt.ok ? nxt.lx + nxt.ox : 1e18f;
-            const float sy = nxt.ok ? nxt.ly + nxt.oy : 1e18f;
-            const float su = nxt.ok ? nxt.lw : 0.0f;
-            nxt = fetch(k2, b2);
-            // smallest min(|dx|, |dy|) of the round (bits), a cheap bound
-            // for the smallest |dy|
-            uint32_t worst = 0x7f800000u;
-            // pairs near the branch cut: the argument's sign from FP64 (the
-            // B-side term only for a symmetric cell)
-            auto fix_cut = [&](bool two, float &bi) {
-                if (!(__uint_as_float(worst) < dtol)) return;
+        // The item's rounds for NB target blocks (dispatched once per item,
+        // so the accumulators stay in place from round to round).
+        auto item_rounds = [&](auto nb_const) {
+            constexpr int NB = decltype(nb_const)::value;
+            float ar[NB], ai[NB];
 #pragma unroll
-                for (int blk = 0; blk < 8; ++blk) {
-                    const int q = 8 * blk + row;
-                    if (blk < nblk && q < m && b + col < ce) {
-                        const float4 A = sA[8 * blk + row];
-                        const float dx = A.x - sx, dy = A.y - sy;
-                        if (fabsf(dy) < dtol && (two || fmaf(dx, dx, dy * dy) > 0.0f)) {
-                            const float sg = dy_sign_fp64(J, st + q, b + col);
-                            const float a = atan2_abs<7>(dy, dx);
-                            ai[blk] += su * (signed_arg(a, sg) - fast_arg(a, dy));
-                            if (two) bi += A.z * (reverse_arg(a, sg) + fast_rev_neg(a, dy));
-                        }
+            for (int blk = 0; blk < NB; ++blk) ar[blk] = ai[blk] = 0.0f;
+            // A's partial sums of each target block: over the columns
+            // (DPP), then column 0 adds them to the FP64 sums.
+            auto flush = [&]() {
+#pragma unroll
+                for (int blk = 0; blk < NB; ++blk) {
+                    float vr = ar[blk], vi = ai[blk];
+                    vr = add_dpp<0xB1>(vr);
+                    vi = add_dpp<0xB1>(vi);
+                    vr = add_dpp<0x4E>(vr);
+                    vi = add_dpp<0x4E>(vi);
+                    vr = add_dpp<0x141>(vr);
+                    vi = add_dpp<0x141>(vi);
+                    if (col == 0) {
+                        sre[8 * blk + row] += (double)vr;
+                        sim[8 * blk + row] += (double)vi;
                     }
+                    ar[blk] = ai[blk] = 0.0f;
                 }
             };
-            if (uniform(cmode[k]) == kCellSym) {
-                float br = 0.0f, bi = 0.0f;
-                // the round for NB target blocks, a straight line of code
-                auto sym_round = [&](auto nb_const) {
-                    constexpr int NB = decltype(nb_const)::value;
+            int k = next_cell(0);
+            int32_t b = k < nw ? uniform(cbeg[k]) : 0;
+            Src nxt = fetch(k, b);
+            int rounds = 0;
+            while (k < nw) {
+                const int32_t ce = uniform(cend[k]);
+                int k2 = k;
+                int32_t b2 = b + 8;
+                if (b2 >= ce) {
+                    k2 = next_cell(k + 1);
+                    b2 = k2 < nw ? uniform(cbeg[k2]) : 0;
+                }
+                const float sx = nxt.ok ? nxt.lx + nxt.ox : 1e18f;
+                const float sy = nxt.ok ? nxt.ly + nxt.oy : 1e18f;
+                const float su = nxt.ok ? nxt.lw : 0.0f;
+                nxt = fetch(k2, b2);
+                // smallest min(|dx|, |dy|) of the round (bits), a cheap
+                // bound for the smallest |dy|
+                uint32_t worst = 0x7f800000u;
+                // pairs near the branch cut: the argument's sign from FP64
+                // (the B-side term only for a symmetric cell)
+                auto fix_cut = [&](bool two, float &bi) {
+                    if (!(__uint_as_float(worst) < dtol)) return;
+#pragma unroll
+                    for (int blk = 0; blk < NB; ++blk) {
+                        const int q = 8 * blk + row;
+                        if (q < m && b + col < ce) {
+                            const float4 A = sA[q];
+                            const float dx = A.x - sx, dy = A.y - sy;
+                            if (fabsf(dy) < dtol && (two || fmaf(dx, dx, dy * dy) > 0.0f)) {
+                                const float sg = dy_sign_fp64(J, st + q, b + col);
+                                const float a = atan2_abs<7>(dy, dx);
+                                ai[blk] += su * (signed_arg(a, sg) - fast_arg(a, dy));
+                                if (two) bi += A.z * (reverse_arg(a, sg) + fast_rev_neg(a, dy));
+                            }
+                        }
+                    }
+                };
+                if (uniform(cmode[k]) == kCellSym) {
+                    float br = 0.0f, bi = 0.0f;
 #pragma unroll
                     for (int blk = 0; blk < NB; ++blk) {
                         // distinct leaves: the 1e-37 only keeps a pair closer
@@ -553,57 +553,60 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
                         br = fmaf(A.z, lg, br);
                         bi = fmaf(-A.z, fast_rev_neg(a, dy), bi);
                     }
-                };
-                switch (nblk) {
-                case 1: sym_round(std::integral_constant<int, 1>{}); break;
-                case 2: sym_round(std::integral_constant<int, 2>{}); break;
-                case 3: sym_round(std::integral_constant<int, 3>{}); break;
-                case 4: sym_round(std::integral_constant<int, 4>{}); break;
-                case 5: sym_round(std::integral_constant<int, 5>{}); break;
-                case 6: sym_round(std::integral_constant<int, 6>{}); break;
-                case 7: sym_round(std::integral_constant<int, 7>{}); break;
-                default: sym_round(std::integral_constant<int, 8>{}); break;
-                }
-                if (__any(__uint_as_float(worst) < dtol)) fix_cut(true, bi);
+                    if (__any(__uint_as_float(worst) < dtol)) fix_cut(true, bi);
+                    // B's sums over the rows: lane ^ 8 by DPP (a rotation by
+                    // eight within each 16-lane row), lane ^ 16 and ^ 32 by
+                    // permutes with addresses computed once
+                    br = add_dpp<0x128>(br);
+                    bi = add_dpp<0x128>(bi);
+                    br += __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(perm16, __builtin_bit_cast(int, br)));
+                    bi += __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(perm16, __builtin_bit_cast(int, bi)));
+                    br += __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(perm32, __builtin_bit_cast(int, br)));
+                    bi += __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(perm32, __builtin_bit_cast(int, bi)));
+                    const int32_t i = b + col;
+                    if (row == 0 && i < ce)
+                        J.bside[(int64_t)uniform(cslot[k]) * J.n_tgt + i] = make_float2(br * half_ln2, bi);
+                } else {
+                    // one side; a zero separation (the point itself, or an
+                    // equal point) is skipped
 #pragma unroll
-                for (int o = 8; o < 64; o <<= 1) {
-                    br += __shfl_xor(br, o);
-                    bi += __shfl_xor(bi, o);
-                }
-                const int32_t i = b + col;
-                if (row == 0 && i < ce)
-                    J.bside[(int64_t)uniform(cslot[k]) * J.n_tgt + i] = make_float2(br * half_ln2, bi);
-            } else {
-                // one side; a zero separation (the point itself, or an
-                // equal point) is skipped
-#pragma unroll
-                for (int blk = 0; blk < 8; ++blk) {
-                    if (blk >= nblk) continue;
-                    const float4 A = sA[8 * blk + row];
+                    for (int blk = 0; blk < NB; ++blk) {
+                        const float4 A = sA[8 * blk + row];
                         const float dx = A.x - sx, dy = A.y - sy;
-                    const float r2 = fmaf(dx, dx, dy * dy);
-                    const bool live = r2 > 0.0f;
-                    const float lg = __log2f(live ? r2 : 1.0f);
-                    float mn;
-                    const float th = fast_arg(atan2_abs<7>(dy, dx, mn), dy);
-                    const float w = live ? su : 0.0f;
-                    keep_min(worst, mn);
-                    ar[blk] = fmaf(w, lg, ar[blk]);
-                    ai[blk] = fmaf(w, th, ai[blk]);
+                        const float r2 = fmaf(dx, dx, dy * dy);
+                        const bool live = r2 > 0.0f;
+                        const float lg = __log2f(live ? r2 : 1.0f);
+                        float mn;
+                        const float th = fast_arg(atan2_abs<7>(dy, dx, mn), dy);
+                        const float w = live ? su : 0.0f;
+                        keep_min(worst, mn);
+                        ar[blk] = fmaf(w, lg, ar[blk]);
+                        ai[blk] = fmaf(w, th, ai[blk]);
+                    }
+                    if (__any(__uint_as_float(worst) < dtol)) {
+                        float unused = 0.0f;
+                        fix_cut(false, unused);
+                    }
                 }
-                if (__any(__uint_as_float(worst) < dtol)) {
-                    float unused = 0.0f;
-                    fix_cut(false, unused);
+                k = k2;
+                b = b2;
+                if (++rounds == kFlush) {
+                    flush();
+                    rounds = 0;
                 }
             }
-            k = k2;
-            b = b2;
-            if (++rounds == kFlush) {
-                flush();
-                rounds = 0;
-            }
+            flush();
+        };
+        switch (nblk) {
+        case 1: item_rounds(std::integral_constant<int, 1>{}); break;
+        case 2: item_rounds(std::integral_constant<int, 2>{}); break;
+        case 3: item_rounds(std::integral_constant<int, 3>{}); break;
+        case 4: item_rounds(std::integral_constant<int, 4>{}); break;
+        case 5: item_rounds(std::integral_constant<int, 5>{}); break;
+        case 6: item_rounds(std::integral_constant<int, 6>{}); break;
+        case 7: item_rounds(std::integral_constant<int, 7>{}); break;
+        default: item_rounds(std::integral_constant<int, 8>{}); break;
         }
-        flush();
         __syncthreads();
         if (lane < m) {
             J.nsum[2 * (st + lane)] = sre[lane] * 0.34657359027997264;   // ln 2 / 2
