@@ -133,13 +133,19 @@ fmm_status fmm_options_default(fmm_options *opt);
 /* Build a plan (Secs. 4-6: CellIndex keys at the leaf level, sort, per-level
  * occupied cells, Neighbors and NeighborsE4 lists).  src: n_src complex128
  * points; tgt: n_tgt complex128 points (tgt may equal src, in which case the
- * sorted arrays are shared).  eps in (0, 0.5) selects p when opt->p < 0.
+ * sorted arrays are shared, and the plan also holds (near width - 1) x 2 x n
+ * second-side near sums, FP32 or FP64 pairs, for the symmetric near field
+ * of fmm_eval).  eps in (0, 0.5) selects p when opt->p < 0.
  * opt may be NULL (defaults).  On success *out holds the plan. */
 fmm_status fmm_plan(fmm_tiling tiling, const double *src, int64_t n_src, const double *tgt,
                     int64_t n_tgt, double eps, const fmm_options *opt, fmm_plan_t *out);
 
 /* Evaluate Phi for strengths u (n_src doubles) into phi (2*n_tgt doubles):
  * P2M, M2M, M2L, L2L, L2P and the P2P near field (GR87 Lemmas 2.1-2.5).
+ * When the targets are the sources, each pair of neighbouring leaves is
+ * evaluated once for both of its sides (ln|y - x| is symmetric, and the two
+ * arguments differ by pi on the principal branch), so the near field's
+ * rounding differs from fmm_eval_field's one-sided sums.
  * Allocates nothing.  n_src = 0 gives Phi = 0. */
 fmm_status fmm_eval(fmm_plan_t plan, const double *u, double *phi);
 
@@ -149,7 +155,9 @@ fmm_status fmm_eval(fmm_plan_t plan, const double *u, double *phi);
  * same near lists, coincident pairs skipped (same precision policy as the
  * potential).  field: 2*n_tgt doubles (complex128, caller's target order),
  * host or device like phi.  The plan takes 16 B per target more on the first
- * call.  Errors as fmm_eval; FMM_E_NOMEM if the field buffers cannot be
+ * call.  Its potential equals fmm_eval's bitwise when the targets are not
+ * the sources, and to rounding (the near sums are one-sided here) when they
+ * are.  Errors as fmm_eval; FMM_E_NOMEM if the field buffers cannot be
  * allocated. */
 fmm_status fmm_eval_field(fmm_plan_t plan, const double *u, double *phi, double *field);
 
