@@ -364,7 +364,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 5 : 
 // sizes.  B's sums (at most 64 terms) are reduced over the rows in FP32.
 
 
-constexpr int kFlush = 8;
+constexpr int kFlush = 16;
 
 // v + (v of the lane given by a DPP pattern): quad_perm [1,0,3,2] (lane ^ 1),
 // quad_perm [2,3,0,1] (lane ^ 2), row_half_mirror (lane 7 - lane within 8).
