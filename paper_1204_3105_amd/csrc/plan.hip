@@ -551,7 +551,7 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     FMM_HIP_CHECK(hipEventRecord(P->ev[0], s));
 
     // Bounding box (sources and targets), also flags non-finite input.
-    const int nbb = 256;
+    const int nbb = 1024;   // partial boxes: four points per thread
     double *bbp = take<double>(P, 5 * 2 * nbb, &err);
     if (err) return fail(FMM_E_NOMEM, "device allocation failed (bbox)");
     // The source and target partial boxes are reduced together.

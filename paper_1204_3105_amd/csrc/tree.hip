@@ -63,6 +63,7 @@ __global__ void k_mark_cells(int tiling, Levels s, const uint32_t *__restrict__ 
     if (i >= n) return;
     uint32_t k = key[i];
     uint32_t kp = i > 0 ? key[i - 1] : 0xffffffffu;
+    if (i > 0 && kp == k) return;   // same leaf, so the same cell at every level
     for (int l = 0; l <= s.L; ++l) {
         uint32_t lk = level_key(tiling, s, k, l);
         bool start = (i == 0) || level_key(tiling, s, kp, l) != lk;
@@ -172,6 +173,9 @@ __global__ void k_ranges(int tiling, Levels s, const uint32_t *__restrict__ key,
     uint32_t k = key[i];
     uint32_t kp = i > 0 ? key[i - 1] : 0u;
     uint32_t kn = i + 1 < n ? key[i + 1] : 0u;
+    // inside a leaf's run (same leaf key on both sides): no cell starts or
+    // ends here at any level
+    if (i > 0 && i + 1 < n && kp == k && kn == k) return;
     for (int l = 0; l <= s.L; ++l) {
         uint32_t lk = level_key(tiling, s, k, l);
         int32_t gid = dense[s.l[l].dense_off + lk];
