@@ -100,8 +100,10 @@ def parse():
                     help="requests in the serving stream (0 = skip the serving leg)")
     ap.add_argument("--clustered-n", type=int, default=4 << 20,
                     help="points per side of the clustered-input leg (0 = skip)")
-    ap.add_argument("--streams", type=int, default=2,
+    ap.add_argument("--streams", type=int, default=3,
                     help="streams that consecutive solves take turns on (1 = all on one stream)")
+    ap.add_argument("--near-stream", default="own", choices=["own", "side"],
+                    help="near field on each solve's own stream (own) or beside its far field (side)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 512 MiB device copy first (HBM counter calibration)")
     ap.add_argument("--serve-load", type=float, default=0.7,
@@ -109,7 +111,7 @@ def parse():
     return ap.parse_args()
 
 
-def run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs, streams):
+def run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs, streams, near_stream="own"):
     """`steps` passes of plan + evaluate per tiling.  Consecutive solves take
     turns on the given streams, so one solve's plan (short, latency-bound
     kernels and two host read-backs) runs while the previous solve's
@@ -122,7 +124,8 @@ def run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs, streams):
         for t in tilings:
             st = streams[j % len(streams)]
             j += 1
-            plan = F.Plan(t, src=pts, tgt=pts, eps=eps, precision=prec, leaf_size=leaf, stream=st)
+            plan = F.Plan(t, src=pts, tgt=pts, eps=eps, precision=prec, leaf_size=leaf, stream=st,
+                          near_stream=near_stream)
             plan.eval(u, out=outs[t])
             if step == steps - 1:
                 kept[t] = plan
@@ -131,15 +134,15 @@ def run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs, streams):
     return kept
 
 
-def timed(F, torch, pts, u, tilings, eps, prec, leaf, steps, warmup, outs, n_streams=2):
+def timed(F, torch, pts, u, tilings, eps, prec, leaf, steps, warmup, outs, n_streams=3, near_stream="own"):
     # torch's current stream alone, or that many new default-priority streams
     streams = ([torch.cuda.current_stream()] if n_streams <= 1 else
                [torch.cuda.Stream() for _ in range(n_streams)])
-    for plan in run_steps(F, torch, pts, u, tilings, eps, prec, leaf, warmup, outs, streams).values():
+    for plan in run_steps(F, torch, pts, u, tilings, eps, prec, leaf, warmup, outs, streams, near_stream).values():
         plan.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    kept = run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs, streams)
+    kept = run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs, streams, near_stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     infos = {}
@@ -352,7 +355,7 @@ def main():
           (a.n, tilings, a.precision, a.steps, a.warmup), file=sys.stderr, flush=True)
 
     wall, infos = timed(F, torch, pts, u, tilings, a.eps, a.precision, a.leaf, a.steps, a.warmup, outs,
-                        a.streams)
+                        a.streams, a.near_stream)
     value = len(tilings) * a.n * a.steps / wall
     prec_used = infos[tilings[0]][-1]["precision"]
     print("bench: timed %.3f s -> %.4g targets/s (%s)" % (wall, value, prec_used), file=sys.stderr,
@@ -396,14 +399,16 @@ def main():
     extra["errors"] = errs
 
     if a.compare_fp64 and prec_used != "fp64":
-        wall64, infos64 = timed(F, torch, pts, u, tilings, a.eps, "fp64", a.leaf, a.steps, 1, outs, a.streams)
+        wall64, infos64 = timed(F, torch, pts, u, tilings, a.eps, "fp64", a.leaf, a.steps, 1, outs, a.streams,
+                                a.near_stream)
         extra["fp64_form"] = {"value": len(tilings) * a.n * a.steps / wall64,
                               "ms_per_step": wall64 / a.steps * 1e3,
                               "errors": error_check(oracle, w, outs, infos64, tilings, a.check)}
         print("bench: plain FP64 form %.4g targets/s" % extra["fp64_form"]["value"], file=sys.stderr,
               flush=True)
         # The same workload at eps 1e-10 (FP64 only: p 38 / 35 / 46).
-        wall10, infos10 = timed(F, torch, pts, u, tilings, 1e-10, "fp64", a.leaf, a.steps, 1, outs, a.streams)
+        wall10, infos10 = timed(F, torch, pts, u, tilings, 1e-10, "fp64", a.leaf, a.steps, 1, outs, a.streams,
+                                a.near_stream)
         extra["fp64_eps1e-10"] = {
             "value": len(tilings) * a.n * a.steps / wall10, "ms_per_step": wall10 / a.steps * 1e3,
             "per_tiling": {t: {"p": infos10[t][-1]["p"],
@@ -437,7 +442,7 @@ def main():
         "config": {"workload": "N=M=2^20 uniform unit square, sources=targets, u~U[-1,1], "
                                "eps=%g, leaf %d, one plan+eval per tiling (%s) per step" %
                                (a.eps, a.leaf, "+".join(tilings)),
-                   "precision": prec_used, "n": a.n, "streams": a.streams},
+                   "precision": prec_used, "n": a.n, "streams": a.streams, "near_stream": a.near_stream},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,

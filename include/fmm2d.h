@@ -103,6 +103,12 @@ typedef struct {
     int32_t device_pointers; /* 1 = all data pointers are device pointers     */
     int32_t depth_rule;      /* fmm_depth_rule, used when lmax < 0 and no
                                 explicit geometry (FMM_DEPTH_MEAN)            */
+    int32_t near_stream;     /* where fmm_eval runs the P2P near field:
+                                0 = a library stream beside the far-field
+                                passes (default: one solve's latency);
+                                1 = the plan's own stream after them (for a
+                                caller that overlaps several solves on
+                                streams of its own); other values rejected   */
 } fmm_options;
 
 /* Read-only summary of a plan. */

@@ -82,6 +82,7 @@ struct Plan {
     int leaf_size = 64;
     int64_t n_src = 0, n_tgt = 0;
     bool same = false;   // targets are the sources
+    bool near_own_stream = false;   // evaluation: near field on the plan's stream
     double scale[kMaxL + 1]{};   // radius scale of each level
 
     // arena

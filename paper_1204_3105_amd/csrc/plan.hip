@@ -867,11 +867,13 @@ fmm_status fmm_plan(fmm_tiling tiling, const double *src, int64_t n_src, const d
     if (o.lmax > kMaxL) return fail(FMM_E_INVALID, "lmax above the supported maximum (16)");
     if (o.precision < 0 || o.precision > 2) return fail(FMM_E_INVALID, "bad precision");
     if (o.depth_rule != FMM_DEPTH_MEAN && o.depth_rule != FMM_DEPTH_COST) return fail(FMM_E_INVALID, "bad depth_rule");
+    if (o.near_stream != 0 && o.near_stream != 1) return fail(FMM_E_INVALID, "bad near_stream");
     PlanImpl *P = new PlanImpl();
     P->device_pointers = o.device_pointers != 0;
     P->n_src = n_src;
     P->n_tgt = n_tgt;
     P->same = (tgt == src) && (n_tgt == n_src);
+    P->near_own_stream = o.near_stream == 1;
     P->leaf_size = o.leaf_size;
     int prec = o.precision;
     if (prec == FMM_PREC_AUTO) prec = eps >= 1e-6 ? FMM_PREC_MIXED : FMM_PREC_FP64;
@@ -939,7 +941,7 @@ static fmm_status eval_impl(fmm_plan_t plan, const double *u, double *phi, doubl
         FMM_HIP_CHECK(hipEventRecord(P->ev[9], s));
     } else {
         Plan *one = P;
-        run_batch(&one, 1, (const EvalJob *)P->job_dev, dphi, s, side_stream(), &P->ev[3], dfield,
+        run_batch(&one, 1, (const EvalJob *)P->job_dev, dphi, s, P->near_own_stream ? s : side_stream(), &P->ev[3], dfield,
                   dfield ? P->nfield : nullptr, du);
     }
     FMM_HIP_CHECK(hipGetLastError());

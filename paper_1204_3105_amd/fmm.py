@@ -33,7 +33,7 @@ class Options(C.Structure):
     _fields_ = [("struct_size", C.c_uint32), ("leaf_size", C.c_int32), ("lmax", C.c_int32),
                 ("p", C.c_int32), ("precision", C.c_int32), ("has_geometry", C.c_int32),
                 ("geometry", C.c_double * 3), ("stream", C.c_void_p),
-                ("device_pointers", C.c_int32), ("depth_rule", C.c_int32)]
+                ("device_pointers", C.c_int32), ("depth_rule", C.c_int32), ("near_stream", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -162,6 +162,7 @@ def _points_host(x, y=None) -> np.ndarray:
 
 
 DEPTH = {"mean": 0, "cost": 1}
+NEAR_STREAM = {"side": 0, "own": 1}
 
 
 class Plan:
@@ -174,7 +175,8 @@ class Plan:
     """
 
     def __init__(self, tiling, xs=None, ys=None, xt=None, yt=None, eps=1e-6, *, src=None, tgt=None,
-                 leaf_size=64, lmax=-1, p=-1, precision="auto", geometry=None, stream=None, depth="mean"):
+                 leaf_size=64, lmax=-1, p=-1, precision="auto", geometry=None, stream=None, depth="mean",
+                 near_stream="side"):
         L = lib()
         self._plan = C.c_void_p()
         opt = Options()
@@ -184,6 +186,7 @@ class Plan:
         opt.p = int(p)
         opt.precision = PREC[precision] if isinstance(precision, str) else int(precision)
         opt.depth_rule = DEPTH[depth] if isinstance(depth, str) else int(depth)
+        opt.near_stream = NEAR_STREAM[near_stream] if isinstance(near_stream, str) else int(near_stream)
         if geometry is not None:
             opt.has_geometry = 1
             for k in range(3):

@@ -116,3 +116,16 @@ def test_depth_rule_option(F):
     pts = (C.c_double * 4)(0.1, 0.2, 0.3, 0.4)
     assert lib.fmm_plan(0, pts, 2, pts, 2, 1e-6, C.byref(o), C.byref(plan)) == 1
     assert b"depth" in lib.fmm_last_error()
+
+
+def test_near_stream_option(F):
+    lib = F.lib()
+    o = F.Options()
+    assert lib.fmm_options_default(C.byref(o)) == 0
+    assert o.near_stream == 0
+    assert C.sizeof(o) == o.struct_size
+    o.near_stream = 2
+    plan = C.c_void_p()
+    pts = (C.c_double * 4)(0.1, 0.2, 0.3, 0.4)
+    assert lib.fmm_plan(0, pts, 2, pts, 2, 1e-6, C.byref(o), C.byref(plan)) == 1
+    assert b"near_stream" in lib.fmm_last_error()

@@ -108,3 +108,16 @@ def test_mixed_symmetric_uneven_leaves(F, orc, tiling):
           (tiling, inf["lmax"], big, len(sizes), e), flush=True)
     assert big > 0
     assert e <= EPS
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_near_stream_option_same_result(F, prec):
+    """The near field on the plan's own stream (after the far field) gives
+    bitwise the potential of the default side-stream schedule."""
+    w = inputs.uniform_square(30011, seed=5)
+    out = {}
+    for ns in ("side", "own"):
+        with F.Plan("tri", w.xs, w.ys, eps=1e-6, precision=prec, near_stream=ns) as plan:
+            out[ns] = plan.eval(w.u)
+    print("near_stream own vs side (%s): equal %s" % (prec, np.array_equal(out["own"], out["side"])), flush=True)
+    assert np.array_equal(out["own"], out["side"])
