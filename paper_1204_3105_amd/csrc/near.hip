@@ -616,9 +616,12 @@ __device__ __forceinline__ void ln_atan2_pair_f64(double r2, double y, double x,
     atr = (y > 0.0) ? -ab : ab;
 }
 
-__device__ __forceinline__ double shfl_xor_f64(double v, int mask)
+// The value v of the lane whose byte address (4 x lane) is addr, by two
+// 32-bit permutes.
+__device__ __forceinline__ double bperm_f64(int addr, double v)
 {
-    const int lo = __shfl_xor(__double2loint(v), mask), hi = __shfl_xor(__double2hiint(v), mask);
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
     return __hiloint2double(hi, lo);
 }
 
@@ -638,6 +641,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
     __shared__ int8_t cmode[kNearSlots];
     __shared__ double sax[64], say[64], sau[64];   // A's targets
     const int lane = threadIdx.x, row = lane >> 3, col = lane & 7;
+    // ds_bpermute byte addresses of lane ^ 1, 2, 4 (columns) and ^ 8, 16, 32 (rows)
+    const int perm1 = (lane ^ 1) << 2, perm2 = (lane ^ 2) << 2, perm4 = (lane ^ 4) << 2;
+    const int perm8 = (lane ^ 8) << 2, perm16 = (lane ^ 16) << 2, perm32 = (lane ^ 32) << 2;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
         const int e = batch_entry(bm, item);
         const EvalJob &J = jobs[bm.job[e]];
@@ -687,9 +693,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         }
         __syncthreads();
 
-        double ar[8], ai[8];
-#pragma unroll
-        for (int blk = 0; blk < 8; ++blk) ar[blk] = ai[blk] = 0.0;
         struct Src {
             double x, y, w;
             bool ok;
@@ -709,25 +712,30 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
             while (k < nw && uniform(cbeg[k]) >= uniform(cend[k])) ++k;
             return k;
         };
-        int k = next_cell(0);
-        int32_t b = k < nw ? uniform(cbeg[k]) : 0;
-        Src nxt = fetch(k, b);
-        while (k < nw) {
-            const int32_t ce = uniform(cend[k]);
-            int k2 = k;
-            int32_t b2 = b + 8;
-            if (b2 >= ce) {
-                k2 = next_cell(k + 1);
-                b2 = k2 < nw ? uniform(cbeg[k2]) : 0;
-            }
-            // padding: zero strength, far away
-            const double sx = nxt.ok ? nxt.x : 1e100, sy = nxt.ok ? nxt.y : 1e100;
-            const double su = nxt.ok ? nxt.w : 0.0;
-            nxt = fetch(k2, b2);
-            if (uniform(cmode[k]) == kCellSym) {
-                double br = 0.0, bi = 0.0;
-                auto sym_round = [&](auto nb_const) {
-                    constexpr int NB = decltype(nb_const)::value;
+        // The item's rounds for NB target blocks (dispatched once per item,
+        // so the accumulators stay in place from round to round).
+        auto item_rounds = [&](auto nb_const) {
+            constexpr int NB = decltype(nb_const)::value;
+            double ar[NB], ai[NB];
+#pragma unroll
+            for (int blk = 0; blk < NB; ++blk) ar[blk] = ai[blk] = 0.0;
+            int k = next_cell(0);
+            int32_t b = k < nw ? uniform(cbeg[k]) : 0;
+            Src nxt = fetch(k, b);
+            while (k < nw) {
+                const int32_t ce = uniform(cend[k]);
+                int k2 = k;
+                int32_t b2 = b + 8;
+                if (b2 >= ce) {
+                    k2 = next_cell(k + 1);
+                    b2 = k2 < nw ? uniform(cbeg[k2]) : 0;
+                }
+                // padding: zero strength, far away
+                const double sx = nxt.ok ? nxt.x : 1e100, sy = nxt.ok ? nxt.y : 1e100;
+                const double su = nxt.ok ? nxt.w : 0.0;
+                nxt = fetch(k2, b2);
+                if (uniform(cmode[k]) == kCellSym) {
+                    double br = 0.0, bi = 0.0;
 #pragma unroll
                     for (int blk = 0; blk < NB; ++blk) {
                         const int q = 8 * blk + row;
@@ -739,60 +747,62 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                         br = fma(u, lg, br);
                         bi = fma(u, atr, bi);
                     }
-                };
-                switch (nblk) {
-                case 1: sym_round(std::integral_constant<int, 1>{}); break;
-                case 2: sym_round(std::integral_constant<int, 2>{}); break;
-                case 3: sym_round(std::integral_constant<int, 3>{}); break;
-                case 4: sym_round(std::integral_constant<int, 4>{}); break;
-                case 5: sym_round(std::integral_constant<int, 5>{}); break;
-                case 6: sym_round(std::integral_constant<int, 6>{}); break;
-                case 7: sym_round(std::integral_constant<int, 7>{}); break;
-                default: sym_round(std::integral_constant<int, 8>{}); break;
-                }
+                    // B's sums over the rows (lane ^ 8, ^ 16, ^ 32), with
+                    // permute addresses computed once
+                    br += bperm_f64(perm8, br);
+                    bi += bperm_f64(perm8, bi);
+                    br += bperm_f64(perm16, br);
+                    bi += bperm_f64(perm16, bi);
+                    br += bperm_f64(perm32, br);
+                    bi += bperm_f64(perm32, bi);
+                    const int32_t i = b + col;
+                    if (row == 0 && i < ce)
+                        J.bside64[(int64_t)uniform(cslot[k]) * J.n_tgt + i] = make_double2(0.5 * br, bi);
+                } else {
+                    // one side; a zero separation (the point itself, or an
+                    // equal point) is skipped
 #pragma unroll
-                for (int o = 8; o < 64; o <<= 1) {
-                    br += shfl_xor_f64(br, o);
-                    bi += shfl_xor_f64(bi, o);
+                    for (int blk = 0; blk < NB; ++blk) {
+                        const int q = 8 * blk + row;
+                        const double dx = sax[q] - sx, dy = say[q] - sy;
+                        const double r2 = fma(dx, dx, dy * dy);
+                        const bool live = r2 > 0.0;
+                        double lg, at;
+                        ln_atan2_f64(live ? r2 : 1.0, dy, live ? dx : 1.0, lg, at);
+                        const double w = live ? su : 0.0;
+                        ar[blk] = fma(w, lg, ar[blk]);
+                        ai[blk] = fma(w, at, ai[blk]);
+                    }
                 }
-                const int32_t i = b + col;
-                if (row == 0 && i < ce)
-                    J.bside64[(int64_t)uniform(cslot[k]) * J.n_tgt + i] = make_double2(0.5 * br, bi);
-            } else {
-                // one side; a zero separation (the point itself, or an equal
-                // point) is skipped
+                k = k2;
+                b = b2;
+            }
+            // A's sums over the columns; column 0 writes
 #pragma unroll
-                for (int blk = 0; blk < 8; ++blk) {
-                    if (blk >= nblk) continue;
-                    const int q = 8 * blk + row;
-                    const double dx = sax[q] - sx, dy = say[q] - sy;
-                    const double r2 = fma(dx, dx, dy * dy);
-                    const bool live = r2 > 0.0;
-                    double lg, at;
-                    ln_atan2_f64(live ? r2 : 1.0, dy, live ? dx : 1.0, lg, at);
-                    const double w = live ? su : 0.0;
-                    ar[blk] = fma(w, lg, ar[blk]);
-                    ai[blk] = fma(w, at, ai[blk]);
+            for (int blk = 0; blk < NB; ++blk) {
+                double vr = ar[blk], vi = ai[blk];
+                vr += bperm_f64(perm1, vr);
+                vi += bperm_f64(perm1, vi);
+                vr += bperm_f64(perm2, vr);
+                vi += bperm_f64(perm2, vi);
+                vr += bperm_f64(perm4, vr);
+                vi += bperm_f64(perm4, vi);
+                const int q = 8 * blk + row;
+                if (col == 0 && q < m) {
+                    J.nsum[2 * (st + q)] = 0.5 * vr;
+                    J.nsum[2 * (st + q) + 1] = vi;
                 }
             }
-            k = k2;
-            b = b2;
-        }
-        // A's sums over the columns; column 0 writes
-#pragma unroll
-        for (int blk = 0; blk < 8; ++blk) {
-            if (blk >= nblk) continue;
-            double vr = ar[blk], vi = ai[blk];
-#pragma unroll
-            for (int o = 1; o < 8; o <<= 1) {
-                vr += shfl_xor_f64(vr, o);
-                vi += shfl_xor_f64(vi, o);
-            }
-            const int q = 8 * blk + row;
-            if (col == 0 && q < m) {
-                J.nsum[2 * (st + q)] = 0.5 * vr;
-                J.nsum[2 * (st + q) + 1] = vi;
-            }
+        };
+        switch (nblk) {
+        case 1: item_rounds(std::integral_constant<int, 1>{}); break;
+        case 2: item_rounds(std::integral_constant<int, 2>{}); break;
+        case 3: item_rounds(std::integral_constant<int, 3>{}); break;
+        case 4: item_rounds(std::integral_constant<int, 4>{}); break;
+        case 5: item_rounds(std::integral_constant<int, 5>{}); break;
+        case 6: item_rounds(std::integral_constant<int, 6>{}); break;
+        case 7: item_rounds(std::integral_constant<int, 7>{}); break;
+        default: item_rounds(std::integral_constant<int, 8>{}); break;
         }
     }
 }
