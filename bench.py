@@ -104,6 +104,8 @@ def parse():
                     help="points per side of the clustered-input leg (0 = skip)")
     ap.add_argument("--streams", type=int, default=3,
                     help="streams that consecutive solves take turns on (1 = all on one stream)")
+    ap.add_argument("--host-threads", type=int, default=0, choices=[0, 1],
+                    help="1: each stream's solves are issued by a host thread of its own")
     ap.add_argument("--near-stream", default="own", choices=["own", "side"],
                     help="near field on each solve's own stream (own) or beside its far field (side)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -113,19 +115,23 @@ def parse():
     return ap.parse_args()
 
 
-def run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs, streams, near_stream="own"):
+def run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs, streams, near_stream="own",
+              threads=False):
     """`steps` passes of plan + evaluate per tiling.  Consecutive solves take
     turns on the given streams, so one solve's plan (short, latency-bound
     kernels and two host read-backs) runs while the previous solve's
-    evaluation occupies the GPU.  Plans are released without a host wait;
-    the last pass's plans are returned open so their event timings can be
-    read after the clock."""
+    evaluation occupies the GPU.  With `threads`, each stream's solves are
+    issued by a host thread of its own (the library calls release the
+    interpreter lock), so one solve's read-backs do not hold back the
+    others' launches.  Plans are released without a host wait; the last
+    pass's plans are returned open so their event timings can be read after
+    the clock."""
+    solves = [(step, t, streams[j % len(streams)])
+              for j, (step, t) in enumerate((s, t) for s in range(steps) for t in tilings)]
     kept = {}
-    j = 0
-    for step in range(steps):
-        for t in tilings:
-            st = streams[j % len(streams)]
-            j += 1
+
+    def issue(mine):
+        for step, t, st in mine:
             plan = F.Plan(t, src=pts, tgt=pts, eps=eps, precision=prec, leaf_size=leaf, stream=st,
                           near_stream=near_stream)
             plan.eval(u, out=outs[t])
@@ -133,18 +139,40 @@ def run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs, streams, 
                 kept[t] = plan
             else:
                 plan.close()
+
+    if not threads or len(streams) == 1:
+        issue(solves)
+        return kept
+    import threading
+    errors = []
+
+    def worker(k):
+        try:
+            issue([x for x in solves if x[2] is streams[k]])
+        except BaseException as e:   # re-raised on the main thread
+            errors.append(e)
+
+    pool = [threading.Thread(target=worker, args=(k,)) for k in range(len(streams))]
+    for th in pool:
+        th.start()
+    for th in pool:
+        th.join()
+    if errors:
+        raise errors[0]
     return kept
 
 
-def timed(F, torch, pts, u, tilings, eps, prec, leaf, steps, warmup, outs, n_streams=3, near_stream="own"):
+def timed(F, torch, pts, u, tilings, eps, prec, leaf, steps, warmup, outs, n_streams=3, near_stream="own",
+          threads=False):
     # torch's current stream alone, or that many new default-priority streams
     streams = ([torch.cuda.current_stream()] if n_streams <= 1 else
                [torch.cuda.Stream() for _ in range(n_streams)])
-    for plan in run_steps(F, torch, pts, u, tilings, eps, prec, leaf, warmup, outs, streams, near_stream).values():
+    for plan in run_steps(F, torch, pts, u, tilings, eps, prec, leaf, warmup, outs, streams, near_stream,
+                          threads).values():
         plan.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    kept = run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs, streams, near_stream)
+    kept = run_steps(F, torch, pts, u, tilings, eps, prec, leaf, steps, outs, streams, near_stream, threads)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     infos = {}
@@ -363,7 +391,7 @@ def main():
           (a.n, tilings, a.precision, a.steps, a.warmup), file=sys.stderr, flush=True)
 
     wall, infos = timed(F, torch, pts, u, tilings, a.eps, a.precision, a.leaf, a.steps, a.warmup, outs,
-                        a.streams, a.near_stream)
+                        a.streams, a.near_stream, bool(a.host_threads))
     value = len(tilings) * a.n * a.steps / wall
     prec_used = infos[tilings[0]][-1]["precision"]
     print("bench: timed %.3f s -> %.4g targets/s (%s)" % (wall, value, prec_used), file=sys.stderr,
@@ -408,7 +436,7 @@ def main():
 
     if a.compare_fp64 and prec_used != "fp64":
         wall64, infos64 = timed(F, torch, pts, u, tilings, a.eps, "fp64", a.leaf, a.steps, 1, outs, a.streams,
-                                a.near_stream)
+                                a.near_stream, bool(a.host_threads))
         extra["fp64_form"] = {"value": len(tilings) * a.n * a.steps / wall64,
                               "ms_per_step": wall64 / a.steps * 1e3,
                               "errors": error_check(oracle, w, outs, infos64, tilings, a.check)}
@@ -416,7 +444,7 @@ def main():
               flush=True)
         # The same workload at eps 1e-10 (FP64 only: p 38 / 35 / 46).
         wall10, infos10 = timed(F, torch, pts, u, tilings, 1e-10, "fp64", a.leaf, a.steps, 1, outs, a.streams,
-                                a.near_stream)
+                                a.near_stream, bool(a.host_threads))
         extra["fp64_eps1e-10"] = {
             "value": len(tilings) * a.n * a.steps / wall10, "ms_per_step": wall10 / a.steps * 1e3,
             "per_tiling": {t: {"p": infos10[t][-1]["p"],
@@ -450,7 +478,8 @@ def main():
         "config": {"workload": "N=M=2^20 uniform unit square, sources=targets, u~U[-1,1], "
                                "eps=%g, leaf %d, one plan+eval per tiling (%s) per step" %
                                (a.eps, a.leaf, "+".join(tilings)),
-                   "precision": prec_used, "n": a.n, "streams": a.streams, "near_stream": a.near_stream},
+                   "precision": prec_used, "n": a.n, "streams": a.streams, "near_stream": a.near_stream,
+                   "host_threads": a.host_threads},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "extra": extra,

@@ -35,3 +35,44 @@ def test_symmetric_mix_by_hand():
 def test_one_sided_plans_use_the_per_pair_count():
     for prec in ("mixed", "fp64"):
         assert bench.near_valu_ops(level(), prec, False, 1234) == 1234 * bench.VALU_PER_PAIR[prec]
+
+
+class _FakeF:
+    """Stands in for the binding: records which stream each solve was issued on."""
+
+    def __init__(self):
+        import threading
+        self.log = []
+        self.mu = threading.Lock()
+        F = self
+
+        class Plan:
+            def __init__(self, t, stream=None, **kw):
+                self.t, self.stream, self.closed = t, stream, False
+
+            def eval(self, u, out=None):
+                with F.mu:
+                    F.log.append((self.t, self.stream))
+
+            def close(self):
+                self.closed = True
+
+        self.Plan = Plan
+
+
+def test_run_steps_issue_order_with_and_without_threads():
+    # every solve issued once, solve j on stream j mod S, each stream's solves
+    # in step order, and the last step's plans returned open
+    tilings = ["quad", "sept", "tri"]
+    for threads in (False, True):
+        for streams in (["s0"], ["s0", "s1"], ["s0", "s1", "s2"]):
+            F = _FakeF()
+            kept = bench.run_steps(F, None, None, None, tilings, 1e-6, "mixed", 64, 4,
+                                   {t: None for t in tilings}, streams, threads=threads)
+            want = [(t, streams[j % len(streams)])
+                    for j, t in enumerate(t for _ in range(4) for t in tilings)]
+            assert sorted(F.log) == sorted(want)
+            for st in streams:
+                assert [x for x in F.log if x[1] == st] == [x for x in want if x[1] == st]
+            assert sorted(kept) == sorted(tilings)
+            assert not any(p.closed for p in kept.values())
