@@ -660,9 +660,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
 
         __syncthreads();   // the previous item is done with the LDS
         {
+            // Padding targets: zero strength, far from every source and from
+            // the padding source, so no separation in the tile is zero (the
+            // symmetric rounds have no zero-separation guard, and a zero
+            // there would turn a padding row's 0 x log 0 into a NaN in the
+            // B-side sums).
             const bool ok = lane < m;
-            sax[lane] = ok ? J.tx[st + lane] : 0.0;
-            say[lane] = ok ? J.ty[st + lane] : 0.0;
+            sax[lane] = ok ? J.tx[st + lane] : -1e100;
+            say[lane] = ok ? J.ty[st + lane] : -1e100;
             sau[lane] = ok ? J.su[st + lane] : 0.0;
         }
         if (lane < nw) {

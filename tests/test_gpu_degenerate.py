@@ -1,0 +1,86 @@
+"""GPU parity on degenerate point sets, both precisions, sources = targets:
+a regular lattice (many pairs with exactly equal y, so the near field meets
+log's branch cut on the negative real axis exactly: Im log(y - x) = +pi for a
+negative real difference, as in the oracle), points on one horizontal and one
+vertical line (a box of zero height or width), and all points at one place
+(a box of zero size: every pair coincident, so Phi is exactly zero).  Bars:
+1e-12 relative L2 for FP64, eps = 1e-6 for the mixed form, and for the lattice
+no target off by more than a small fraction of pi."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+TILES = ["quad", "sept", "tri"]
+BAR = {"fp64": 1e-12, "mixed": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def F():
+    from paper_1204_3105_amd import fmm
+    fmm.lib()
+    return fmm
+
+
+def say(*a):
+    print("[degenerate]", *a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def against_oracle(F, orc, tiling, prec, xs, ys, u, leaf, depth="mean"):
+    with F.Plan(tiling, xs, ys, eps=1e-6, precision=prec, leaf_size=leaf, depth=depth) as plan:
+        inf = plan.info()
+        phi = plan.eval(u)
+    g = orc.geom(tiling, inf["lmax"], *inf["geometry"])
+    ref = orc.fmm(g, inf["p"], xs, ys, u, xs, ys)
+    return phi, ref
+
+
+@pytest.mark.parametrize("tiling", TILES)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lattice(F, orc, tiling, prec):
+    say("lattice", tiling, prec)
+    k = 56
+    gx, gy = np.meshgrid(np.arange(k) / k, np.arange(k) / k)
+    xs, ys = gx.ravel().copy(), gy.ravel().copy()
+    u = np.random.default_rng(21).uniform(-1.0, 1.0, xs.size)
+    phi, ref = against_oracle(F, orc, tiling, prec, xs, ys, u, 32)
+    e = rel(phi, ref)
+    worst = float(np.max(np.abs(phi.imag - ref.imag)))
+    say("lattice %s %s rel_l2=%.3e max|dIm|=%.3e" % (tiling, prec, e, worst))
+    assert e <= BAR[prec]
+    assert worst < 1e-3
+
+
+@pytest.mark.parametrize("tiling", TILES)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_lines(F, orc, tiling, prec):
+    g = np.random.default_rng(22)
+    n = 3000
+    t = g.random(n)
+    u = g.uniform(-1.0, 1.0, n)
+    errs = []
+    for name, xs, ys in (("horizontal", t, np.full(n, 0.25)), ("vertical", np.full(n, -0.5), t)):
+        for depth in ("mean", "cost"):
+            say("line", name, tiling, prec, depth)
+            phi, ref = against_oracle(F, orc, tiling, prec, xs, ys, u, 64, depth)
+            e = rel(phi, ref)
+            say("line %s %s %s %s rel_l2=%.3e" % (name, tiling, prec, depth, e))
+            errs.append(e)
+    assert max(errs) <= (BAR[prec] if prec == "fp64" else 1e-5)
+
+
+@pytest.mark.parametrize("tiling", TILES)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_all_points_coincident(F, tiling, prec):
+    say("coincident", tiling, prec)
+    n = 700
+    u = np.random.default_rng(23).uniform(-1.0, 1.0, n)
+    with F.Plan(tiling, np.full(n, 0.3), np.full(n, -0.7), eps=1e-6, precision=prec) as plan:
+        phi = plan.eval(u)
+    assert phi.shape == (n,)
+    assert np.all(phi == 0)
