@@ -84,3 +84,32 @@ def test_all_points_coincident(F, tiling, prec):
         phi = plan.eval(u)
     assert phi.shape == (n,)
     assert np.all(phi == 0)
+
+
+@pytest.mark.parametrize("tiling", TILES)
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_targets_on_sources_and_cuts(F, orc, tiling, prec):
+    """Sources != targets: a third of the targets sit exactly on sources (the
+    pair is skipped), a third share a source's y exactly with a shift in x
+    (the pair on the branch cut, either side of the source), a third on a
+    regular lattice."""
+    say("targets on sources and cuts", tiling, prec)
+    g = np.random.default_rng(24)
+    ns, k = 4000, 500
+    xs, ys = g.random(ns), g.random(ns)
+    u = g.uniform(-1.0, 1.0, ns)
+    pick = g.choice(ns, 2 * k, replace=False)
+    shift = g.uniform(-2e-3, 2e-3, k)
+    gx, gy = np.meshgrid(np.arange(25) / 25, np.arange(20) / 20)
+    xt = np.concatenate([xs[pick[:k]], np.clip(xs[pick[k:]] + shift, 0.0, 1.0), gx.ravel()])
+    yt = np.concatenate([ys[pick[:k]], ys[pick[k:]], gy.ravel()])
+    with F.Plan(tiling, xs, ys, xt, yt, eps=1e-6, precision=prec, leaf_size=32) as plan:
+        inf = plan.info()
+        phi = plan.eval(u)
+    geo = orc.geom(tiling, inf["lmax"], *inf["geometry"])
+    ref = orc.fmm(geo, inf["p"], xs, ys, u, xt, yt)
+    e = rel(phi, ref)
+    worst = float(np.max(np.abs(phi.imag - ref.imag)))
+    say("targets on sources and cuts %s %s rel_l2=%.3e max|dIm|=%.3e" % (tiling, prec, e, worst))
+    assert e <= BAR[prec]
+    assert worst < 1e-3
