@@ -91,8 +91,12 @@ def test_all_points_coincident(F, tiling, prec):
 def test_targets_on_sources_and_cuts(F, orc, tiling, prec):
     """Sources != targets: a third of the targets sit exactly on sources (the
     pair is skipped), a third share a source's y exactly with a shift in x
-    (the pair on the branch cut, either side of the source), a third on a
-    regular lattice."""
+    of at most 2e-3 (the pair on the branch cut, either side of the source),
+    a third on a regular lattice.  The planted pairs are close: the mixed
+    form's FP32 leaf offsets (rounded by 2^-25 of the leaf's extent h) put an
+    error of about 2^-24 h/d on ln|r| at separation d, so its bar here is
+    1e-5 in relative L2; the branch cut is pinned by Im, which no target may
+    miss by 1e-3."""
     say("targets on sources and cuts", tiling, prec)
     g = np.random.default_rng(24)
     ns, k = 4000, 500
@@ -111,5 +115,5 @@ def test_targets_on_sources_and_cuts(F, orc, tiling, prec):
     e = rel(phi, ref)
     worst = float(np.max(np.abs(phi.imag - ref.imag)))
     say("targets on sources and cuts %s %s rel_l2=%.3e max|dIm|=%.3e" % (tiling, prec, e, worst))
-    assert e <= BAR[prec]
+    assert e <= (BAR[prec] if prec == "fp64" else 1e-5)
     assert worst < 1e-3
