@@ -58,7 +58,13 @@ typedef enum {
     FMM_PREC_FP64 = 1,    /* every step in FP64                               */
     FMM_PREC_MIXED = 2    /* M2L as BF16x3 split products on MFMA with FP32
                              accumulation, P2P in FP32 with compensated sums;
-                             monopole/log terms, P2M, M2M, L2L, L2P in FP64   */
+                             monopole/log terms, P2M, M2M, L2L, L2P in FP64.
+                             P2P takes FP32 offsets from leaf centres, so a
+                             pair at separation d in leaves of extent h
+                             carries about 2^-24 h/d in ln|r|: inputs with
+                             many pairs far closer than their leaves are
+                             wide (points on a curve, targets planted next
+                             to sources) can miss eps; use FP64 for them   */
 } fmm_precision;
 
 typedef enum {
