@@ -365,7 +365,7 @@ def m2l_mfma(infos, tilings):
 def main():
     a = parse()
     if a.gpus != 1:
-        print("bench.py runs on one GPU: this build has no multi-GPU path "
+        print("bench.py runs on one GPU: the library has no multi-GPU path "
               "(requested --gpus %d)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
