@@ -286,3 +286,23 @@ def test_coincident_pairs_are_skipped(orc):
     d1 = orc.direct_principal(xs, ys, u, xs[:1], ys[:1])
     want = u[2] * np.log(complex(0.2 - 0.7, 0.3 - 0.1))
     assert abs(d1[0] - want) < 1e-15
+
+
+def test_direct_on_a_lattice_takes_plus_pi_on_the_cut(orc):
+    """D1 on a 9 x 7 lattice, targets = sources: many differences are exactly
+    negative real (equal y, +0 imaginary part), where the principal Log has
+    Im = +pi; coincident pairs are skipped.  Brute force with numpy's complex
+    log on the same differences."""
+    gx, gy = np.meshgrid(np.arange(9) / 9.0, np.arange(7) / 7.0)
+    x, y = gx.ravel(), gy.ravel()
+    u = np.random.default_rng(31).uniform(-1.0, 1.0, x.size)
+    got = orc.direct_principal(x, y, u, x, y)
+    want = np.zeros(x.size, dtype=complex)
+    for j in range(x.size):
+        for i in range(x.size):
+            if i != j:
+                want[j] += u[i] * np.log(complex(x[j] - x[i], y[j] - y[i]))
+    assert np.max(np.abs(got - want)) <= 1e-13 * np.sum(np.abs(u)) * 10
+    # a pair on the cut: the left neighbour seen from its right neighbour's
+    # source has Im exactly pi
+    assert np.log(complex(x[0] - x[1], y[0] - y[1])).imag == np.pi
