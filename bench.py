@@ -243,7 +243,7 @@ def cpu_baseline(orc, w, infos, tilings, sample):
 
 
 def serve_bench(F, nreq, load, leaf):
-    """cfg5-shaped stream: N log-uniform in [1e3, 2e6], uniform or 4-Gaussian
+    """Mixed request stream: N log-uniform in [1e3, 2e6], uniform or 4-Gaussian
     sources (50/50), tiling uniform over three, eps in {1e-4, 1e-8}.  First
     all requests at once (saturated throughput), then Poisson arrivals at
     `load` times the saturated request rate; latency = end - submit."""

@@ -126,7 +126,7 @@ def test_fp64_separate_clustered(F, orc, tiling):
 
 @pytest.mark.parametrize("tiling", TILES)
 def test_fp64_matches_direct_sum_at_eps(F, orc, tiling):
-    """cfg1-shaped: N = M = 4096 uniform, eps-derived p: rel L2 vs the
+    """N = M = 4096 uniform (the points of the quadtree p = 20 case), eps-derived p: rel L2 vs the
     principal direct sum (Re) and the branch-aware direct sum (complex)."""
     say("direct", tiling)
     w = inputs.uniform_square(4096, seed=1)
@@ -139,7 +139,7 @@ def test_fp64_matches_direct_sum_at_eps(F, orc, tiling):
     assert rel(phi, d2) <= 1e-10
 
 
-def test_quad_cfg1_p20(F, orc):
+def test_quad_4096_p20(F, orc):
     """Quadtree FP64, N = M = 4096 uniform, p = 20, mean <= 32 per leaf."""
     w = inputs.uniform_square(4096, seed=1)
     with F.Plan("quad", w.xs, w.ys, eps=1e-6, p=20, precision="fp64", leaf_size=32) as plan:

@@ -168,16 +168,16 @@ def test_upward_pass_equals_direct_p2m(orc, tiling):
 
 
 # -------------------------------------------------------------- full sweep
-def cfg1_like(orc, n=4096, seed=1):
+def uniform_4096(orc, n=4096, seed=1):
     w = inputs.uniform_square(n, seed=seed)
     return w, quad_geom(orc, w.xs, w.ys, 4)
 
 
-def test_fmm_quad_cfg1_against_direct(orc):
+def test_fmm_quad_4096_against_direct(orc):
     """Quadtree, N = M = 4096 uniform, p = 20, mean 16 per leaf: relative
     L2 error of Re vs the principal direct sum and of the complex value vs
     the branch-aware direct sum."""
-    w, g = cfg1_like(orc)
+    w, g = uniform_4096(orc)
     phi = orc.fmm(g, 20, w.xs, w.ys, w.u, w.xt, w.yt)
     d1 = orc.direct_principal(w.xs, w.ys, w.u, w.xt, w.yt)
     d2 = orc.direct_branch_aware(g, w.xs, w.ys, w.u, w.xt, w.yt)
