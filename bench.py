@@ -29,10 +29,10 @@ sys.path.insert(0, ROOT)
 # x 2.4 GHz (FP64 and non-packed FP32 issue at the same rate).
 LANE_OPS = 256 * 4 * 16 * 2.4e9
 # VALU instructions per source-target pair in the near-field inner loops of
-# our gfx950 build (counted from the kernels' AMD assembly; see the design
-# notes): the one-sided kernels (FP64, and mixed with separate targets), and
-# the symmetric mixed kernel (targets = sources), where one evaluation of a
-# neighbour pair serves both of its sides and the leaf itself is one-sided.
+# the gfx950 code (counted in the kernels' AMD assembly as the compiler emits
+# it): the one-sided kernels (FP64, and mixed with separate targets), and the
+# symmetric kernels (targets = sources), where one evaluation of a neighbour
+# pair serves both of its sides and the leaf itself is one-sided.
 VALU_PER_PAIR = {"fp64": 104.0, "mixed": 31.0}
 VALU_SYM_EVAL = {"mixed": 30.5, "fp64": 92.0}
 VALU_SYM_ONE_SIDED = {"mixed": 30.0, "fp64": 104.0}
@@ -242,6 +242,27 @@ def cpu_baseline(orc, w, infos, tilings, sample):
             "sample": sample, "detail": detail}
 
 
+def near_roofline(infos, tilings, prec):
+    """The dominant kernel, the P2P near-field launch, against the VALU issue
+    rate (FP64 VALU issues at the FP32 rate on this chip).  It runs beside
+    the far-field passes and other solves, so its duration includes sharing
+    the GPU with them."""
+    near_ms = np.mean([i["stage_ms"][3] for t in tilings for i in infos[t]])
+    pairs = np.mean([i["n_near_pairs"] for t in tilings for i in infos[t]])
+    ops = np.mean([i["near_valu_ops"] for t in tilings for i in infos[t]])
+    ach = ops / (near_ms * 1e-3)
+    sym = all(i["targets_are_sources"] for t in tilings for i in infos[t])
+    kname = ("k_near_mixed" if prec == "mixed" else "k_near_fp64") + ("_sym" if sym else "")
+    traffic = committed_traffic(kname) if prec == "mixed" else None
+    return {"bound": "alu", "kernel": "near field (P2P), %s" % kname, "achieved": ach / 1e9,
+            "peak": LANE_OPS / 1e9, "unit": "G VALU lane-op/s", "frac": ach / LANE_OPS, "traffic": traffic,
+            "avg_launch_ms": float(near_ms), "pairs_per_launch": float(pairs),
+            "valu_ops_per_launch": float(ops),
+            "valu_per_pair": ({"symmetric_eval": VALU_SYM_EVAL[prec],
+                               "one_sided": VALU_SYM_ONE_SIDED[prec]}
+                              if sym else VALU_PER_PAIR[prec])}
+
+
 def serve_bench(F, nreq, load, leaf):
     """Mixed request stream: N log-uniform in [1e3, 2e6], uniform or 4-Gaussian
     sources (50/50), tiling uniform over three, eps in {1e-4, 1e-8}.  First
@@ -397,23 +418,7 @@ def main():
     print("bench: timed %.3f s -> %.4g targets/s (%s)" % (wall, value, prec_used), file=sys.stderr,
           flush=True)
 
-    # Dominant kernel: the P2P near-field launch (it runs beside the far-field
-    # passes, so its duration includes sharing the GPU with them).
-    near_ms = np.mean([i["stage_ms"][3] for t in tilings for i in infos[t]])
-    pairs = np.mean([i["n_near_pairs"] for t in tilings for i in infos[t]])
-    ops = np.mean([i["near_valu_ops"] for t in tilings for i in infos[t]])
-    ach = ops / (near_ms * 1e-3)
-    peak = LANE_OPS
-    sym = all(i["targets_are_sources"] for t in tilings for i in infos[t])
-    kname = ("k_near_mixed" if prec_used == "mixed" else "k_near_fp64") + ("_sym" if sym else "")
-    traffic = committed_traffic(kname) if prec_used == "mixed" else None
-    roofline = {"bound": "alu", "kernel": "near field (P2P), %s" % kname, "achieved": ach / 1e9,
-                "peak": peak / 1e9, "unit": "G VALU lane-op/s", "frac": ach / peak, "traffic": traffic,
-                "avg_launch_ms": float(near_ms), "pairs_per_launch": float(pairs),
-                "valu_ops_per_launch": float(ops),
-                "valu_per_pair": ({"symmetric_eval": VALU_SYM_EVAL[prec_used],
-                                   "one_sided": VALU_SYM_ONE_SIDED[prec_used]}
-                                  if sym else VALU_PER_PAIR[prec_used])}
+    roofline = near_roofline(infos, tilings, prec_used)
 
     per_tiling = {}
     for t in tilings:
@@ -439,6 +444,7 @@ def main():
                                 a.near_stream, bool(a.host_threads))
         extra["fp64_form"] = {"value": len(tilings) * a.n * a.steps / wall64,
                               "ms_per_step": wall64 / a.steps * 1e3,
+                              "near_roofline": near_roofline(infos64, tilings, "fp64"),
                               "errors": error_check(oracle, w, outs, infos64, tilings, a.check)}
         print("bench: plain FP64 form %.4g targets/s" % extra["fp64_form"]["value"], file=sys.stderr,
               flush=True)

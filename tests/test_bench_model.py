@@ -76,3 +76,18 @@ def test_run_steps_issue_order_with_and_without_threads():
                 assert [x for x in F.log if x[1] == st] == [x for x in want if x[1] == st]
             assert sorted(kept) == sorted(tilings)
             assert not any(p.closed for p in kept.values())
+
+
+def test_near_roofline_from_plan_infos():
+    # two tilings, one launch each: VALU operations over the launch time
+    # against the issue rate; FP64 carries no committed traffic figure
+    infos = {"quad": [{"stage_ms": [0, 0, 0, 0.5, 0], "n_near_pairs": 100, "near_valu_ops": 4e9,
+                       "targets_are_sources": True}],
+             "tri": [{"stage_ms": [0, 0, 0, 1.5, 0], "n_near_pairs": 300, "near_valu_ops": 8e9,
+                      "targets_are_sources": True}]}
+    r = bench.near_roofline(infos, ["quad", "tri"], "fp64")
+    assert r["kernel"].endswith("k_near_fp64_sym")
+    assert r["traffic"] is None
+    assert abs(r["achieved"] * 1e9 - 6e9 / 1e-3) < 1.0
+    assert abs(r["frac"] - 6e12 / bench.LANE_OPS) < 1e-12
+    assert r["valu_per_pair"] == {"symmetric_eval": 92.0, "one_sided": 104.0}
