@@ -306,3 +306,26 @@ def test_direct_on_a_lattice_takes_plus_pi_on_the_cut(orc):
     # a pair on the cut: the left neighbour seen from its right neighbour's
     # source has Im exactly pi
     assert np.log(complex(x[0] - x[1], y[0] - y[1])).imag == np.pi
+
+
+@pytest.mark.parametrize("tiling", ["quad", "sept", "tri"])
+def test_fmm_on_a_lattice_converges_to_branch_aware_sum(orc, tiling):
+    """A 40 x 40 regular lattice, targets = sources: pairs exactly on the
+    branch cut (equal y), pairs with dx = 0, points on cell edges.  At p = 45
+    the FMM equals the branch-aware direct sum to rounding, and Re the
+    principal one."""
+    k = 40
+    gx, gy = np.meshgrid(np.arange(k) / k, np.arange(k) / k)
+    x, y = gx.ravel().copy(), gy.ravel().copy()
+    u = np.random.default_rng(32).uniform(-1.0, 1.0, x.size)
+    if tiling == "quad":
+        g = quad_geom(orc, x, y, 3)
+    elif tiling == "sept":
+        g = sept_geom(orc, 0.5, 0.5, 0.04, 4)
+    else:
+        g = tri_geom(orc, 0.5, 0.5, 0.75, 4)
+    d1 = orc.direct_principal(x, y, u, x, y)
+    d2 = orc.direct_branch_aware(g, x, y, u, x, y)
+    phi = orc.fmm(g, 45, x, y, u, x, y)
+    assert rel(phi.real, d1.real) < 1e-12
+    assert rel(phi, d2) < 1e-12
