@@ -59,12 +59,15 @@ typedef enum {
     FMM_PREC_MIXED = 2    /* M2L as BF16x3 split products on MFMA with FP32
                              accumulation, P2P in FP32 with compensated sums;
                              monopole/log terms, P2M, M2M, L2L, L2P in FP64.
-                             P2P takes FP32 offsets from leaf centres, so a
-                             pair at separation d in leaves of extent h
-                             carries about 2^-24 h/d in ln|r|: inputs with
-                             many pairs far closer than their leaves are
-                             wide (points on a curve, targets planted next
-                             to sources) can miss eps; use FP64 for them   */
+                             P2P takes FP32 offsets from leaf centres; pairs
+                             closer than 1/32 of the leaf scale, and pairs
+                             near the log's branch cut, are formed again
+                             from the FP64 coordinates, so the error does
+                             not grow for points on curves or planted next
+                             to each other.  Its arithmetic floor is about
+                             2e-8 in relative L2: for eps below 1e-6 a MIXED
+                             request is resolved to FP64 (fmm_plan_info
+                             reports the precision used)                  */
 } fmm_precision;
 
 typedef enum {

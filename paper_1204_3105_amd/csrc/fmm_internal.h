@@ -29,6 +29,7 @@ constexpr int kMaxP = 60;         // highest expansion order
 constexpr int kMaxSlots = 42;     // largest E4 list (septree)
 constexpr int kNearSlots = 13;    // largest closed neighbourhood (triangles)
 constexpr int kMaxGroups = 8;     // M2L target groups (triangle: 4 types x 2)
+constexpr double kMixedMinEps = 1e-6;   // smallest eps the mixed form is used for
 constexpr int kChunk = 64;        // targets per near-field work item (at most)
 // A leaf with at most this many chunks of kChunk targets evaluates the pairs
 // with its higher-indexed neighbours for both sides (mixed, targets = sources).

@@ -48,21 +48,53 @@ __device__ __forceinline__ float atan2_abs(float y, float x, float &mn)
     return (x < 0.0f) ? kPi - a : a;
 }
 
-// The FP32 offsets carry a vertical separation with an absolute error of
-// at most 9 * 2^-24 of the leaf scale (two offsets within a leaf, the
-// leaf-to-leaf offset and one rounded sum), enough to give a tiny dy the
-// wrong sign or make it zero.  Near the negative real axis that moves the
-// pair across the logarithm's principal branch cut, and its argument jumps
-// by 2 pi.  So where |dy| is below 2^-19 of the scale (about one pair in
-// 10^6), the sign is taken from the FP64 coordinates instead: +1, -1, or +0
-// when they are equal (the principal branch's arg = pi).  The hot loops
-// take the FP32 sign and only keep each lane's smallest |dy|; a round in
-// which some lane saw |dy| below the bound is gone over again for those
-// pairs, and the argument terms are corrected by the difference.
-__device__ __forceinline__ float dy_sign_fp64(const EvalJob &J, int32_t t, int32_t i)
+// The FP32 offsets carry a separation with an absolute error of at most
+// about 9 * 2^-24 of the leaf scale h (two offsets within a leaf, the
+// leaf-to-leaf offset and one rounded sum).  Two kinds of pair are hurt by it
+// and are evaluated again from the FP64 coordinates:
+//  - near the negative real axis a tiny dy can get the wrong sign or become
+//    zero, which moves the pair across the logarithm's principal branch cut
+//    (its argument jumps by 2 pi): pairs with |dy| below 2^-19 h (about one
+//    pair in 10^6 for spread-out points);
+//  - a pair at separation d carries about 2^-24 h / d in ln|r| and in its
+//    argument, which points on a curve or planted next to each other (d far
+//    below h) turn into errors above eps: pairs with r^2 below (h 2^-5)^2, so
+//    that every pair kept in FP32 has h / d < 32.
+// For those pairs the separation is formed in FP64 from the absolute
+// coordinates and rounded to FP32 (relative error 2^-24, whatever d), the
+// sign of dy taken from the FP64 difference (+0 when the coordinates are
+// equal: the principal branch's arg = pi), and the log and argument terms
+// are corrected by the difference to what the hot loop summed.  The hot
+// loops only keep each lane's smallest |dy| (or min(|dx|, |dy|), a cheap bound
+// for it) and smallest r^2; a round in which some lane saw a value below its
+// bound is gone over again for those pairs.  A pair of points with equal FP64
+// coordinates contributes nothing, whatever its FP32 offsets.
+constexpr float kCloseTau = 0x1p-5f;   // close-pair radius in units of the leaf scale
+
+__device__ __forceinline__ float close_tau2(const EvalJob &J)
 {
-    const double a = J.ty[t], b = J.sy[i];
-    return a > b ? 1.0f : (a < b ? -1.0f : 0.0f);
+    const float t = (float)J.scale[J.L] * kCloseTau;
+    return t * t;
+}
+
+// The pair (target t, source i) from the FP64 coordinates: the separation
+// rounded to FP32, the sign of dy (+1, -1, or +0 for equal y) and whether the
+// two points differ at all (the FP64 difference of finite values is zero only
+// for equal values).
+struct Pair64 {
+    float ex, ey, sg;
+    bool live;
+};
+
+__device__ __forceinline__ Pair64 pair_fp64(const EvalJob &J, int32_t t, int32_t i)
+{
+    const double ddx = J.tx[t] - J.sx[i], ddy = J.ty[t] - J.sy[i];
+    Pair64 r;
+    r.ex = (float)ddx;
+    r.ey = (float)ddy;
+    r.sg = ddy > 0.0 ? 1.0f : (ddy < 0.0 ? -1.0f : 0.0f);
+    r.live = ddx != 0.0 || ddy != 0.0;
+    return r;
 }
 
 // atan2 on the principal branch (-pi, pi]; y = -0 is treated as +0 and
@@ -152,7 +184,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 5 : 
         const float tlx = in ? J.txl[t] : 0.0f, tly = in ? J.tyl[t] : 0.0f;
         const double tx = FIELD && in ? J.tx[t] : 0.0, ty = FIELD && in ? J.ty[t] : 0.0;
         const double tcx = J.cx[gid], tcy = J.cy[gid];
-        const float dtol = (float)(J.scale[J.L] * 0x1p-19);
+        const float dtol = (float)(J.scale[J.L] * 0x1p-19), tau2 = close_tau2(J);
 
         // Near-cell table (slot 0 is the leaf itself); an absent cell has an
         // empty range.
@@ -237,7 +269,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 5 : 
             __syncthreads();
             const float ax = tlx - (busy ? cdx[k] : 0.0f);
             const float ay = tly - (busy ? cdy[k] : 0.0f);
-            float worst = 1e30f;   // smallest |dy| of the round
+            float worst = 1e30f, wclose = 1e30f;   // smallest |dy| and r^2 of the round
             if (self_round) {
                 for (int j = 0; j < padn; ++j) {
                     const float4 sv = gsh[j];
@@ -247,6 +279,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 5 : 
                     const float lg = __log2f(live ? r2 : 1.0f);
                     const float at = atan2_f32(dy, dx);
                     worst = fminf(worst, fabsf(dy));
+                    wclose = fminf(wclose, r2);
                     acc(live ? sv.z * lg : 0.0f, live ? sv.w * at : 0.0f);
                     if (FIELD) {
                         const double2 sd = gshd[j];
@@ -271,6 +304,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 5 : 
                         pr = fmaf(sv.z, __log2f(r2), pr);
                         pi = fmaf(sv.w, atan2_f32(dy, dx), pi);
                         worst = fminf(worst, fabsf(dy));
+                        wclose = fminf(wclose, r2);
                         if (FIELD) {
                             const double2 sd = gshd[j + jj];
                             const float ex = (float)(tx - sd.x), ey = (float)(ty - sd.y);
@@ -286,17 +320,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 5 : 
                     }
                 }
             }
-            if (__any(worst < dtol)) {
-                // pairs near the branch cut: the argument's sign from FP64
-                if (worst < dtol && busy) {
+            const bool flagged = worst < dtol || wclose < tau2;
+            if (__any(flagged)) {
+                // pairs near the branch cut or close together: again from
+                // the FP64 coordinates, corrected by the difference to the
+                // terms the loop above summed
+                if (flagged && busy) {
                     for (int j = 0; j < n; ++j) {
                         const float4 sv = gsh[j];
                         const float dx = ax - sv.x, dy = ay - sv.y;
-                        if (!(fabsf(dy) < dtol)) continue;
-                        if (self_round && !(fmaf(dx, dx, dy * dy) > 0.0f)) continue;   // skipped pair
-                        const float a = atan2_abs(dy, dx);
-                        const float d = signed_arg(a, dy_sign_fp64(J, t, base + j)) - signed_arg(a, dy);
-                        acc(0.0f, sv.w * d);
+                        const float r2 = self_round ? fmaf(dx, dx, dy * dy) : fmaf(dx, dx, fmaf(dy, dy, 1e-37f));
+                        if (!(fabsf(dy) < dtol || r2 < tau2)) continue;
+                        const bool live0 = !self_round || r2 > 0.0f;
+                        const float lg0 = live0 ? __log2f(r2) : 0.0f;
+                        const float at0 = live0 ? atan2_f32(dy, dx) : 0.0f;
+                        const Pair64 q = pair_fp64(J, t, base + j);
+                        const float lg1 = q.live ? __log2f(fmaf(q.ex, q.ex, fmaf(q.ey, q.ey, 1e-37f))) : 0.0f;
+                        const float at1 = q.live ? signed_arg(atan2_abs(q.ey, q.ex), q.sg) : 0.0f;
+                        acc(sv.z * (lg1 - lg0), sv.w * (at1 - at0));
                     }
                 }
             }
@@ -399,7 +440,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
         const int nblk = (m + 7) >> 3;
         const int chunk = (st - tb) / kChunk;
         const bool own_sym = (te - tb + kChunk - 1) / kChunk <= kSymChunks;
-        const float dtol = (float)(J.scale[J.L] * 0x1p-19);
+        const float dtol = (float)(J.scale[J.L] * 0x1p-19), tau2 = close_tau2(J);
 
         // Cell table: range, offset from this leaf's centre, and how the
         // cell's pairs are taken.  Slot 0 is the leaf itself.
@@ -514,24 +555,40 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
                 const float sy = nxt.ok ? nxt.ly + nxt.oy : 1e18f;
                 const float su = nxt.ok ? nxt.lw : 0.0f;
                 nxt = fetch(k2, b2);
-                // smallest min(|dx|, |dy|) of the round (bits), a cheap
-                // bound for the smallest |dy|
-                uint32_t worst = 0x7f800000u;
-                // pairs near the branch cut: the argument's sign from FP64
-                // (the B-side term only for a symmetric cell)
-                auto fix_cut = [&](bool two, float &bi) {
-                    if (!(__uint_as_float(worst) < dtol)) return;
+                // smallest min(|dx|, |dy|) (a cheap bound for the smallest
+                // |dy|) and smallest r^2 of the round, as bits
+                uint32_t worst = 0x7f800000u, wclose = 0x7f800000u;
+                auto flagged = [&]() {
+                    return __uint_as_float(worst) < dtol || __uint_as_float(wclose) < tau2;
+                };
+                // pairs near the branch cut or close together: again from the
+                // FP64 coordinates, corrected by the difference to the terms
+                // the round summed (the B-side terms only for a symmetric cell)
+                auto fix_pairs = [&](bool two, float &br, float &bi) {
+                    if (!flagged()) return;
+                    const int32_t i = b + col;
 #pragma unroll
                     for (int blk = 0; blk < NB; ++blk) {
                         const int q = 8 * blk + row;
-                        if (q < m && b + col < ce) {
+                        if (q < m && i < ce) {
                             const float4 A = sA[q];
                             const float dx = A.x - sx, dy = A.y - sy;
-                            if (fabsf(dy) < dtol && (two || fmaf(dx, dx, dy * dy) > 0.0f)) {
-                                const float sg = dy_sign_fp64(J, st + q, b + col);
-                                const float a = atan2_abs<7>(dy, dx);
-                                ai[blk] += su * (signed_arg(a, sg) - fast_arg(a, dy));
-                                if (two) bi += A.z * (reverse_arg(a, sg) + fast_rev_neg(a, dy));
+                            const float r2 = two ? fmaf(dx, dx, fmaf(dy, dy, 1e-37f)) : fmaf(dx, dx, dy * dy);
+                            if (fabsf(dy) < dtol || r2 < tau2) {
+                                const bool live0 = two || r2 > 0.0f;
+                                const float lg0 = live0 ? __log2f(r2) : 0.0f;
+                                const float a0 = atan2_abs<7>(dy, dx);
+                                const Pair64 p64 = pair_fp64(J, st + q, i);
+                                const float lg1 = p64.live ? __log2f(fmaf(p64.ex, p64.ex, fmaf(p64.ey, p64.ey, 1e-37f))) : 0.0f;
+                                const float a1 = atan2_abs(p64.ey, p64.ex);
+                                const float th1 = p64.live ? signed_arg(a1, p64.sg) : 0.0f;
+                                const float th0 = live0 ? fast_arg(a0, dy) : 0.0f;
+                                ar[blk] += su * (lg1 - lg0);
+                                ai[blk] += su * (th1 - th0);
+                                if (two) {
+                                    br += A.z * (lg1 - lg0);
+                                    bi += A.z * (reverse_arg(a1, p64.sg) + fast_rev_neg(a0, dy));
+                                }
                             }
                         }
                     }
@@ -544,16 +601,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
                         // than FP32 resolution finite
                         const float4 A = sA[8 * blk + row];
                         const float dx = A.x - sx, dy = A.y - sy;
-                        const float lg = __log2f(fmaf(dx, dx, fmaf(dy, dy, 1e-37f)));
+                        const float r2 = fmaf(dx, dx, fmaf(dy, dy, 1e-37f));
+                        const float lg = __log2f(r2);
                         float mn;
                         const float a = atan2_abs<7>(dy, dx, mn);
                         keep_min(worst, mn);
+                        keep_min(wclose, r2);
                         ar[blk] = fmaf(su, lg, ar[blk]);
                         ai[blk] = fmaf(su, fast_arg(a, dy), ai[blk]);
                         br = fmaf(A.z, lg, br);
                         bi = fmaf(-A.z, fast_rev_neg(a, dy), bi);
                     }
-                    if (__any(__uint_as_float(worst) < dtol)) fix_cut(true, bi);
+                    if (__any(flagged())) fix_pairs(true, br, bi);
                     // B's sums over the rows: lane ^ 8 by DPP (a rotation by
                     // eight within each 16-lane row), lane ^ 16 and ^ 32 by
                     // permutes with addresses computed once
@@ -580,12 +639,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
                         const float th = fast_arg(atan2_abs<7>(dy, dx, mn), dy);
                         const float w = live ? su : 0.0f;
                         keep_min(worst, mn);
+                        keep_min(wclose, r2);
                         ar[blk] = fmaf(w, lg, ar[blk]);
                         ai[blk] = fmaf(w, th, ai[blk]);
                     }
-                    if (__any(__uint_as_float(worst) < dtol)) {
-                        float unused = 0.0f;
-                        fix_cut(false, unused);
+                    if (__any(flagged())) {
+                        float unused_r = 0.0f, unused_i = 0.0f;
+                        fix_pairs(false, unused_r, unused_i);
                     }
                 }
                 k = k2;
