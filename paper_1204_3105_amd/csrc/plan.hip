@@ -344,7 +344,8 @@ int64_t plan_device_bytes(const Plan *P) { return ((const PlanImpl *)P)->device_
 // ------------------------------------------------------------ rules
 static const double kQ[3] = {
     0.54691816067802259,   // quadtree 1/(1 + 2(sqrt2 - 1))
-    0.5244,                // septree, GBT aggregates (coarse-level rho/r = 0.907)
+    0.52443357281057,      // septree, GBT aggregates: 1/(1 + rho/r) with rho/r = 0.906819,
+                           // the smallest over 0..10 levels above the leaves (reached at 8)
     0.60762521851393328    // triangle-quadtree 1/(sqrt7 - 1)
 };
 
@@ -875,8 +876,13 @@ fmm_status fmm_plan(fmm_tiling tiling, const double *src, int64_t n_src, const d
     P->same = (tgt == src) && (n_tgt == n_src);
     P->near_own_stream = o.near_stream == 1;
     P->leaf_size = o.leaf_size;
+    // The mixed form holds eps down to 1e-6 (its arithmetic floor is about
+    // 2e-8 in relative L2: FP32 pair terms, FP32 accumulation of the split
+    // M2L products); a smaller eps takes the FP64 form, also when the mixed
+    // form was asked for.
     int prec = o.precision;
-    if (prec == FMM_PREC_AUTO) prec = eps >= 1e-6 ? FMM_PREC_MIXED : FMM_PREC_FP64;
+    if (prec == FMM_PREC_AUTO || (prec == FMM_PREC_MIXED && !(eps >= kMixedMinEps)))
+        prec = eps >= kMixedMinEps ? FMM_PREC_MIXED : FMM_PREC_FP64;
     P->precision = prec;
     hipGetDevice(&P->device);
     if (o.device_pointers) {

@@ -36,7 +36,7 @@ def test_library_exports_every_declared_symbol(F):
 
 
 def test_order_rule_matches_separation_ratios(F):
-    # p = ceil(ln eps / ln q) - 1 with q = 1/(2 sqrt2 - 1), 0.5244, 1/(sqrt7 - 1)
+    # p = ceil(ln eps / ln q) - 1 with q = 1/(2 sqrt2 - 1), 0.524434, 1/(sqrt7 - 1)
     assert [F.order_for_eps(t, 1e-6) for t in ("quad", "sept", "tri")] == [22, 21, 27]
     assert [F.order_for_eps(t, 1e-10) for t in ("quad", "sept", "tri")] == [38, 35, 46]
     assert [F.order_for_eps(t, 1e-4) for t in ("quad", "sept", "tri")] == [15, 14, 18]
