@@ -145,6 +145,8 @@ void batch_l2l_lanes(const EvalJob *jobs, const BatchMap &m, int pm, hipStream_t
 void batch_m2l_block(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_m2l_lanes(const EvalJob *jobs, const BatchMap &m, int pm, hipStream_t s);
 void batch_m2l_mixed(const EvalJob *jobs, const BatchMap &m, int MT, int KB, hipStream_t s);
+// FP64 M2L on MFMA; every job of the batch has kernel class m2l_f64_mfma_class(p).
+void batch_m2l_f64_mfma(const EvalJob *jobs, const BatchMap &m, int p, hipStream_t s);
 bool mixed_shape_supported(int MT, int KB);
 void batch_split_mp(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_near_fp64(const EvalJob *jobs, const BatchMap &m, hipStream_t s);

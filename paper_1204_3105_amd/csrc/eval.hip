@@ -93,6 +93,12 @@ EvalJob make_job(const Plan &P)
         J.MT = MT;
         J.KB = KB;
         J.mix_split = P.mixed_tiles > 0 && base_of(P.geo.tiling) == 4 ? 1 : 0;
+    } else if (P.mixed) {
+        // FP64 M2L on MFMA: only the target tiles and their cell list
+        const __bf16 *tab;
+        __bf16 *bsplit;
+        int MT, KB;
+        mixed_pointers(P, &tab, &J.mix_tiles, &J.mix_list, &bsplit, &MT, &KB);
     }
     return J;
 }
@@ -257,12 +263,31 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
             auto f = [&](const BatchMap &m) { batch_m2l_lanes(jobs_dev, m, pm, s); };
             for (int i = 0; i < n; ++i) {
                 const Plan &P = *plans[i];
-                const bool mixed_ok = P.precision == FMM_PREC_MIXED && P.mixed_tiles > 0;
-                if (P.geo.L < 1 || P.m2l_pm != pm || mixed_ok) continue;
+                const bool tiled = P.mixed_tiles > 0;   // mixed or FP64 MFMA form
+                if (P.geo.L < 1 || P.m2l_pm != pm || tiled) continue;
                 const int64_t cells = P.n_cells - P.lev[1].cell_off;
                 Lc.add(i, 0, (cells + 63) / 64, f);
             }
             go(f);
+        }
+        // FP64 on MFMA, one launch per kernel class present
+        {
+            std::vector<int> done;
+            for (int i = 0; i < n; ++i) {
+                const Plan &Pi = *plans[i];
+                if (Pi.precision == FMM_PREC_MIXED || Pi.mixed_tiles == 0) continue;
+                const int cls = m2l_f64_mfma_class(Pi.p);
+                if (std::find(done.begin(), done.end(), cls) != done.end()) continue;
+                done.push_back(cls);
+                auto f = [&](const BatchMap &m) { batch_m2l_f64_mfma(jobs_dev, m, Pi.p, s); };
+                for (int k = i; k < n; ++k) {
+                    const Plan &P = *plans[k];
+                    if (P.precision == FMM_PREC_MIXED || P.mixed_tiles == 0 || m2l_f64_mfma_class(P.p) != cls)
+                        continue;
+                    Lc.add(k, 0, P.mixed_tiles, f);
+                }
+                go(f);
+            }
         }
         auto fb = [&](const BatchMap &m) { batch_m2l_block(jobs_dev, m, s); };
         for (int i = 0; i < n; ++i) {

@@ -219,6 +219,8 @@ const double *device_binom(int *err);
 
 // m2l.hip
 int m2l_pm_for(int p);
+// FP64 M2L on MFMA: kernel class of order p (0 = not supported).
+int m2l_f64_mfma_class(int p);
 size_t m2l_table_doubles(const Plan &P, int pm);
 void launch_m2l_tables(Plan &P, int pm, double *base, hipStream_t s);
 

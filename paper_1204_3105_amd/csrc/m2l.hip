@@ -1,4 +1,6 @@
-// m2l.hip -- multipole-to-local translation, FP64, one target cell per lane.
+// m2l.hip -- multipole-to-local translation in FP64: the per-plan offset
+// tables, the dense contraction on FP64 MFMA (orders up to 48), and the lane
+// form (one target cell per lane) for plans without target tiles.
 //
 // Greengard & Rokhlin (1987) Lemma 2.4 in radius-scaled form.  For a source
 // cell S and target cell T on level l with delta = (c_S - c_T)/ell_l and
@@ -239,6 +241,193 @@ __global__ __launch_bounds__(64) void k_m2l_lanes(const EvalJob *__restrict__ jo
         }
     }
 }
+
+// ------------------------------------------------------------ FP64 MFMA form
+// The same translation as a dense contraction on v_mfma_f64_16x16x4f64.
+// With g = D_in a (D_in = diag((-1/delta)^k), k = 1..p) and the offset-free
+// matrix H[m][k'] = C(m + k', k') (m = 0..p, k' = k - 1), every E4 pair is
+//     b~ += D_out (H g - a_0 [0, 1/1, 1/2, ..., 1/p]) + a_0 Log(c_T - c_S) e_0,
+// D_out = diag(delta^-m) = diag((-1)^m (-1/delta)^m).  H is the same for every
+// pair of every level and tiling, so it sits in the MFMA A-operand registers
+// for the whole kernel; each pair contributes two real columns (Re g, Im g)
+// to the B operand.  One workgroup takes a tile of up to 16 target cells of
+// one (level, group) -- they share the slot offsets, so the slot's D_in and
+// D_out are read from a table staged in LDS -- and its four waves split the
+// E4 slots (wave w takes the slots s = w mod 4, so a target's sums do not
+// depend on which cells share its tile); the waves' partial rows are added
+// in wave order through LDS and written as contiguous rows.  Accumulation is
+// FP64 throughout (the MFMA accumulates in FP64).
+//
+// MFMA 16x16x4 f64 operand layout (lane l, register j):
+//   A[i = l%16][k = l/16], B[k = l/16][n = l%16], D[i = l/16 + 4j][n = l%16].
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+// Output row of register j of lane group q in row tile mt.
+__device__ __forceinline__ constexpr int f64_out_row(int mt, int q, int j) { return 16 * mt + q + 4 * j; }
+
+template <int MT, int KT>
+__global__ __launch_bounds__(256) void k_m2l_f64_mfma(const EvalJob *__restrict__ jobs, BatchMap bm)
+{
+    far_field_priority();
+    constexpr int W = 16 * MT > 4 * KT + 1 ? 16 * MT : 4 * KT + 1;   // table entries per slot
+    constexpr int NR = 16 * MT;                                       // output rows per column
+    constexpr int TAB_BYTES = kMaxSlots * W * 16, RED_BYTES = 4 * 16 * 2 * NR * 8;
+    __shared__ __align__(16) char lds[TAB_BYTES > RED_BYTES ? TAB_BYTES : RED_BYTES];
+    __shared__ double2 lgs[kMaxSlots];
+    __shared__ int32_t srcs[kMaxSlots][16];
+    double2 *tab = reinterpret_cast<double2 *>(lds);        // [slot][W]: (-1/delta)^k, zero beyond p
+    double(*red)[16][2 * NR] = reinterpret_cast<double(*)[16][2 * NR]>(lds);   // after the slots
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int n = lane & 15, q = lane >> 4;
+
+    // H in the A-operand layout: h[mt][t] = C(m + k', k'), m = 16 mt + n,
+    // k' = 4 t + q (rows beyond p meet zero D_out entries, columns beyond p
+    // meet zero B entries; the bounds keep the binomial table in range).
+    double h[MT][KT];
+    {
+        const double *binom = jobs[bm.job[0]].binom;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int t = 0; t < KT; ++t) {
+                const int m = 16 * mt + n, kp = 4 * t + q;
+                h[mt][t] = (m <= kMaxP && kp < kMaxP) ? binom[(m + kp) * kBinomStride + kp] : 0.0;
+            }
+    }
+    // This lane's output rows m = 16 mt + 4 q + j: (-1)^m and 1/m (0 for m = 0).
+    double sg[MT][4], im_[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int m = f64_out_row(mt, q, j);
+            sg[mt][j] = (m & 1) ? -1.0 : 1.0;
+            im_[mt][j] = m ? 1.0 / (double)m : 0.0;
+        }
+
+    // XCD-aware order: each XCD takes a contiguous range of the tiles, so
+    // tiles of one (level, group) share an L2.
+    const int64_t total = bm.pre[bm.n];
+    const int xcd = blockIdx.x % 8, lb = blockIdx.x / 8, nb = gridDim.x / 8;
+    const int64_t t_beg = total * xcd / 8, t_end = total * (xcd + 1) / 8;
+    for (int64_t item = t_beg + lb; item < t_end; item += nb) {
+        const int e = batch_entry(bm, item);
+        const EvalJob &J = jobs[bm.job[e]];
+        if (item - bm.pre[e] >= J.counts[1]) continue;   // block-uniform
+        const int32_t *tile = J.mix_tiles + 4 * (item - bm.pre[e]);
+        const int key = tile[0], start = tile[1], count = tile[2];
+        const int G = J.G, S = J.ew, p = J.p, pm = J.pm;
+        const int l = key / G, g = key % G;
+        const int P1 = p + 1;
+        const size_t tab0 = ((size_t)l * G + g) * S;
+
+        __syncthreads();   // the previous tile is done with the LDS
+        for (int i = threadIdx.x; i < S * W; i += 256) {
+            const int sl = i / W, k = i - sl * W;
+            double2 v = make_double2(0.0, 0.0);
+            if (k <= p) {
+                const double *pw = J.m2l_pw + 2 * ((tab0 + sl) * (pm + 1) + k);
+                v = make_double2(pw[0], pw[1]);
+            }
+            tab[i] = v;
+        }
+        for (int i = threadIdx.x; i < S; i += 256)
+            lgs[i] = make_double2(J.m2l_lg[2 * (tab0 + i)], J.m2l_lg[2 * (tab0 + i) + 1]);
+        for (int i = threadIdx.x; i < S * 16; i += 256) {
+            const int c = i / S, sl = i - c * S;
+            srcs[sl][c] = c < count ? J.e4[(int64_t)J.mix_list[start + c] * S + sl] : -1;
+        }
+        __syncthreads();
+
+        double accr[MT][4], acci[MT][4];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) accr[mt][j] = acci[mt][j] = 0.0;
+        for (int sl = w; sl < S; sl += 4) {
+            const int32_t src = srcs[sl][n];
+            if (!__any(src >= 0)) continue;
+            const double2 *ts = tab + sl * W;
+            // B operand: g_k = a~_k (-1/delta)^k, k = 4 t + q + 1
+            double br[KT], bi[KT];
+            double a0 = 0.0;
+            const double *a = J.mp + (int64_t)(src >= 0 ? src : 0) * 2 * P1;
+            if (src >= 0) a0 = a[0];
+#pragma unroll
+            for (int t = 0; t < KT; ++t) {
+                const int k = 4 * t + q + 1;
+                double2 c = make_double2(0.0, 0.0);
+                if (src >= 0 && k <= p) c = *reinterpret_cast<const double2 *>(a + 2 * k);
+                const double2 d = ts[k];
+                br[t] = c.x * d.x - c.y * d.y;
+                bi[t] = c.x * d.y + c.y * d.x;
+            }
+            const double2 lg = lgs[sl];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                doublex4 yr = {0.0, 0.0, 0.0, 0.0}, yi = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int t = 0; t < KT; ++t) {
+                    yr = __builtin_amdgcn_mfma_f64_16x16x4f64(h[mt][t], br[t], yr, 0, 0, 0);
+                    yi = __builtin_amdgcn_mfma_f64_16x16x4f64(h[mt][t], bi[t], yi, 0, 0, 0);
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int m = f64_out_row(mt, q, j);
+                    const double2 d = ts[m];
+                    const double dr = sg[mt][j] * d.x, di = sg[mt][j] * d.y;
+                    const double y = fma(-a0, im_[mt][j], yr[j]);
+                    accr[mt][j] = fma(y, dr, fma(-yi[j], di, accr[mt][j]));
+                    acci[mt][j] = fma(y, di, fma(yi[j], dr, acci[mt][j]));
+                }
+            }
+            if (q == 0) {   // row 0 (register 0 of lane group 0): the log term
+                accr[0][0] = fma(a0, lg.x, accr[0][0]);
+                acci[0][0] = fma(a0, lg.y, acci[0][0]);
+            }
+        }
+        __syncthreads();   // every wave is done with the table
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int m = f64_out_row(mt, q, j);
+                red[w][n][2 * m] = accr[mt][j];
+                red[w][n][2 * m + 1] = acci[mt][j];
+            }
+        __syncthreads();
+        // Rows of the tile's targets, the waves' partial sums added in order.
+        for (int i = threadIdx.x; i < count * 2 * P1; i += 256) {
+            const int c = i / (2 * P1), r = i - c * 2 * P1;
+            const double v = ((red[0][c][r] + red[1][c][r]) + red[2][c][r]) + red[3][c][r];
+            J.lc[(int64_t)J.mix_list[start + c] * 2 * P1 + r] = v;
+        }
+    }
+}
+
+// (MT, KT) of the FP64 MFMA form for order p: MT = ceil((p+1)/16),
+// KT = ceil(p/4).
+static int f64_mfma_key(int p) { return ((p + 1 + 15) / 16) * 100 + (p + 3) / 4; }
+
+bool m2l_f64_mfma_supported(int p) { return p >= 1 && p <= 48; }
+
+void batch_m2l_f64_mfma(const EvalJob *jobs, const BatchMap &m, int p, hipStream_t s)
+{
+    if (m.n <= 0 || m.pre[m.n] <= 0) return;
+    const dim3 grid((persistent_grid(m.pre[m.n], 12) + 7) / 8 * 8), block(256);
+#define F64_MFMA_CASE(MT, KT)                                                                         \
+    case MT * 100 + KT: hipLaunchKernelGGL((k_m2l_f64_mfma<MT, KT>), grid, block, 0, s, jobs, m); break;
+    switch (f64_mfma_key(p)) {
+        F64_MFMA_CASE(1, 1) F64_MFMA_CASE(1, 2) F64_MFMA_CASE(1, 3) F64_MFMA_CASE(1, 4)
+        F64_MFMA_CASE(2, 4) F64_MFMA_CASE(2, 5) F64_MFMA_CASE(2, 6) F64_MFMA_CASE(2, 7) F64_MFMA_CASE(2, 8)
+        F64_MFMA_CASE(3, 8) F64_MFMA_CASE(3, 9) F64_MFMA_CASE(3, 10) F64_MFMA_CASE(3, 11) F64_MFMA_CASE(3, 12)
+        F64_MFMA_CASE(4, 12)
+    default: break;
+    }
+#undef F64_MFMA_CASE
+}
+
+int m2l_f64_mfma_class(int p) { return m2l_f64_mfma_supported(p) ? f64_mfma_key(p) : 0; }
 
 void batch_m2l_lanes(const EvalJob *jobs, const BatchMap &m, int pm, hipStream_t s)
 {

@@ -29,7 +29,11 @@ namespace fmm {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
-constexpr int kTileT = 64;   // targets per workgroup (4 waves x 16 columns)
+constexpr int kTileT = 64;   // mixed: targets per workgroup (4 waves x 16 columns)
+constexpr int kTileT64 = 16; // FP64: targets per workgroup (4 waves share 16 columns)
+
+// Targets per M2L tile of a plan's form.
+static int tile_targets(const Plan &P) { return P.precision == FMM_PREC_MIXED ? kTileT : kTileT64; }
 
 struct MixedLayout {
     int MT, KB;          // 16-row M tiles, 32-deep K blocks
@@ -40,8 +44,11 @@ struct MixedLayout {
     size_t off_tab, off_tiles, off_list, off_cnt, off_b;   // byte offsets in P.mixed
 };
 
+// The M2L area of a plan: target tiles grouped by (level, group) for both
+// forms; the split matrices and split multipoles only for the mixed form.
 static MixedLayout layout_of(const Plan &P)
 {
+    const bool mixed = P.precision == FMM_PREC_MIXED;
     MixedLayout m;
     m.MT = (2 * (P.p + 1) + 15) / 16;
     m.KB = (2 * P.p + 31) / 32;
@@ -53,19 +60,18 @@ static MixedLayout layout_of(const Plan &P)
     m.n_tiles = 0;
     size_t o = 0;
     m.off_tab = o;
-    o += (size_t)m.tab_levels * m.G * m.S * m.tab_elems * 2;
+    if (mixed) o += (size_t)m.tab_levels * m.G * m.S * m.tab_elems * 2;
     o = (o + 255) & ~(size_t)255;
     m.off_cnt = o;   // cell counts/offsets, cursors, tile offsets: 256 each
     o += 3 * 256 * sizeof(int32_t);
     m.off_tiles = o;
     int64_t ncell = P.n_cells;
-    o += (size_t)(ncell / kTileT + 2 * (kMaxL + 1) * kMaxGroups + 2) * 4 * sizeof(int32_t);
+    o += (size_t)(ncell / tile_targets(P) + 2 * (kMaxL + 1) * kMaxGroups + 2) * 4 * sizeof(int32_t);
     o = (o + 255) & ~(size_t)255;
     m.off_list = o;
     o += (size_t)(ncell + 1) * sizeof(int32_t);
     o = (o + 255) & ~(size_t)255;
     m.off_b = o;   // split multipoles: [cell][kb][split][q] bf16x8
-    o += (size_t)ncell * m.KB * 12 * 16;
     return m;
 }
 
@@ -73,7 +79,8 @@ size_t mixed_bytes(const Plan &P)
 {
     if (P.m2l_pm == 0) return 256;
     MixedLayout m = layout_of(P);
-    return m.off_b + (size_t)P.n_cells * m.KB * 12 * 16 + 256;
+    const size_t splits = P.precision == FMM_PREC_MIXED ? (size_t)P.n_cells * m.KB * 12 * 16 : 0;
+    return m.off_b + splits + 256;
 }
 
 struct CellOffsets {
@@ -180,7 +187,7 @@ __global__ void k_group_scatter(int64_t first, int64_t n_cells, int L, int G, Ce
 // One block: turns the per-key cell counts into cell offsets (in place,
 // off[K] = total), tile offsets toff[0..K] (ceil(count / T) tiles per key)
 // and the tile total; clears the scatter cursors.
-__global__ __launch_bounds__(256) void k_tile_plan(int K, int32_t *__restrict__ cnt,
+__global__ __launch_bounds__(256) void k_tile_plan(int K, int T, int32_t *__restrict__ cnt,
                                                    int32_t *__restrict__ cursor,
                                                    int32_t *__restrict__ toff,
                                                    int32_t *__restrict__ n_tiles)
@@ -189,7 +196,7 @@ __global__ __launch_bounds__(256) void k_tile_plan(int K, int32_t *__restrict__ 
     const int k = threadIdx.x;
     const int32_t c = k < K ? cnt[k] : 0;
     sc[k] = c;
-    st[k] = (c + kTileT - 1) / kTileT;
+    st[k] = (c + T - 1) / T;
     cursor[k] = 0;
     __syncthreads();
     for (int d = 1; d < 256; d <<= 1) {   // inclusive Hillis-Steele scans
@@ -208,7 +215,7 @@ __global__ __launch_bounds__(256) void k_tile_plan(int K, int32_t *__restrict__ 
 
 // Thread per tile t < n_tiles: key = the k with toff[k] <= t < toff[k+1];
 // tile = {key, first list position, cell count (<= T), 0}.
-__global__ void k_tile_fill(int K, const int32_t *__restrict__ off, const int32_t *__restrict__ toff,
+__global__ void k_tile_fill(int K, int T, const int32_t *__restrict__ off, const int32_t *__restrict__ toff,
                             const int32_t *__restrict__ n_tiles, int32_t *__restrict__ tiles)
 {
     const int32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -222,8 +229,8 @@ __global__ void k_tile_fill(int K, const int32_t *__restrict__ off, const int32_
     const int32_t j = t - toff[lo];
     const int32_t c = off[lo + 1] - off[lo];
     tiles[4 * t] = lo;
-    tiles[4 * t + 1] = off[lo] + j * kTileT;
-    tiles[4 * t + 2] = min(kTileT, c - j * kTileT);
+    tiles[4 * t + 1] = off[lo] + j * T;
+    tiles[4 * t + 2] = min(T, c - j * T);
     tiles[4 * t + 3] = 0;
 }
 
@@ -248,14 +255,16 @@ int mixed_setup(Plan &P)
     if (n > 0)
         hipLaunchKernelGGL(k_group_count, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, first,
                            P.n_cells, L, G, coff, P.cell_occ, P.group, cnt);
-    hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(256), 0, s, K, cnt, cursor, toff, P.counts + 1);
+    const int T = tile_targets(P);
+    hipLaunchKernelGGL(k_tile_plan, dim3(1), dim3(256), 0, s, K, T, cnt, cursor, toff, P.counts + 1);
     // sum_k ceil(c_k / T) <= (sum_k c_k) / T + (keys of levels >= 1)
-    P.mixed_tiles = (int)(n / kTileT + (int64_t)L * G + 1);
+    P.mixed_tiles = (int)(n / T + (int64_t)L * G + 1);
     hipLaunchKernelGGL(k_tile_fill, dim3((unsigned)((P.mixed_tiles + 255) / 256)), dim3(256), 0, s,
-                       K, cnt, toff, P.counts + 1, tiles);
+                       K, T, cnt, toff, P.counts + 1, tiles);
     if (n > 0)
         hipLaunchKernelGGL(k_group_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, first,
                            P.n_cells, L, G, coff, P.cell_occ, P.group, cnt, cursor, list);
+    if (P.precision != FMM_PREC_MIXED) return hipGetLastError() != hipSuccess;
     // Split translation matrices.
     SlotCounts counts;
     for (int g = 0; g < kMaxGroups; ++g) counts.v[g] = g < G ? P.tables.e4_count[g] : 0;

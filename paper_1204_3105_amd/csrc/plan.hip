@@ -740,6 +740,11 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
         P->mixed = take<char>(P, (int64_t)mb, &err);
         if (err) return fail(FMM_E_NOMEM, "device allocation failed (mixed M2L)");
         if (mixed_setup(*P)) return fail(FMM_E_DEVICE, "mixed-precision setup failed");
+    } else if (P->m2l_pm > 0 && g.L >= 1 && m2l_f64_mfma_class(P->p) > 0) {
+        // FP64 M2L on MFMA: target tiles grouped by (level, group)
+        P->mixed = take<char>(P, (int64_t)mixed_bytes(*P), &err);
+        if (err) return fail(FMM_E_NOMEM, "device allocation failed (M2L tiles)");
+        if (mixed_setup(*P)) return fail(FMM_E_DEVICE, "M2L tile setup failed");
     }
     FMM_HIP_CHECK(hipEventRecord(P->ev[1], s));
     // Item counts stay on the device; launches use these upper bounds and
