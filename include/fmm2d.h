@@ -224,6 +224,24 @@ int32_t fmm_order_for_eps(fmm_tiling tiling, double eps);
 fmm_status fmm_direct(const double *src, int64_t n_src, const double *tgt, int64_t n_tgt,
                       const double *u, double *phi, const fmm_options *opt);
 
+/* fmm_direct without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, serving loops or harnesses that
+ * forbid hipMalloc).  Same sum, same kernels and the same slicing of the
+ * sources as fmm_direct with device pointers, so the result is bitwise
+ * fmm_direct's.  src, tgt, u, phi are device pointers on the current
+ * device; work is ordered on stream (hipStream_t, NULL = null stream) and
+ * the call returns without waiting.  The slices' partial sums live in a
+ * fixed 16 MiB device array of the library (one per GPU, held until the
+ * process ends; the slicing rule needs at most 12 MiB, and a size that
+ * needed more would return FMM_E_INVALID).  Calls that overlap on one GPU
+ * share that array and race: order them on one stream or wait between them.
+ * Nothing needs clearing between calls (every partial sum a call reads it
+ * wrote first).  Errors: FMM_E_INVALID for negative sizes or null arrays
+ * with nonzero sizes; FMM_E_DEVICE if the array's address cannot be found
+ * or the launch fails.  Coordinates are not checked for finiteness. */
+fmm_status fmm_direct_noalloc(const double *src, int64_t n_src, const double *tgt, int64_t n_tgt,
+                              const double *u, double *phi, void *stream);
+
 /* ------------------------------------------------------------------ serving
  * A request loop that admits independent solves by free device memory,
  * keeps their plans resident, and runs the same phase of every admitted

@@ -341,6 +341,40 @@ static void put_fenced(void *p, size_t bytes, hipStream_t s)
 
 int64_t plan_device_bytes(const Plan *P) { return ((const PlanImpl *)P)->device_bytes; }
 
+// ------------------------------------------------------------ fixed scratch
+// Device scratch of fmm_direct_noalloc: the slices' partial sums (complex128
+// per slice and target).  The slicing rule (direct_slices) keeps them under
+// 12 MiB for every size, so 16 MiB covers all calls; each GPU the library
+// runs on holds its own copy until the process ends.
+static constexpr size_t kDirectScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) double direct_scratch[kDirectScratchBytes / sizeof(double)];
+
+// The device address of this device's direct_scratch, looked up once per
+// device with that device current (the host-side name of the array is not
+// a device address).
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[64] = {};
+
+static fmm_status direct_scratch_ptr(void **out)
+{
+    int dev = 0;
+    FMM_HIP_CHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(FMM_E_DEVICE, "device ordinal out of range for the fixed scratch");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(direct_scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(FMM_E_DEVICE, std::string("hipGetSymbolAddress(direct_scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return FMM_OK;
+}
+
+
 // ------------------------------------------------------------ rules
 static const double kQ[3] = {
     0.54691816067802259,   // quadtree 1/(1 + 2(sqrt2 - 1))
@@ -848,6 +882,31 @@ fmm_status fmm_direct(const double *src, int64_t n_src, const double *tgt, int64
     dev_free(part, bpart);
     hipStreamDestroy(s);
     return st;
+}
+
+fmm_status fmm_direct_noalloc(const double *src, int64_t n_src, const double *tgt, int64_t n_tgt,
+                              const double *u, double *phi, void *stream)
+{
+    g_err.clear();
+    if (n_src < 0 || n_tgt < 0) return fail(FMM_E_INVALID, "negative size");
+    if ((n_src > 0 && (!src || !u)) || (n_tgt > 0 && (!tgt || !phi)))
+        return fail(FMM_E_INVALID, "null array");
+    if (n_tgt == 0) return FMM_OK;
+    const int slices = direct_slices(n_src, n_tgt);
+    const size_t bpart = slices > 1 ? 16 * (size_t)slices * (size_t)n_tgt : 0;
+    if (bpart > kDirectScratchBytes)
+        return fail(FMM_E_INVALID, "direct sum: partial sums need " + std::to_string(bpart) +
+                                       " bytes, the fixed scratch holds " + std::to_string(kDirectScratchBytes));
+    double *part = nullptr;
+    if (bpart) {
+        void *ptr = nullptr;
+        const fmm_status st = direct_scratch_ptr(&ptr);
+        if (st != FMM_OK) return st;
+        part = (double *)ptr;
+    }
+    launch_direct(src, n_src, tgt, n_tgt, u, phi, part, slices, (hipStream_t)stream);
+    FMM_HIP_CHECK(hipGetLastError());
+    return FMM_OK;
 }
 
 fmm_status fmm_plan(fmm_tiling tiling, const double *src, int64_t n_src, const double *tgt,

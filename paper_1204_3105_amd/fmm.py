@@ -67,7 +67,7 @@ EXPORTED = ["fmm_options_default", "fmm_plan", "fmm_eval", "fmm_plan_info_get",
             "fmm_plan_export_points", "fmm_plan_export_level", "fmm_plan_destroy",
             "fmm_last_error", "fmm_order_for_eps", "fmm_server_create", "fmm_submit",
             "fmm_poll", "fmm_server_drain", "fmm_server_destroy", "fmm_direct",
-            "fmm_eval_field"]
+            "fmm_eval_field", "fmm_direct_noalloc"]
 
 _lib = None
 
@@ -115,6 +115,8 @@ def lib():
     L.fmm_order_for_eps.restype = C.c_int32
     L.fmm_direct.argtypes = [P, C.c_int64, P, C.c_int64, P, P, C.POINTER(Options)]
     L.fmm_direct.restype = C.c_int
+    L.fmm_direct_noalloc.argtypes = [P, C.c_int64, P, C.c_int64, P, P, P]
+    L.fmm_direct_noalloc.restype = C.c_int
     L.fmm_server_create.argtypes = [C.POINTER(ServerOptions), C.POINTER(P)]
     L.fmm_server_create.restype = C.c_int
     L.fmm_submit.argtypes = [P, C.POINTER(Request), C.POINTER(C.c_uint64)]
@@ -389,6 +391,28 @@ def direct(xs, ys, u, xt=None, yt=None, *, src=None, tgt=None, out=None, stream=
                         C.c_void_p(u.ctypes.data) if ns else None,
                         C.c_void_p(res.ctypes.data) if nt else None, C.byref(opt)))
     return res
+
+
+def direct_noalloc(src, tgt, u, out, stream=None):
+    """fmm_direct_noalloc: the direct sum of `direct` with device tensors
+    only, writing into the caller's `out` (complex128, one per target) and
+    taking its partial sums from the library's fixed device scratch instead
+    of allocating.  Ordered on `stream` (default: torch's current stream);
+    returns `out`."""
+    import torch
+    L = lib()
+    for a in (src, tgt):
+        if not (_is_torch(a) and a.is_cuda and a.dtype == torch.complex128 and a.is_contiguous()):
+            raise TypeError("points must be contiguous complex128 CUDA tensors")
+    if not (u.is_cuda and u.dtype == torch.float64 and u.is_contiguous() and u.numel() == src.numel()):
+        raise TypeError("u must be a contiguous float64 CUDA tensor of n_src elements")
+    if not (out.is_cuda and out.dtype == torch.complex128 and out.is_contiguous() and out.numel() == tgt.numel()):
+        raise TypeError("out must be a contiguous complex128 CUDA tensor of n_tgt elements")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(L.fmm_direct_noalloc(C.c_void_p(src.data_ptr()), src.numel(), C.c_void_p(tgt.data_ptr()),
+                                tgt.numel(), C.c_void_p(u.data_ptr()), C.c_void_p(out.data_ptr()),
+                                C.c_void_p(st.cuda_stream)))
+    return out
 
 
 class Server:
