@@ -227,6 +227,9 @@ void launch_m2l_tables(Plan &P, int pm, double *base, hipStream_t s);
 // m2l_mixed.hip
 size_t mixed_bytes(const Plan &P);
 int64_t plan_device_bytes(const Plan *P);
+// Device bytes a plan of these sizes may take (admission estimate).
+int64_t plan_bytes_estimate(int tiling, int64_t n_src, int64_t n_tgt, bool same, double eps, int precision,
+                            int leaf_size);
 // Direct sum: slices of the sources per target block (direct_slices), with
 // partial sums in part (slices * n_tgt complex128; unused for one slice).
 int direct_slices(int64_t n_src, int64_t n_tgt);

@@ -341,6 +341,36 @@ static void put_fenced(void *p, size_t bytes, hipStream_t s)
 
 int64_t plan_device_bytes(const Plan *P) { return ((const PlanImpl *)P)->device_bytes; }
 
+static int order_for(int tiling, double eps);
+
+// Device bytes a plan of these sizes takes, from the buffers build_plan
+// allocates (a bound for admission: the depth rule and the point layout
+// decide the exact cell counts).  Per point: inputs, sorted coordinates,
+// keys, permutation, strengths, the sort's scratch, near sums, output, the
+// mixed form's FP32 copies and the symmetric near field's second-side sums;
+// per cell (at most 3 n / leaf over all levels, more for clustered inputs
+// at deeper levels): multipole and local rows, E4 and near lists, the dense
+// key maps, the mixed M2L's split columns; plus 2 MiB granules per buffer.
+int64_t plan_bytes_estimate(int tiling, int64_t n_src, int64_t n_tgt, bool same, double eps, int precision,
+                            int leaf_size)
+{
+    int prec = precision;
+    if (prec == FMM_PREC_AUTO || (prec == FMM_PREC_MIXED && !(eps >= kMixedMinEps)))
+        prec = eps >= kMixedMinEps ? FMM_PREC_MIXED : FMM_PREC_FP64;
+    const int p = std::max(order_for(tiling, eps), 1);
+    const int ew = tiling == kQuad ? 27 : tiling == kSept ? 42 : 39;
+    const int nw = tiling == kQuad ? 9 : tiling == kSept ? 7 : 13;
+    const int64_t pts = std::max(n_src, n_tgt);
+    const int64_t sides = same ? 1 : 2;
+    int64_t per_pt = 24 + sides * 40 + 24 + 32;   // inputs, sorted arrays, sort scratch, sums and output
+    if (prec == FMM_PREC_MIXED) per_pt += sides * 12 + (same ? (nw - 1) * kSymChunks * 8 : 0);
+    else if (same) per_pt += (nw - 1) * kSymChunks * 16;
+    const int64_t cells = 3 * pts / std::max(leaf_size, 1) + 64;
+    int64_t per_cell = 2 * 16 * (p + 1) + 4 * (ew + nw) + 64 + 48;
+    if (prec == FMM_PREC_MIXED) per_cell += 12 * 16 * ((2 * p + 31) / 32);
+    return per_pt * pts + per_cell * cells + ((int64_t)48 << 20);
+}
+
 // ------------------------------------------------------------ fixed scratch
 // Device scratch of fmm_direct_noalloc: the slices' partial sums (complex128
 // per slice and target).  The slicing rule (direct_slices) keeps them under
@@ -373,7 +403,6 @@ static fmm_status direct_scratch_ptr(void **out)
     *out = g_scratch_ptr[dev];
     return FMM_OK;
 }
-
 
 // ------------------------------------------------------------ rules
 static const double kQ[3] = {

@@ -1,18 +1,25 @@
 // server.hip -- serving loop: continuous batching of independent solves.
 //
-// A scheduler thread owns two HIP streams (default priority).  Requests are
-// admitted in arrival order while their device-memory estimate fits the
-// budget (a request larger than the whole budget runs when nothing else is
-// resident).  Admitted requests are planned on the planning stream while the
-// previous batch evaluates on the evaluation stream; when the evaluation
-// stream is idle, every planned request joins the next batch, whose phases
-// (P2M, M2M, M2L, L2L, L2P + P2P) are each one launch over all of them
-// (run_batch).  A finished batch's results are copied back, its plans
-// destroyed and its memory returned to the budget.  Each request's numbers
-// are the same as a standalone fmm_plan + fmm_eval: an item's arithmetic
-// depends only on its own plan's data.
+// Two host threads share a request queue.  The planner admits requests in
+// arrival order while their device-memory estimate fits the budget (a
+// request larger than the whole budget runs when nothing else is resident)
+// and plans each on the planning stream without waiting for it: an event
+// recorded behind the plan marks it ready.  The scheduler keeps up to
+// kEvalSlots batches in flight, each on an evaluation stream of its own:
+// whenever a slot is free, every planned request joins a new batch there,
+// whose phases (P2M, M2M, M2L, L2L, P2P, L2P) are each one launch over all of
+// them (run_batch, near field on the batch's stream), after the stream has
+// waited for their plans' events.  So requests planned while a batch runs
+// start at once on the other slot and overlap it on the device; a small
+// request can finish before a large one submitted earlier.  A finished
+// batch's results are copied back, its plans destroyed and its memory
+// returned to the budget.  Each request's numbers are the same as a
+// standalone fmm_plan + fmm_eval: an item's arithmetic depends only on its
+// own plan's data.  Streams: one planning and kEvalSlots evaluation streams,
+// within the four hardware queues a process gets.
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -30,6 +37,8 @@ static double now_s()
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
+constexpr int kEvalSlots = 2;
+
 struct Req {
     uint64_t ticket = 0;
     int tiling = 0, precision = 0;
@@ -41,49 +50,60 @@ struct Req {
     bool done = false;
     fmm_status status = FMM_OK;
     fmm_plan_t plan = nullptr;
+    hipEvent_t ready = nullptr;   // recorded behind the plan on the planning stream
     double *d_pts = nullptr, *d_tgt = nullptr, *d_u = nullptr;
     size_t pts_bytes = 0, tgt_bytes = 0, u_bytes = 0;
     int64_t reserved = 0;
     int p = 0, lmax = 0;
 };
 
-struct Server {
-    fmm_server_options opt{};
-    std::thread th;
-    std::mutex mu;
-    std::condition_variable cv, cv_done;
-    std::deque<Req *> queue;
-    std::map<uint64_t, Req *> all;
-    std::vector<Req *> planned, running;
-    uint64_t next_ticket = 1;
-    int64_t used = 0;
-    int admitted = 0;
-    bool stop = false;
-    hipStream_t s_plan = nullptr, s_eval = nullptr, s_near = nullptr;
-    hipEvent_t done_ev = nullptr;
+struct Slot {
+    std::vector<Req *> reqs;
+    hipStream_t s = nullptr;
+    hipEvent_t done = nullptr;
     hipEvent_t bev[7] = {};   // run_batch stage, fork and near-field events
     EvalJob *jobs = nullptr;
     size_t jobs_cap = 0;
+    bool busy = false;
+};
+
+struct Server {
+    fmm_server_options opt{};
+    std::thread th_sched, th_plan;
+    std::mutex mu;
+    std::condition_variable cv_sched, cv_plan, cv_done;
+    std::deque<Req *> queue;
+    std::map<uint64_t, Req *> all;
+    std::vector<Req *> planned;
+    uint64_t next_ticket = 1;
+    int64_t used = 0;
+    int64_t budget = 0;
+    int admitted = 0;
+    int planning = 0;   // requests admitted and being planned
+    bool stop = false;
+    hipStream_t s_plan = nullptr;
+    Slot slot[kEvalSlots];
     int device = 0;
 };
 
-static int64_t estimate_bytes(const Req &r)
+static int64_t estimate_bytes(const Server &S, const Req &r)
 {
-    const int64_t pts = r.n_src + (r.same ? 0 : r.n_tgt);
-    return (int64_t)400 * pts + ((int64_t)32 << 20);
+    return plan_bytes_estimate(r.tiling, r.n_src, r.n_tgt, r.same, r.eps, r.precision,
+                               S.opt.leaf_size > 0 ? S.opt.leaf_size : 64) +
+           (int64_t)24 * (r.n_src + (r.same ? 0 : r.n_tgt));
 }
 
 static void free_inputs(Req *r)
 {
-    dev_free(r->d_pts, r->pts_bytes);
+    if (r->d_pts) dev_free(r->d_pts, r->pts_bytes);
     if (r->d_tgt) dev_free(r->d_tgt, r->tgt_bytes);
-    dev_free(r->d_u, r->u_bytes);
+    if (r->d_u) dev_free(r->d_u, r->u_bytes);
     r->d_pts = r->d_tgt = r->d_u = nullptr;
 }
 
-// Plan one request on the planning stream.  Returns false on failure (the
-// request is then finished with its error status).
-static bool plan_request(Server &S, Req *r)
+// Plan one request on the planning stream, without waiting for the plan's
+// last kernels (r->ready marks them).  Returns the status.
+static fmm_status plan_request(Server &S, Req *r)
 {
     int err = 0;
     r->pts_bytes = (size_t)std::max<int64_t>(r->n_src, 1) * 16;
@@ -95,28 +115,47 @@ static bool plan_request(Server &S, Req *r)
         r->d_tgt = (double *)dev_alloc(r->tgt_bytes, &err);
     }
     if (err) {
-        r->status = FMM_E_NOMEM;
-        return false;
+        free_inputs(r);
+        return FMM_E_NOMEM;
     }
-    if (r->n_src) {
-        hipMemcpyAsync(r->d_pts, r->src.data(), 16 * r->n_src, hipMemcpyHostToDevice, S.s_plan);
-        hipMemcpyAsync(r->d_u, r->u.data(), 8 * r->n_src, hipMemcpyHostToDevice, S.s_plan);
+    if ((r->n_src && (hipMemcpyAsync(r->d_pts, r->src.data(), 16 * r->n_src, hipMemcpyHostToDevice,
+                                     S.s_plan) != hipSuccess ||
+                      hipMemcpyAsync(r->d_u, r->u.data(), 8 * r->n_src, hipMemcpyHostToDevice, S.s_plan) !=
+                          hipSuccess)) ||
+        (!r->same && r->n_tgt &&
+         hipMemcpyAsync(r->d_tgt, r->tgt.data(), 16 * r->n_tgt, hipMemcpyHostToDevice, S.s_plan) != hipSuccess)) {
+        (void)hipGetLastError();
+        hipStreamSynchronize(S.s_plan);
+        free_inputs(r);
+        return FMM_E_DEVICE;
     }
-    if (!r->same && r->n_tgt)
-        hipMemcpyAsync(r->d_tgt, r->tgt.data(), 16 * r->n_tgt, hipMemcpyHostToDevice, S.s_plan);
     fmm_options o;
     fmm_options_default(&o);
     o.leaf_size = S.opt.leaf_size > 0 ? S.opt.leaf_size : 64;
     o.precision = r->precision;
     o.device_pointers = 1;
     o.stream = (void *)S.s_plan;
+    o.near_stream = 1;   // the batch runs the near field on its own stream
     const double *tgt = r->same ? r->d_pts : r->d_tgt;
     fmm_status st = fmm_plan((fmm_tiling)r->tiling, r->d_pts, r->n_src, tgt, r->n_tgt, r->eps, &o,
                              &r->plan);
-    hipStreamSynchronize(S.s_plan);
+    if (st == FMM_OK && (hipEventCreateWithFlags(&r->ready, hipEventDisableTiming) != hipSuccess ||
+                         hipEventRecord(r->ready, S.s_plan) != hipSuccess)) {
+        (void)hipGetLastError();
+        st = FMM_E_DEVICE;
+    }
     if (st != FMM_OK) {
-        r->status = st;
-        return false;
+        if (r->plan) {
+            fmm_plan_destroy(r->plan);
+            r->plan = nullptr;
+        }
+        if (r->ready) {
+            hipEventDestroy(r->ready);
+            r->ready = nullptr;
+        }
+        hipStreamSynchronize(S.s_plan);   // the input copies are done before their memory goes back
+        free_inputs(r);
+        return st;
     }
     // Sizes straight from the plan (fmm_plan_info_get would also count the
     // interaction pairs, which the scheduler does not need).
@@ -124,14 +163,20 @@ static bool plan_request(Server &S, Req *r)
     r->reserved = plan_device_bytes(P) + (int64_t)(r->pts_bytes + r->tgt_bytes + r->u_bytes);
     r->p = P->p;
     r->lmax = P->geo.L;
-    return true;
+    return FMM_OK;
 }
 
+// Release a request's device resources and publish its result; the caller
+// has seen all of its device work finish.
 static void finish(Server &S, Req *r, bool ok)
 {
     if (r->plan) {
         fmm_plan_destroy(r->plan);
         r->plan = nullptr;
+    }
+    if (r->ready) {
+        hipEventDestroy(r->ready);
+        r->ready = nullptr;
     }
     free_inputs(r);
     if (!ok && r->status == FMM_OK) r->status = FMM_E_DEVICE;
@@ -146,51 +191,74 @@ static void finish(Server &S, Req *r, bool ok)
     std::vector<double>().swap(r->u);
 }
 
-static void launch_batch(Server &S, std::vector<Req *> &batch)
+// Enqueue a batch on a slot's stream.  Returns false if the batch could not
+// be started (its requests are then finished with FMM_E_NOMEM or
+// FMM_E_DEVICE after the stream has drained).
+static bool launch_batch(Server &S, Slot &L)
 {
-    const int n = (int)batch.size();
-    if ((size_t)n > S.jobs_cap) {
-        if (S.jobs) dev_free(S.jobs, S.jobs_cap * sizeof(EvalJob));
+    const int n = (int)L.reqs.size();
+    if ((size_t)n > L.jobs_cap) {
+        if (L.jobs) dev_free(L.jobs, L.jobs_cap * sizeof(EvalJob));
         int err = 0;
-        S.jobs_cap = (size_t)std::max(n, 64);
-        S.jobs = (EvalJob *)dev_alloc(S.jobs_cap * sizeof(EvalJob), &err);
+        L.jobs_cap = (size_t)std::max(n, 64);
+        L.jobs = (EvalJob *)dev_alloc(L.jobs_cap * sizeof(EvalJob), &err);
+        if (err || !L.jobs) {
+            L.jobs = nullptr;
+            L.jobs_cap = 0;
+            for (Req *r : L.reqs) r->status = FMM_E_NOMEM;
+            return false;
+        }
     }
     std::vector<Plan *> plans;
     std::vector<Req *> work;
-    for (Req *r : batch) {
+    bool ok = true;
+    for (Req *r : L.reqs) {
         Plan *P = (Plan *)r->plan;
         r->t_start = now_s();
+        ok = ok && hipStreamWaitEvent(L.s, r->ready, 0) == hipSuccess;
         if (P->n_tgt == 0) continue;
         if (P->n_src == 0) {
-            hipMemsetAsync(P->phi_int, 0, sizeof(double) * 2 * P->n_tgt, S.s_eval);
+            ok = ok && hipMemsetAsync(P->phi_int, 0, sizeof(double) * 2 * P->n_tgt, L.s) == hipSuccess;
             continue;
         }
         const int i = (int)plans.size();
-        hipMemcpyAsync(S.jobs + i, P->job_dev, sizeof(EvalJob), hipMemcpyDeviceToDevice, S.s_eval);
+        ok = ok && hipMemcpyAsync(L.jobs + i, P->job_dev, sizeof(EvalJob), hipMemcpyDeviceToDevice, L.s) ==
+                       hipSuccess;
         plans.push_back(P);
         work.push_back(r);
     }
     for (size_t i = 0; i < plans.size(); ++i) {
         EvalJob J = make_job(*plans[i]);
-        batch_gather_u(S.jobs, J, work[i]->d_u, S.s_eval);
+        batch_gather_u(L.jobs, J, work[i]->d_u, L.s);
     }
-    if (!plans.empty())
-        run_batch(plans.data(), (int)plans.size(), S.jobs, nullptr, S.s_eval, S.s_near, S.bev);
-    hipEventRecord(S.done_ev, S.s_eval);
+    if (!plans.empty()) run_batch(plans.data(), (int)plans.size(), L.jobs, nullptr, L.s, L.s, L.bev);
+    ok = ok && hipGetLastError() == hipSuccess;
+    ok = ok && hipEventRecord(L.done, L.s) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        hipStreamSynchronize(L.s);
+        for (Req *r : L.reqs) r->status = FMM_E_DEVICE;
+    }
+    return ok;
 }
 
-static void complete_batch(Server &S, std::vector<Req *> &batch)
+static void complete_batch(Server &S, Slot &L, bool launched)
 {
-    for (Req *r : batch) {
-        Plan *P = (Plan *)r->plan;
-        r->phi.resize(2 * (size_t)r->n_tgt);
-        bool ok = true;
-        if (r->n_tgt)
-            ok = hipMemcpy(r->phi.data(), P->phi_int, sizeof(double) * 2 * r->n_tgt,
-                           hipMemcpyDeviceToHost) == hipSuccess;
+    for (Req *r : L.reqs) {
+        bool ok = launched;
+        if (ok) {
+            Plan *P = (Plan *)r->plan;
+            r->phi.resize(2 * (size_t)r->n_tgt);
+            if (r->n_tgt)
+                ok = hipMemcpy(r->phi.data(), P->phi_int, sizeof(double) * 2 * r->n_tgt,
+                               hipMemcpyDeviceToHost) == hipSuccess;
+        }
         finish(S, r, ok);
     }
+    L.reqs.clear();
+    L.busy = false;
     S.cv_done.notify_all();
+    S.cv_plan.notify_all();
 }
 
 // Whether the event has passed; a "not ready" answer is not kept as the
@@ -202,60 +270,93 @@ static bool done_query(hipEvent_t ev)
     return e == hipSuccess;
 }
 
+// Admission and planning.
+static void planner(Server *Sp)
+{
+    Server &S = *Sp;
+    hipSetDevice(S.device);
+    for (;;) {
+        Req *r = nullptr;
+        int64_t est = 0;
+        {
+            std::unique_lock<std::mutex> lk(S.mu);
+            for (;;) {
+                if (S.stop && S.queue.empty()) return;
+                if (!S.queue.empty() && S.admitted < S.opt.max_inflight) {
+                    Req *h = S.queue.front();
+                    est = estimate_bytes(S, *h);
+                    if (S.admitted == 0 || S.used + est <= S.budget) {
+                        S.queue.pop_front();
+                        S.used += est;
+                        S.admitted++;
+                        S.planning++;
+                        if (h->t_admit == 0) h->t_admit = now_s();
+                        r = h;
+                        break;
+                    }
+                }
+                S.cv_plan.wait_for(lk, std::chrono::milliseconds(2));
+            }
+        }
+        const fmm_status st = plan_request(S, r);
+        bool retry = false;
+        {
+            std::lock_guard<std::mutex> lk(S.mu);
+            S.planning--;
+            if (st == FMM_OK) {
+                S.used += r->reserved - est;
+                S.planned.push_back(r);
+            } else if (st == FMM_E_NOMEM && S.admitted > 1) {
+                // Memory is held by other resident requests: queue again at
+                // the front and wait until one of them finishes.
+                S.used -= est;
+                S.admitted--;
+                S.queue.push_front(r);
+                retry = true;
+            } else {
+                r->reserved = est;
+                r->status = st;
+            }
+        }
+        if (st != FMM_OK && !retry) finish(S, r, false);
+        S.cv_sched.notify_all();
+        if (retry) {
+            std::unique_lock<std::mutex> lk(S.mu);
+            const int before = S.admitted;
+            S.cv_done.wait_for(lk, std::chrono::milliseconds(50), [&] { return S.admitted < before || S.stop; });
+        }
+    }
+}
+
+// Batch launches and completions.
 static void scheduler(Server *Sp)
 {
     Server &S = *Sp;
     hipSetDevice(S.device);
     for (;;) {
         bool progress = false;
-        // 1. completion of the running batch
-        if (!S.running.empty() && done_query(S.done_ev)) {
-            complete_batch(S, S.running);
-            S.running.clear();
-            progress = true;
-        }
-        // 2. admission and planning
-        for (;;) {
-            Req *r = nullptr;
+        for (Slot &L : S.slot)
+            if (L.busy && done_query(L.done)) {
+                complete_batch(S, L, true);
+                progress = true;
+            }
+        for (Slot &L : S.slot) {
+            if (L.busy) continue;
             {
                 std::lock_guard<std::mutex> lk(S.mu);
-                if (S.queue.empty() || S.admitted >= S.opt.max_inflight) break;
-                Req *h = S.queue.front();
-                const int64_t est = estimate_bytes(*h);
-                if (S.admitted > 0 && S.used + est > S.opt.hbm_budget_bytes) break;
-                S.queue.pop_front();
-                S.used += est;
-                S.admitted++;
-                h->reserved = est;
-                h->t_admit = now_s();
-                r = h;
+                if (S.planned.empty()) break;
+                L.reqs.swap(S.planned);
             }
-            const int64_t est = r->reserved;
-            const bool ok = plan_request(S, r);
-            {
-                std::lock_guard<std::mutex> lk(S.mu);
-                if (ok) S.used += r->reserved - est;
-                else r->reserved = est;
-            }
-            if (ok)
-                S.planned.push_back(r);
-            else
-                finish(S, r, false);
-            progress = true;
-            // Start evaluating as soon as the GPU is free.
-            if (S.running.empty()) break;
-            if (done_query(S.done_ev)) break;
-        }
-        // 3. launch the next batch
-        if (S.running.empty() && !S.planned.empty()) {
-            S.running.swap(S.planned);
-            launch_batch(S, S.running);
+            L.busy = true;
+            if (!launch_batch(S, L)) complete_batch(S, L, false);
             progress = true;
         }
         if (!progress) {
+            bool any_busy = false;
+            for (Slot &L : S.slot) any_busy = any_busy || L.busy;
             std::unique_lock<std::mutex> lk(S.mu);
-            if (S.stop && S.queue.empty() && S.running.empty() && S.planned.empty()) break;
-            S.cv.wait_for(lk, std::chrono::microseconds(S.running.empty() ? 2000 : 50));
+            if (S.stop && S.queue.empty() && S.planned.empty() && S.planning == 0 && !any_busy) break;
+            S.cv_sched.wait_for(lk, std::chrono::microseconds(any_busy ? 50 : 2000));
         }
     }
 }
@@ -280,23 +381,37 @@ fmm_status fmm_server_create(const fmm_server_options *opt, fmm_server_t *out)
     }
     Server *S = new Server();
     S->opt = *opt;
+    S->budget = opt->hbm_budget_bytes;
     hipGetDevice(&S->device);
-    if (hipStreamCreateWithFlags(&S->s_plan, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&S->s_eval, hipStreamNonBlocking) != hipSuccess ||
-        hipStreamCreateWithFlags(&S->s_near, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&S->done_ev, hipEventDisableTiming) != hipSuccess) {
+    {
+        // The budget never exceeds 90% of what the device has free now.
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr > 0)
+            S->budget = std::min<int64_t>(S->budget, (int64_t)(0.9 * (double)fr));
+        else
+            (void)hipGetLastError();
+    }
+    bool ok = hipStreamCreateWithFlags(&S->s_plan, hipStreamNonBlocking) == hipSuccess;
+    for (Slot &L : S->slot) {
+        ok = ok && hipStreamCreateWithFlags(&L.s, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&L.done, hipEventDisableTiming) == hipSuccess;
+        for (auto &e : L.bev) ok = ok && hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+    }
+    if (!ok) {
+        (void)hipGetLastError();
         set_error("stream or event creation failed");
+        for (Slot &L : S->slot) {
+            if (L.s) hipStreamDestroy(L.s);
+            if (L.done) hipEventDestroy(L.done);
+            for (auto &e : L.bev)
+                if (e) hipEventDestroy(e);
+        }
+        if (S->s_plan) hipStreamDestroy(S->s_plan);
         delete S;
         return FMM_E_DEVICE;
     }
-    for (auto &e : S->bev) {
-        if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-            set_error("event creation failed");
-            delete S;
-            return FMM_E_DEVICE;
-        }
-    }
-    S->th = std::thread(scheduler, S);
+    S->th_plan = std::thread(planner, S);
+    S->th_sched = std::thread(scheduler, S);
     *out = (fmm_server_t)S;
     return FMM_OK;
 }
@@ -332,7 +447,7 @@ fmm_status fmm_submit(fmm_server_t s, const fmm_request *req, uint64_t *ticket)
         S->all[r->ticket] = r;
         S->queue.push_back(r);
     }
-    S->cv.notify_all();
+    S->cv_plan.notify_all();
     *ticket = r->ticket;
     return FMM_OK;
 }
@@ -380,7 +495,8 @@ fmm_status fmm_server_drain(fmm_server_t s)
     for (;;) {
         bool busy = !S->queue.empty() || S->admitted > 0;
         if (!busy) return FMM_OK;
-        S->cv.notify_all();
+        S->cv_plan.notify_all();
+        S->cv_sched.notify_all();
         S->cv_done.wait_for(lk, std::chrono::milliseconds(1));
     }
 }
@@ -394,15 +510,18 @@ fmm_status fmm_server_destroy(fmm_server_t s)
         std::lock_guard<std::mutex> lk(S->mu);
         S->stop = true;
     }
-    S->cv.notify_all();
-    if (S->th.joinable()) S->th.join();
+    S->cv_plan.notify_all();
+    S->cv_sched.notify_all();
+    if (S->th_plan.joinable()) S->th_plan.join();
+    if (S->th_sched.joinable()) S->th_sched.join();
     for (auto &kv : S->all) delete kv.second;
-    if (S->jobs) dev_free(S->jobs, S->jobs_cap * sizeof(EvalJob));
-    hipEventDestroy(S->done_ev);
-    for (auto &e : S->bev) hipEventDestroy(e);
+    for (Slot &L : S->slot) {
+        if (L.jobs) dev_free(L.jobs, L.jobs_cap * sizeof(EvalJob));
+        hipEventDestroy(L.done);
+        for (auto &e : L.bev) hipEventDestroy(e);
+        hipStreamDestroy(L.s);
+    }
     hipStreamDestroy(S->s_plan);
-    hipStreamDestroy(S->s_eval);
-    hipStreamDestroy(S->s_near);
     delete S;
     return FMM_OK;
 }

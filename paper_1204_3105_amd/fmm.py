@@ -452,12 +452,15 @@ class Server:
         self._n[t.value] = r.n_tgt
         return t.value
 
-    def poll(self, ticket: int):
+    def poll(self, ticket: int, want_phi: bool = True):
+        """None while the request is queued or running; then (phi, result),
+        phi None when want_phi is false (the result is still consumed)."""
         n = self._n[ticket]
-        phi = np.empty(n, dtype=np.complex128)
+        phi = np.empty(n, dtype=np.complex128) if want_phi else None
         res = Result()
         st = lib().fmm_poll(self._s, C.c_uint64(ticket),
-                            phi.ctypes.data_as(C.POINTER(C.c_double)) if n else None, C.byref(res))
+                            phi.ctypes.data_as(C.POINTER(C.c_double)) if (n and want_phi) else None,
+                            C.byref(res))
         if st == 5:
             return None
         del self._n[ticket]

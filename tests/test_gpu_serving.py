@@ -98,3 +98,26 @@ def test_bad_request_does_not_disturb_others(F):
     for t, req in zip(tickets, stream):
         assert res[t][1]["status"] == "OK"
         assert np.array_equal(res[t][0], alone(F, *req))
+
+
+def test_small_request_overtakes_large_batch(F):
+    # A large FP64 request is planned and launched first; a small request
+    # submitted right after it is planned while the large batch runs, starts
+    # on the second evaluation stream and finishes first.  Both equal their
+    # solves alone.
+    big = inputs.uniform_square(8 << 20, seed=21)
+    small = inputs.uniform_square(3000, seed=22)
+    print("serving overtake: big n=%d fp64 eps 1e-10, small n=%d" % (big.n_src, small.n_src), flush=True)
+    with F.Server(hbm_budget_bytes=32 << 30, max_inflight=8) as srv:
+        tb = srv.submit("tri", big.xs, big.ys, big.u, eps=1e-10, precision="fp64")
+        ts = srv.submit("quad", small.xs, small.ys, small.u, eps=1e-6, precision="fp64")
+        res = wait_all(srv, [tb, ts])
+    rb, rs = res[tb][1], res[ts][1]
+    assert rb["status"] == "OK" and rs["status"] == "OK"
+    print("serving overtake: big start %.4f end %.4f, small start %.4f end %.4f" % (
+        rb["t_start"] - rb["t_submit"], rb["t_end"] - rb["t_submit"], rs["t_start"] - rb["t_submit"],
+        rs["t_end"] - rb["t_submit"]), flush=True)
+    assert rs["t_start"] >= rb["t_start"]   # the large batch was already running
+    assert rs["t_end"] < rb["t_end"]
+    assert np.array_equal(res[ts][0], alone(F, "quad", small.xs, small.ys, small.u, 1e-6, "fp64", None, None))
+    assert np.array_equal(res[tb][0], alone(F, "tri", big.xs, big.ys, big.u, 1e-10, "fp64", None, None))
