@@ -34,6 +34,18 @@ constexpr int kChunk = 64;        // targets per near-field work item (at most)
 // A leaf with at most this many chunks of kChunk targets evaluates the pairs
 // with its higher-indexed neighbours for both sides (mixed, targets = sources).
 constexpr int kSymChunks = 2;
+// The FP64 symmetric near-field kernel takes a leaf of at most kWide targets
+// as one item (up to kWide / 8 blocks of eight rows), so a leaf just above
+// kChunk points is not split into a full and a nearly empty item; the mixed
+// one splits every leaf into chunks of kChunk.
+constexpr int kWide = 96;
+// Chunks of a leaf with n targets in a symmetric kernel whose single items
+// hold up to `wide` targets (kWide for FP64, kChunk for mixed): one up to
+// `wide`, else ceil(n / kChunk).  Its second-side sums take one slot per chunk.
+__host__ __device__ inline int sym_chunks(int n, int wide)
+{
+    return n <= wide ? 1 : (n + kChunk - 1) / kChunk;
+}
 
 enum Tiling { kQuad = 0, kSept = 1, kTri = 2 };
 

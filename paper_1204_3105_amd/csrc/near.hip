@@ -25,6 +25,35 @@ static constexpr double kPi2Hi = 1.5707963267948966, kPi2Lo = 6.123233995736766e
 static constexpr double kPi6Hi = 0.5235987755982989, kPi6Lo = -5.360408832255455e-17;
 static constexpr double kInvSqrt3 = 0.5773502691896257, kTanPi12 = 0.2679491924311227;
 static constexpr double kSqrtHalf = 0.7071067811865476;
+// Series remainders on the reduced intervals, weighted minimax fits from
+// gen_f64_poly.py: ln m = 2s (1 + z P(z)) with z = s^2 <= (3 - 2 sqrt2)^2
+// (|z dP| <= 1.3e-18), atan t = t (1 + w Q(w)) with w = t^2 <= (2 - sqrt3)^2
+// (|w dQ| <= 1.6e-17); coefficient k multiplies z^k (w^k).
+static constexpr double kLnPoly[7] = {0.3333333333333367, 0.19999999999707335, 0.14285714371194552, 0.11111099286525694, 0.090917821661685105, 0.076570252032999594, 0.073979755249923215};
+static constexpr double kAtanPoly64[8] = {-0.33333333333331033, 0.19999999998955142, -0.14285714123172341, 0.11111098862513553, -0.090903969460381456, 0.076797606015821029, -0.064863446745019704, 0.044493669821161291};
+
+__device__ __forceinline__ double ln_poly(double z)
+{
+    double p = kLnPoly[6];
+    p = fma(p, z, kLnPoly[5]);
+    p = fma(p, z, kLnPoly[4]);
+    p = fma(p, z, kLnPoly[3]);
+    p = fma(p, z, kLnPoly[2]);
+    p = fma(p, z, kLnPoly[1]);
+    return fma(p, z, kLnPoly[0]);
+}
+
+__device__ __forceinline__ double atan_poly(double w)
+{
+    double q = kAtanPoly64[7];
+    q = fma(q, w, kAtanPoly64[6]);
+    q = fma(q, w, kAtanPoly64[5]);
+    q = fma(q, w, kAtanPoly64[4]);
+    q = fma(q, w, kAtanPoly64[3]);
+    q = fma(q, w, kAtanPoly64[2]);
+    q = fma(q, w, kAtanPoly64[1]);
+    return fma(q, w, kAtanPoly64[0]);
+}
 
 // n / d for d in a safe range (no zero, infinity or denormal): hardware
 // reciprocal, two Newton steps, one residual correction.
@@ -39,8 +68,8 @@ __device__ __forceinline__ double div_f64(double n, double d)
 
 // ln x for a positive normal x (Cody & Waite): x = 2^e m, m in
 // [sqrt(1/2), sqrt(2)); ln m = 2 atanh(s), s = (m - 1)/(m + 1),
-// |s| <= 3 - 2 sqrt(2); atanh(s)/s = sum_k s^(2k)/(2k+1), k <= 10
-// (remainder below 1e-17 relative); e ln 2 in two parts.
+// |s| <= 3 - 2 sqrt(2); atanh(s)/s = 1 + z P(z), z = s^2 (ln_poly, error
+// below 1.3e-18); e ln 2 in two parts.
 __device__ __forceinline__ double ln_f64(double x)
 {
     int e;
@@ -50,16 +79,7 @@ __device__ __forceinline__ double ln_f64(double x)
     e = lo ? e - 1 : e;
     const double s = div_f64(m - 1.0, m + 1.0);
     const double z = s * s;
-    double p = 1.0 / 21.0;
-    p = fma(p, z, 1.0 / 19.0);
-    p = fma(p, z, 1.0 / 17.0);
-    p = fma(p, z, 1.0 / 15.0);
-    p = fma(p, z, 1.0 / 13.0);
-    p = fma(p, z, 1.0 / 11.0);
-    p = fma(p, z, 1.0 / 9.0);
-    p = fma(p, z, 1.0 / 7.0);
-    p = fma(p, z, 1.0 / 5.0);
-    p = fma(p, z, 1.0 / 3.0);
+    const double p = ln_poly(z);
     const double lm = 2.0 * s + 2.0 * s * (z * p);
     const double de = (double)e;
     return fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
@@ -69,8 +89,8 @@ __device__ __forceinline__ double ln_f64(double x)
 // Waite): with mn, mx = min, max of |x|, |y|, t = mn/mx in [0, 1]; above
 // tan(pi/12) the addition formula with k = 1/sqrt(3) gives
 // atan t = pi/6 + atan((mn - k mx)/(mx + k mn)), so one division serves
-// both ranges; atan(t) = sum_k (-1)^k t^(2k+1)/(2k+1), k <= 13 for
-// |t| <= tan(pi/12); then the octant.
+// both ranges; atan(t) = t (1 + w Q(w)), w = t^2, for |t| <= tan(pi/12)
+// (atan_poly, error below 1.6e-17); then the octant.
 __device__ __forceinline__ double atan2_f64(double y, double x)
 {
     const double ax = fabs(x), ay = fabs(y);
@@ -80,19 +100,7 @@ __device__ __forceinline__ double atan2_f64(double y, double x)
     const double den = red ? fma(kInvSqrt3, mn, mx) : mx;
     const double t = div_f64(num, den);
     const double z = t * t;
-    double p = -1.0 / 27.0;
-    p = fma(p, z, 1.0 / 25.0);
-    p = fma(p, z, -1.0 / 23.0);
-    p = fma(p, z, 1.0 / 21.0);
-    p = fma(p, z, -1.0 / 19.0);
-    p = fma(p, z, 1.0 / 17.0);
-    p = fma(p, z, -1.0 / 15.0);
-    p = fma(p, z, 1.0 / 13.0);
-    p = fma(p, z, -1.0 / 11.0);
-    p = fma(p, z, 1.0 / 9.0);
-    p = fma(p, z, -1.0 / 7.0);
-    p = fma(p, z, 1.0 / 5.0);
-    p = fma(p, z, -1.0 / 3.0);
+    const double p = atan_poly(z);
     double a = fma(t * z, p, t);
     a = red ? kPi6Hi + (kPi6Lo + a) : a;
     a = (ay > ax) ? kPi2Hi + (kPi2Lo - a) : a;
@@ -126,34 +134,13 @@ __device__ __forceinline__ void ln_atan2_f64(double r2, double y, double x, doub
     const double t = (num * mp1) * R;
     // ln r2 = e ln 2 + 2 atanh(s)
     const double z = s * s;
-    double p = 1.0 / 21.0;
-    p = fma(p, z, 1.0 / 19.0);
-    p = fma(p, z, 1.0 / 17.0);
-    p = fma(p, z, 1.0 / 15.0);
-    p = fma(p, z, 1.0 / 13.0);
-    p = fma(p, z, 1.0 / 11.0);
-    p = fma(p, z, 1.0 / 9.0);
-    p = fma(p, z, 1.0 / 7.0);
-    p = fma(p, z, 1.0 / 5.0);
-    p = fma(p, z, 1.0 / 3.0);
+    const double p = ln_poly(z);
     const double lm = 2.0 * s + 2.0 * s * (z * p);
     const double de = (double)e;
     lnr2 = fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
     // atan t, then the octant
     const double w = t * t;
-    double q = -1.0 / 27.0;
-    q = fma(q, w, 1.0 / 25.0);
-    q = fma(q, w, -1.0 / 23.0);
-    q = fma(q, w, 1.0 / 21.0);
-    q = fma(q, w, -1.0 / 19.0);
-    q = fma(q, w, 1.0 / 17.0);
-    q = fma(q, w, -1.0 / 15.0);
-    q = fma(q, w, 1.0 / 13.0);
-    q = fma(q, w, -1.0 / 11.0);
-    q = fma(q, w, 1.0 / 9.0);
-    q = fma(q, w, -1.0 / 7.0);
-    q = fma(q, w, 1.0 / 5.0);
-    q = fma(q, w, -1.0 / 3.0);
+    const double q = atan_poly(w);
     double a = fma(t * w, q, t);
     a = red ? kPi6Hi + (kPi6Lo + a) : a;
     a = (ay > ax) ? kPi2Hi + (kPi2Lo - a) : a;
@@ -374,7 +361,7 @@ __global__ __launch_bounds__(64) void k_l2p(const EvalJob *__restrict__ jobs, Ba
             int nch = 0;
             const int32_t c = lane ? J.near[li * J.nw + lane] : -1;
             if (c >= 0 && c < gid) {
-                nch = (J.se[c] - J.sb[c] + kChunk - 1) / kChunk;
+                nch = sym_chunks(J.se[c] - J.sb[c], J.bside64 ? kWide : kChunk);
                 if (nch > kSymChunks) nch = 0;
             }
             bsn[lane] = (int8_t)nch;
@@ -580,33 +567,12 @@ __device__ __forceinline__ void ln_atan2_pair_f64(double r2, double y, double x,
     const double s = ((m - 1.0) * den) * R;
     const double t = (num * mp1) * R;
     const double z = s * s;
-    double p = 1.0 / 21.0;
-    p = fma(p, z, 1.0 / 19.0);
-    p = fma(p, z, 1.0 / 17.0);
-    p = fma(p, z, 1.0 / 15.0);
-    p = fma(p, z, 1.0 / 13.0);
-    p = fma(p, z, 1.0 / 11.0);
-    p = fma(p, z, 1.0 / 9.0);
-    p = fma(p, z, 1.0 / 7.0);
-    p = fma(p, z, 1.0 / 5.0);
-    p = fma(p, z, 1.0 / 3.0);
+    const double p = ln_poly(z);
     const double lm = 2.0 * s + 2.0 * s * (z * p);
     const double de = (double)e;
     lnr2 = fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
     const double w = t * t;
-    double q = -1.0 / 27.0;
-    q = fma(q, w, 1.0 / 25.0);
-    q = fma(q, w, -1.0 / 23.0);
-    q = fma(q, w, 1.0 / 21.0);
-    q = fma(q, w, -1.0 / 19.0);
-    q = fma(q, w, 1.0 / 17.0);
-    q = fma(q, w, -1.0 / 15.0);
-    q = fma(q, w, 1.0 / 13.0);
-    q = fma(q, w, -1.0 / 11.0);
-    q = fma(q, w, 1.0 / 9.0);
-    q = fma(q, w, -1.0 / 7.0);
-    q = fma(q, w, 1.0 / 5.0);
-    q = fma(q, w, -1.0 / 3.0);
+    const double q = atan_poly(w);
     double a = fma(t * w, q, t);
     a = red ? kPi6Hi + (kPi6Lo + a) : a;
     a = (ay > ax) ? kPi2Hi + (kPi2Lo - a) : a;
@@ -629,17 +595,19 @@ __device__ __forceinline__ double bperm_f64(int addr, double v)
 // the mixed symmetric kernel: a neighbour pair {A, B} (A the lower cell id,
 // with at most kSymChunks chunks) is evaluated once, by A's items, for both
 // sides; the leaf itself, and pairs whose lower leaf is larger, one-sided.
-// An 8 x 8 lane tile: A's targets (up to 64) in LDS in blocks of eight rows,
+// An 8 x 8 lane tile: A's targets (all of a leaf of up to kWide = 96, else
+// a chunk of 64) in LDS in blocks of eight rows,
 // eight of a cell's sources per round in the columns (absolute coordinates,
 // loaded a round ahead), so every separation, and with it the sign of dy, is
 // exact.  Sums are FP64 throughout: A's in the lanes, reduced over the
 // columns at the end; B's reduced over the rows each round and stored per
 // (point, lower neighbour, its chunk) in bside64 for L2P.
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_near_fp64_sym(const EvalJob *__restrict__ jobs, BatchMap bm)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_near_fp64_sym(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
     __shared__ int32_t cbeg[kNearSlots], cend[kNearSlots], cslot[kNearSlots];
     __shared__ int8_t cmode[kNearSlots];
-    __shared__ double sax[64], say[64], sau[64];   // A's targets
+    __shared__ double2 sxy[kWide];   // A's targets: coordinates
+    __shared__ double sau[kWide];    // and strengths
     const int lane = threadIdx.x, row = lane >> 3, col = lane & 7;
     // ds_bpermute byte addresses of lane ^ 1, 2, 4 (columns) and ^ 8, 16, 32 (rows)
     const int perm1 = (lane ^ 1) << 2, perm2 = (lane ^ 2) << 2, perm4 = (lane ^ 4) << 2;
@@ -653,22 +621,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         const int64_t gid = J.leaf_off + li;
         const int nw = uniform(J.nw);
         const int32_t tb = uniform(J.tb[gid]), te = uniform(J.te[gid]);
-        const int m = min(kChunk, te - st);
+        // A leaf of at most kWide targets is one item (its first); larger
+        // leaves go in chunks of kChunk.
+        const bool wide = te - tb <= kWide;
+        if (wide && st != tb) continue;
+        const int m = wide ? te - tb : min(kChunk, te - st);
         const int nblk = (m + 7) >> 3;
-        const int chunk = (st - tb) / kChunk;
-        const bool own_sym = (te - tb + kChunk - 1) / kChunk <= kSymChunks;
+        const int chunk = wide ? 0 : (st - tb) / kChunk;
+        const bool own_sym = sym_chunks(te - tb, kWide) <= kSymChunks;
 
         __syncthreads();   // the previous item is done with the LDS
-        {
+        for (int q = lane; q < kWide; q += 64) {
             // Padding targets: zero strength, far from every source and from
             // the padding source, so no separation in the tile is zero (the
             // symmetric rounds have no zero-separation guard, and a zero
             // there would turn a padding row's 0 x log 0 into a NaN in the
             // B-side sums).
-            const bool ok = lane < m;
-            sax[lane] = ok ? J.tx[st + lane] : -1e100;
-            say[lane] = ok ? J.ty[st + lane] : -1e100;
-            sau[lane] = ok ? J.su[st + lane] : 0.0;
+            const bool ok = q < m;
+            sxy[q] = make_double2(ok ? J.tx[st + q] : -1e100, ok ? J.ty[st + q] : -1e100);
+            sau[q] = ok ? J.su[st + q] : 0.0;
         }
         if (lane < nw) {
             const int32_t c = J.near[li * nw + lane];
@@ -686,7 +657,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                         mode = kCellSym;
                         slot = (k2 - 1) * kSymChunks + chunk;
                     }
-                } else if (lane > 0 && c < gid && (e0 - b0 + kChunk - 1) / kChunk <= kSymChunks) {
+                } else if (lane > 0 && c < gid && sym_chunks(e0 - b0, kWide) <= kSymChunks) {
                     mode = kCellSkip;
                 }
             }
@@ -739,12 +710,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                 const double sx = nxt.ok ? nxt.x : 1e100, sy = nxt.ok ? nxt.y : 1e100;
                 const double su = nxt.ok ? nxt.w : 0.0;
                 nxt = fetch(k2, b2);
+                // The targets are read from LDS every round (an opaque copy of
+                // the row index keeps the reads in the loop): holding twelve
+                // blocks' coordinates and strengths in registers would spill.
+                int qrow = row;
+                asm volatile("" : "+v"(qrow));
                 if (uniform(cmode[k]) == kCellSym) {
                     double br = 0.0, bi = 0.0;
 #pragma unroll
                     for (int blk = 0; blk < NB; ++blk) {
-                        const int q = 8 * blk + row;
-                        const double dx = sax[q] - sx, dy = say[q] - sy, u = sau[q];
+                        const int q = 8 * blk + qrow;
+                        const double2 t = sxy[q];
+                        const double dx = t.x - sx, dy = t.y - sy, u = sau[q];
                         double lg, at, atr;
                         ln_atan2_pair_f64(fma(dx, dx, dy * dy), dy, dx, lg, at, atr);
                         ar[blk] = fma(su, lg, ar[blk]);
@@ -768,8 +745,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                     // equal point) is skipped
 #pragma unroll
                     for (int blk = 0; blk < NB; ++blk) {
-                        const int q = 8 * blk + row;
-                        const double dx = sax[q] - sx, dy = say[q] - sy;
+                        const int q = 8 * blk + qrow;
+                        const double2 t = sxy[q];
+                        const double dx = t.x - sx, dy = t.y - sy;
                         const double r2 = fma(dx, dx, dy * dy);
                         const bool live = r2 > 0.0;
                         double lg, at;
@@ -799,6 +777,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
                 }
             }
         };
+        static_assert(kWide == 96, "one case per number of target blocks");
         switch (nblk) {
         case 1: item_rounds(std::integral_constant<int, 1>{}); break;
         case 2: item_rounds(std::integral_constant<int, 2>{}); break;
@@ -807,7 +786,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4, 8))) void
         case 5: item_rounds(std::integral_constant<int, 5>{}); break;
         case 6: item_rounds(std::integral_constant<int, 6>{}); break;
         case 7: item_rounds(std::integral_constant<int, 7>{}); break;
-        default: item_rounds(std::integral_constant<int, 8>{}); break;
+        case 8: item_rounds(std::integral_constant<int, 8>{}); break;
+        case 9: item_rounds(std::integral_constant<int, 9>{}); break;
+        case 10: item_rounds(std::integral_constant<int, 10>{}); break;
+        case 11: item_rounds(std::integral_constant<int, 11>{}); break;
+        default: item_rounds(std::integral_constant<int, 12>{}); break;
         }
     }
 }
