@@ -80,14 +80,45 @@ def test_run_steps_issue_order_with_and_without_threads():
 
 def test_near_roofline_from_plan_infos():
     # two tilings, one launch each: VALU operations over the launch time
-    # against the issue rate; FP64 carries no committed traffic figure
+    # against the issue rate; traffic only from a committed counter summary
+    # whose kernel source is unchanged
     infos = {"quad": [{"stage_ms": [0, 0, 0, 0.5, 0], "n_near_pairs": 100, "near_valu_ops": 4e9,
                        "targets_are_sources": True}],
              "tri": [{"stage_ms": [0, 0, 0, 1.5, 0], "n_near_pairs": 300, "near_valu_ops": 8e9,
                       "targets_are_sources": True}]}
     r = bench.near_roofline(infos, ["quad", "tri"], "fp64")
     assert r["kernel"].endswith("k_near_fp64_sym")
-    assert r["traffic"] is None
+    assert r["traffic"] == bench.committed_traffic("k_near_fp64_sym")
     assert abs(r["achieved"] * 1e9 - 6e9 / 1e-3) < 1.0
     assert abs(r["frac"] - 6e12 / bench.LANE_OPS) < 1e-12
-    assert r["valu_per_pair"] == {"symmetric_eval": 92.0, "one_sided": 104.0}
+    assert r["valu_per_pair"] == {"symmetric_eval": 79.5, "one_sided": 82.0}
+
+
+def test_m2l_flop_model_by_hand():
+    # p = 22: algorithmic 8 (p+1)^2 = 4232 per pair; FP64 MFMA form: rows
+    # 0..22 in two 16-row tiles, k' = 0..21 in six 4-deep steps, Re and Im
+    # columns: 2 x 32 x 24 x 2 = 3072 per pair; BF16x3: six products of a
+    # 48 x 64 padded real block: 6 x 2 x 48 x 64 = 36864 per pair
+    alg, issued, peak = bench.m2l_flops("fp64", 22, 10)
+    assert alg == 42320 and issued == 30720 and peak == bench.FP64_PEAK
+    alg, issued, peak = bench.m2l_flops("mixed", 22, 10)
+    assert alg == 42320 and issued == 368640 and peak == bench.MFMA_BF16_PEAK
+    # p = 15 fills one row tile and four k-steps exactly
+    assert bench.m2l_flops("fp64", 15, 1)[1] == 2 * 16 * 16 * 2
+    f = bench.m2l_fraction("fp64", 22, 10, 1.0)
+    assert abs(f["frac_alg"] - 42320 / 1e-3 / bench.FP64_PEAK) < 1e-15
+
+
+def test_committed_traffic_checks_the_source_hash(tmp_path, monkeypatch):
+    import hashlib
+    import json
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "k.hip").write_bytes(b"kernel source")
+    rec = {"kernel": "k_x", "source": "k.hip", "sha256": hashlib.sha256(b"kernel source").hexdigest(),
+           "bytes_per_launch": 123.0}
+    (tmp_path / "profiles" / "x.md").write_text("# x\n\n```json\n%s\n```\n" % json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.committed_traffic("k_x") == 123.0
+    assert bench.committed_traffic("k_y") is None
+    (tmp_path / "k.hip").write_bytes(b"kernel source, changed")
+    assert bench.committed_traffic("k_x") is None
