@@ -306,19 +306,20 @@ def near_roofline(infos, tilings, prec):
 def m2l_flops(prec, p, pairs):
     """Algorithmic M2L flops (8 (p+1)^2 per E4 pair: a complex (p+1) x (p+1)
     matrix-vector product) and the MFMA flops the kernel issues for them.
-    FP64: H (rows 0..p in 16-row tiles, k' = 0..p-1 in 4-deep steps) times the
-    pair's Re and Im columns, 16 columns per MFMA (full tiles; a tile with
-    fewer targets issues the same MFMAs).  Mixed: six BF16 split products of
-    a real 2(p+1) x 2p block per pair, padded to 16-row tiles and 32-deep
-    k-blocks."""
+    Both forms apply the offset-free binomial matrix H (rows m = 0..p, columns
+    k' = 0..p-1) to the pair's scaled Re and Im columns, 16 columns per MFMA
+    (full tiles; a tile with fewer targets issues the same MFMAs).  FP64: rows
+    in 16-row tiles, k' in 4-deep steps.  Mixed, 16 <= p <= 47: six BF16 split
+    products, rows in 16-row tiles, k' in 32-deep blocks; below p = 16 the
+    mixed form runs the FP64 kernel."""
     alg = 8.0 * (p + 1) ** 2 * pairs
-    if prec == "fp64":
+    if prec == "fp64" or not 16 <= p <= 47:
         mt, kt = (p + 1 + 15) // 16, (p + 3) // 4
         issued = 2.0 * (16 * mt) * (4 * kt) * 2.0 * pairs
         peak = FP64_PEAK
     else:
-        mt, kb = (2 * (p + 1) + 15) // 16, (2 * p + 31) // 32
-        issued = 6.0 * 2.0 * (16 * mt) * (32 * kb) * pairs
+        mt, kb = (p + 1 + 15) // 16, (p + 31) // 32
+        issued = 6.0 * 2.0 * (16 * mt) * (32 * kb) * 2.0 * pairs
         peak = MFMA_BF16_PEAK
     return alg, issued, peak
 

@@ -19,7 +19,7 @@ constexpr int kBinomStride = 2 * kMaxP + 2;
 
 struct EvalJob {
     int p, L, tiling, base, prec;
-    int nw, ew, G, pm, MT, KB, sept;
+    int nw, ew, G, pm, sept;
     int64_t n_src, n_tgt, n_cells, leaf_off, n_leaf, m2l_first;
     double scale[kMaxL + 1];
     int64_t cell_off[kMaxL + 2];
@@ -36,11 +36,10 @@ struct EvalJob {
     const double *cx, *cy;
     double *mp, *lc;
     const double *m2l_pw, *m2l_lg, *m2l_a0, *binom;
-    const __bf16 *mix_tab;
-    const int32_t *mix_tiles, *mix_list;
-    __bf16 *mix_b;   // split multipoles (mixed M2L B operands)
-    int mix_split;   // 1: P2M and the block-form M2M write mix_b as they write the multipoles
-    // Device counts written at plan time: [0] near-field items, [1] mixed M2L
+    // M2L tiles of up to 16 target cells of one (level, group) {key, first
+    // list position, count, 0}, their launch order, and the list of the cells
+    const int32_t *mix_tiles, *mix_order, *mix_list;
+    // Device counts written at plan time: [0] near-field items, [1] M2L
     // tiles.  Launches are sized by host upper bounds; kernels stop here.
     const int32_t *counts;
     double *phi;    // output, caller's target order, 2 n_tgt doubles
@@ -90,30 +89,6 @@ constexpr int kNearWavesPerCU = 128;
 // the remaining issue slots.
 __device__ __forceinline__ void far_field_priority() { __builtin_amdgcn_s_setprio(2); }
 
-// BF16x3 split of an FP32 value: x = h + m + l (24 significand bits).
-__device__ __forceinline__ void split3(float x, __bf16 &h, __bf16 &m, __bf16 &l)
-{
-    h = (__bf16)x;
-    const float r1 = x - (float)h;
-    m = (__bf16)r1;
-    const float r2 = r1 - (float)m;
-    l = (__bf16)r2;
-}
-
-// The mixed M2L's B operand of one cell: value i (0 <= i < 32 KB) of the
-// real coefficient vector (Re, Im of a~_1 .. a~_p, zero beyond 2p), split in
-// three and stored in the layout [cell][k-block][part][lane group q] bf16x8.
-__device__ __forceinline__ void store_split(__bf16 *mix_b, int64_t cell, int KB, int i, double v)
-{
-    const int kb = i / 32, q = (i % 32) / 8, j = i % 8;
-    __bf16 h, m, l;
-    split3((float)v, h, m, l);
-    __bf16 *o = mix_b + ((cell * KB + kb) * 12 + q) * 8 + j;
-    o[0] = h;
-    o[32] = m;
-    o[64] = l;
-}
-
 // A value that is the same in every lane, moved to a scalar register.
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
@@ -144,11 +119,11 @@ void batch_m2m_lanes(const EvalJob *jobs, const BatchMap &m, int pm, int gs, hip
 void batch_l2l_lanes(const EvalJob *jobs, const BatchMap &m, int pm, hipStream_t s);
 void batch_m2l_block(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_m2l_lanes(const EvalJob *jobs, const BatchMap &m, int pm, hipStream_t s);
-void batch_m2l_mixed(const EvalJob *jobs, const BatchMap &m, int MT, int KB, hipStream_t s);
 // FP64 M2L on MFMA; every job of the batch has kernel class m2l_f64_mfma_class(p).
 void batch_m2l_f64_mfma(const EvalJob *jobs, const BatchMap &m, int p, hipStream_t s);
-bool mixed_shape_supported(int MT, int KB);
-void batch_split_mp(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
+// Mixed M2L, factored BF16x3 on MFMA; every job has class m2l_bf16x3f_class(p).
+void batch_m2l_bf16x3f(const EvalJob *jobs, const BatchMap &m, int p, hipStream_t s);
+int m2l_bf16x3f_class(int p);
 void batch_near_fp64(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_l2p(const EvalJob *jobs, const BatchMap &m, hipStream_t s);
 void batch_near_mixed(const EvalJob *jobs, const BatchMap &m, hipStream_t s);

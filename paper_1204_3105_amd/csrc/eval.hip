@@ -21,8 +21,7 @@
 
 namespace fmm {
 
-void mixed_pointers(const Plan &P, const __bf16 **tab, const int32_t **tiles, const int32_t **list,
-                    __bf16 **bsplit, int *MT, int *KB);
+void tile_pointers(const Plan &P, const int32_t **tiles, const int32_t **order, const int32_t **list);
 
 EvalJob make_job(const Plan &P)
 {
@@ -87,19 +86,7 @@ EvalJob make_job(const Plan &P)
     J.nsum = P.nsum;
     J.bside = P.bside;
     J.bside64 = P.bside64;
-    if (P.precision == FMM_PREC_MIXED && P.mixed) {
-        int MT, KB;
-        mixed_pointers(P, &J.mix_tab, &J.mix_tiles, &J.mix_list, &J.mix_b, &MT, &KB);
-        J.MT = MT;
-        J.KB = KB;
-        J.mix_split = P.mixed_tiles > 0 && base_of(P.geo.tiling) == 4 ? 1 : 0;
-    } else if (P.mixed) {
-        // FP64 M2L on MFMA: only the target tiles and their cell list
-        const __bf16 *tab;
-        __bf16 *bsplit;
-        int MT, KB;
-        mixed_pointers(P, &tab, &J.mix_tiles, &J.mix_list, &bsplit, &MT, &KB);
-    }
+    if (P.mixed) tile_pointers(P, &J.mix_tiles, &J.mix_order, &J.mix_list);
     return J;
 }
 
@@ -243,17 +230,6 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
                 }
                 go(f);
             }
-    // Split multipoles for the BF16x3 M2L.
-    {
-        auto f = [&](const BatchMap &m) { batch_split_mp(jobs_dev, m, s); };
-        for (int i = 0; i < n; ++i) {
-            const Plan &P = *plans[i];
-            if (P.precision != FMM_PREC_MIXED || P.mixed_tiles == 0) continue;
-            if (base_of(P.geo.tiling) == 4) continue;   // P2M and M2M wrote the splits
-            Lc.add(i, 0, (P.n_cells - P.lev[1].cell_off) * 4 * ((2 * P.p + 31) / 32), f);
-        }
-        go(f);
-    }
     hipEventRecord(ev[0], s);
 
     // M2L, one launch per kernel variant present in the batch.
@@ -270,22 +246,26 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
             }
             go(f);
         }
-        // FP64 on MFMA, one launch per kernel class present
-        {
+        // FP64 on MFMA, then BF16x3 on MFMA; one launch per kernel class
+        // present
+        for (int bf = 0; bf < 2; ++bf) {
+            auto cls_of = [&](const Plan &P) {
+                if (P.mixed_tiles == 0) return 0;
+                if (m2l_bf16x3_form(P) != (bf == 1)) return 0;
+                return bf ? m2l_bf16x3f_class(P.p) : m2l_f64_mfma_class(P.p);
+            };
             std::vector<int> done;
             for (int i = 0; i < n; ++i) {
                 const Plan &Pi = *plans[i];
-                if (Pi.precision == FMM_PREC_MIXED || Pi.mixed_tiles == 0) continue;
-                const int cls = m2l_f64_mfma_class(Pi.p);
-                if (std::find(done.begin(), done.end(), cls) != done.end()) continue;
+                const int cls = cls_of(Pi);
+                if (cls == 0 || std::find(done.begin(), done.end(), cls) != done.end()) continue;
                 done.push_back(cls);
-                auto f = [&](const BatchMap &m) { batch_m2l_f64_mfma(jobs_dev, m, Pi.p, s); };
-                for (int k = i; k < n; ++k) {
-                    const Plan &P = *plans[k];
-                    if (P.precision == FMM_PREC_MIXED || P.mixed_tiles == 0 || m2l_f64_mfma_class(P.p) != cls)
-                        continue;
-                    Lc.add(k, 0, P.mixed_tiles, f);
-                }
+                auto f = [&](const BatchMap &m) {
+                    if (bf) batch_m2l_bf16x3f(jobs_dev, m, Pi.p, s);
+                    else batch_m2l_f64_mfma(jobs_dev, m, Pi.p, s);
+                };
+                for (int k = i; k < n; ++k)
+                    if (cls_of(*plans[k]) == cls) Lc.add(k, 0, plans[k]->mixed_tiles, f);
                 go(f);
             }
         }
@@ -296,18 +276,6 @@ void run_batch(Plan *const *plans, int n, const EvalJob *jobs_dev, double *phi_s
             Lc.add(i, 0, P.n_cells - P.lev[1].cell_off, fb);
         }
         go(fb);
-        for (int mt = 1; mt <= 7; ++mt)
-            for (int kb = 1; kb <= 3; ++kb) {
-                if (!mixed_shape_supported(mt, kb)) continue;
-                auto f = [&](const BatchMap &m) { batch_m2l_mixed(jobs_dev, m, mt, kb, s); };
-                for (int i = 0; i < n; ++i) {
-                    const Plan &P = *plans[i];
-                    if (P.precision != FMM_PREC_MIXED || P.mixed_tiles == 0) continue;
-                    if ((2 * (P.p + 1) + 15) / 16 != mt || (2 * P.p + 31) / 32 != kb) continue;
-                    Lc.add(i, 0, P.mixed_tiles, f);
-                }
-                go(f);
-            }
     }
     hipEventRecord(ev[1], s);
 

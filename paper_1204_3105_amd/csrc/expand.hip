@@ -168,15 +168,6 @@ __global__ __launch_bounds__(64) void k_p2m(const EvalJob *__restrict__ jobs, Ba
         }
         if (lane < R) row[lane] = acc;
         if (lane + 64 < R) row[lane + 64] = acc2;
-        if (J.mix_split) {
-            // the mixed M2L's B operand of this leaf: value i is row i + 2
-            // (every lane takes part in the shuffles: a lane that is off reads as zero)
-            for (int i0 = 0; i0 < 32 * J.KB; i0 += 64) {
-                const int i = i0 + lane, r = i + 2;
-                const double v0 = lane_read(acc, r & 63), v1 = lane_read(acc2, (r - 64) & 63);
-                if (i < 32 * J.KB) store_split(J.mix_b, gid, J.KB, i, i < 2 * p ? (r < 64 ? v0 : v1) : 0.0);
-            }
-        }
     }
 }
 
@@ -208,8 +199,6 @@ __global__ __launch_bounds__(64) void k_m2m(const EvalJob *__restrict__ jobs, Ba
         double *row = J.mp + gid * 2 * P1;
         if (!(J.occ[gid] & 1)) {
             if (m < P1) row[2 * m] = row[2 * m + 1] = 0.0;
-            if (J.mix_split)
-                for (int i = m; i < 32 * J.KB; i += 64) store_split(J.mix_b, gid, J.KB, i, 0.0);
             continue;
         }
         const double inv = 1.0 / J.scale[l];
@@ -255,15 +244,6 @@ __global__ __launch_bounds__(64) void k_m2m(const EvalJob *__restrict__ jobs, Ba
         if (m < P1) {
             row[2 * m] = acc.x;
             row[2 * m + 1] = acc.y;
-        }
-        if (J.mix_split) {
-            // the mixed M2L's B operand: value i is Re / Im of coefficient i/2 + 1
-            // (every lane takes part in the shuffles: a lane that is off reads as zero)
-            for (int i0 = 0; i0 < 32 * J.KB; i0 += 64) {
-                const int i = i0 + m, c = (i / 2 + 1) & 63;
-                const double vx = lane_read(acc.x, c), vy = lane_read(acc.y, c);
-                if (i < 32 * J.KB) store_split(J.mix_b, gid, J.KB, i, i < 2 * J.p ? ((i & 1) ? vy : vx) : 0.0);
-            }
         }
         __syncthreads();
     }

@@ -233,6 +233,11 @@ const double *device_binom(int *err);
 int m2l_pm_for(int p);
 // FP64 M2L on MFMA: kernel class of order p (0 = not supported).
 int m2l_f64_mfma_class(int p);
+// The mixed form's M2L runs as BF16x3 products on MFMA when the order needs
+// more than one 16-row output tile (16 <= p <= 47); at lower orders the FP64
+// MFMA kernel (2 ceil(p/4) FP64 MFMAs per pair and row tile) finishes before
+// the BF16x3 kernel has split its operands, so the mixed form uses it too.
+inline bool m2l_bf16x3_form(const Plan &P) { return P.precision == FMM_PREC_MIXED && P.p >= 16 && P.p <= 47; }
 size_t m2l_table_doubles(const Plan &P, int pm);
 void launch_m2l_tables(Plan &P, int pm, double *base, hipStream_t s);
 

@@ -279,22 +279,24 @@ __global__ void k_depth_hist(GeoParams g, const double *__restrict__ pts, int64_
 
 // For one coarser level: cell c covers the trial-level keys [c span, (c+1)
 // span) (keys are digit prefixes).  Accumulates sum_c s_c t_c, the source-
-// and the target-occupied cell counts (64-bit integer atomics: exact).
+// and the target-occupied cell counts (64-bit integer sums: exact in any
+// order).  A bounded grid strides over the cells, so the three counters take
+// few atomics.
 __global__ __launch_bounds__(256) void k_depth_stats(const uint32_t *__restrict__ hs, const uint32_t *__restrict__ ht,
                                                       int64_t ncells, int64_t span, unsigned long long *__restrict__ out)
 {
     __shared__ unsigned long long part[3][4];
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     unsigned long long v[3] = {0, 0, 0};
-    if (c < ncells) {
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncells;
+         c += (int64_t)gridDim.x * blockDim.x) {
         unsigned long long s = 0, t = 0;
         for (int64_t j = c * span; j < (c + 1) * span; ++j) {
             s += hs[j];
             t += ht[j];
         }
-        v[0] = s * t;
-        v[1] = s ? 1 : 0;
-        v[2] = t ? 1 : 0;
+        v[0] += s * t;
+        v[1] += s ? 1 : 0;
+        v[2] += t ? 1 : 0;
     }
     // block sums first: three atomics per block
     for (int q = 0; q < 3; ++q) {
@@ -325,7 +327,8 @@ void launch_depth_hist(const GeoParams &g, const double *pts, int64_t n, int64_t
 void launch_depth_stats(const uint32_t *hs, const uint32_t *ht, int64_t ncells, int64_t span,
                         unsigned long long *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_depth_stats, dim3((unsigned)((ncells + 255) / 256)), dim3(256), 0, s, hs, ht, ncells,
+    const int64_t blocks = std::min<int64_t>((ncells + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_depth_stats, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s, hs, ht, ncells,
                        span, out);
 }
 

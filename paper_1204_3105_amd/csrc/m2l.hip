@@ -294,19 +294,15 @@ __global__ __launch_bounds__(256) void k_m2l_f64_mfma(const EvalJob *__restrict_
                 h[mt][t] = (m <= kMaxP && kp < kMaxP) ? binom[(m + kp) * kBinomStride + kp] : 0.0;
             }
     }
-    // This lane's output rows m = 16 mt + 4 q + j: (-1)^m and 1/m (0 for m = 0).
-    double sg[MT][4], im_[MT][4];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int m = f64_out_row(mt, q, j);
-            sg[mt][j] = (m & 1) ? -1.0 : 1.0;
-            im_[mt][j] = m ? 1.0 / (double)m : 0.0;
-        }
+    // 1/m for the output rows (0 for m = 0); every row m = 16 mt + q + 4 j of
+    // this lane has the parity of q, so the sign (-1)^m of D_out is one value.
+    __shared__ double invm[NR];
+    for (int i = threadIdx.x; i < NR; i += 256) invm[i] = i ? 1.0 / (double)i : 0.0;
+    const double sgn = (q & 1) ? -1.0 : 1.0;
 
-    // XCD-aware order: each XCD takes a contiguous range of the tiles, so
-    // tiles of one (level, group) share an L2.
+    // XCD-aware order: each XCD takes a contiguous range of the tiles in
+    // their launch order (by first cell), so the tiles of one region of a
+    // level, of every group, share an L2 and its source multipoles.
     const int64_t total = bm.pre[bm.n];
     const int xcd = blockIdx.x % 8, lb = blockIdx.x / 8, nb = gridDim.x / 8;
     const int64_t t_beg = total * xcd / 8, t_end = total * (xcd + 1) / 8;
@@ -314,7 +310,7 @@ __global__ __launch_bounds__(256) void k_m2l_f64_mfma(const EvalJob *__restrict_
         const int e = batch_entry(bm, item);
         const EvalJob &J = jobs[bm.job[e]];
         if (item - bm.pre[e] >= J.counts[1]) continue;   // block-uniform
-        const int32_t *tile = J.mix_tiles + 4 * (item - bm.pre[e]);
+        const int32_t *tile = J.mix_tiles + 4 * J.mix_order[item - bm.pre[e]];
         const int key = tile[0], start = tile[1], count = tile[2];
         const int G = J.G, S = J.ew, p = J.p, pm = J.pm;
         const int l = key / G, g = key % G;
@@ -375,8 +371,8 @@ __global__ __launch_bounds__(256) void k_m2l_f64_mfma(const EvalJob *__restrict_
                 for (int j = 0; j < 4; ++j) {
                     const int m = f64_out_row(mt, q, j);
                     const double2 d = ts[m];
-                    const double dr = sg[mt][j] * d.x, di = sg[mt][j] * d.y;
-                    const double y = fma(-a0, im_[mt][j], yr[j]);
+                    const double dr = sgn * d.x, di = sgn * d.y;
+                    const double y = fma(-a0, invm[m], yr[j]);
                     accr[mt][j] = fma(y, dr, fma(-yi[j], di, accr[mt][j]));
                     acci[mt][j] = fma(y, di, fma(yi[j], dr, acci[mt][j]));
                 }

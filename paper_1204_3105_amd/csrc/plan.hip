@@ -350,7 +350,7 @@ static int order_for(int tiling, double eps);
 // mixed form's FP32 copies and the symmetric near field's second-side sums;
 // per cell (at most 3 n / leaf over all levels, more for clustered inputs
 // at deeper levels): multipole and local rows, E4 and near lists, the dense
-// key maps, the mixed M2L's split columns; plus 2 MiB granules per buffer.
+// key maps, the M2L tiles; plus 2 MiB granules per buffer.
 int64_t plan_bytes_estimate(int tiling, int64_t n_src, int64_t n_tgt, bool same, double eps, int precision,
                             int leaf_size)
 {
@@ -367,7 +367,7 @@ int64_t plan_bytes_estimate(int tiling, int64_t n_src, int64_t n_tgt, bool same,
     else if (same) per_pt += (nw - 1) * kSymChunks * 16;
     const int64_t cells = 3 * pts / std::max(leaf_size, 1) + 64;
     int64_t per_cell = 2 * 16 * (p + 1) + 4 * (ew + nw) + 64 + 48;
-    if (prec == FMM_PREC_MIXED) per_cell += 12 * 16 * ((2 * p + 31) / 32);
+    per_cell += 24;   // M2L tiles: cell list, sort keys and the sort scratch
     return per_pt * pts + per_cell * cells + ((int64_t)48 << 20);
 }
 

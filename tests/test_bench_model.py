@@ -97,12 +97,15 @@ def test_near_roofline_from_plan_infos():
 def test_m2l_flop_model_by_hand():
     # p = 22: algorithmic 8 (p+1)^2 = 4232 per pair; FP64 MFMA form: rows
     # 0..22 in two 16-row tiles, k' = 0..21 in six 4-deep steps, Re and Im
-    # columns: 2 x 32 x 24 x 2 = 3072 per pair; BF16x3: six products of a
-    # 48 x 64 padded real block: 6 x 2 x 48 x 64 = 36864 per pair
+    # columns: 2 x 32 x 24 x 2 = 3072 per pair; BF16x3: six products of H
+    # padded to 32 rows x 32 columns with the two columns: 6 x 2 x 32 x 32 x 2
+    # = 24576 per pair
     alg, issued, peak = bench.m2l_flops("fp64", 22, 10)
     assert alg == 42320 and issued == 30720 and peak == bench.FP64_PEAK
     alg, issued, peak = bench.m2l_flops("mixed", 22, 10)
-    assert alg == 42320 and issued == 368640 and peak == bench.MFMA_BF16_PEAK
+    assert alg == 42320 and issued == 245760 and peak == bench.MFMA_BF16_PEAK
+    # below p = 16 the mixed form runs the FP64 kernel
+    assert bench.m2l_flops("mixed", 15, 1) == bench.m2l_flops("fp64", 15, 1)
     # p = 15 fills one row tile and four k-steps exactly
     assert bench.m2l_flops("fp64", 15, 1)[1] == 2 * 16 * 16 * 2
     f = bench.m2l_fraction("fp64", 22, 10, 1.0)
