@@ -591,30 +591,46 @@ __device__ __forceinline__ double bperm_f64(int addr, double v)
     return __hiloint2double(hi, lo);
 }
 
-// The FP64 near field for a plan whose targets are its sources, laid out as
-// the mixed symmetric kernel: a neighbour pair {A, B} (A the lower cell id,
-// with at most kSymChunks chunks) is evaluated once, by A's items, for both
-// sides; the leaf itself, and pairs whose lower leaf is larger, one-sided.
-// An 8 x 8 lane tile: A's targets (all of a leaf of up to kWide = 96, else
-// a chunk of 64) in LDS in blocks of eight rows,
-// eight of a cell's sources per round in the columns (absolute coordinates,
-// loaded a round ahead), so every separation, and with it the sign of dy, is
-// exact.  Sums are FP64 throughout: A's in the lanes, reduced over the
-// columns at the end; B's reduced over the rows each round and stored per
-// (point, lower neighbour, its chunk) in bside64 for L2P.
+// The FP64 near field for a plan whose targets are its sources: a neighbour
+// pair {A, B} (A the lower cell id, with at most kSymChunks chunks) is
+// evaluated once, by A's items, for both sides; the leaf itself, and pairs
+// whose lower leaf is larger, one-sided.  An 8 x 8 lane tile: A's targets
+// (all of a leaf of up to kWide = 96, else a chunk of 64) in LDS in blocks
+// of eight rows, eight sources per round in the columns (absolute
+// coordinates, loaded a round ahead), so every separation, and with it the
+// sign of dy, is exact.  The item runs two loops: the leaf's own sources
+// (one side, zero separations skipped), then the sources of its other
+// neighbour cells as one concatenated sequence, so a round's eight columns
+// may come from two cells and only the sequence's last round is padded.
+// Each column keeps a cursor (cell, position) into the sequence.  Sums are
+// FP64 throughout: A's in the lanes, reduced over the columns at the end;
+// each round's second-side sums reduced over the rows and stored per
+// (point, lower neighbour, its chunk) in bside64 for L2P (columns of a cell
+// taken one-sided store nothing).
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_near_fp64_sym(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
-    __shared__ int32_t cbeg[kNearSlots], cend[kNearSlots], cslot[kNearSlots];
-    __shared__ int8_t cmode[kNearSlots];
+    // The item's other neighbour cells in sequence order, per cell {end in
+    // the sequence, first source minus start, second-side offset in bside64
+    // minus start, whether it has one (else this item takes the cell
+    // one-sided)}.
+    __shared__ int4 cinfo[kNearSlots];
     __shared__ double2 sxy[kWide];   // A's targets: coordinates
     __shared__ double sau[kWide];    // and strengths
+    // A's sums of the target blocks past the first kRegBlocks, per lane, in
+    // LDS (each read and written once per round by its own lane): with few
+    // sums in registers the kernel needs 146 VGPRs without spills, three
+    // waves per SIMD, and leaves register room for other kernels' waves.
+    constexpr int kRegBlocks = 2;
+    __shared__ double2 sacc[kWide / 8 - kRegBlocks][64];
     const int lane = threadIdx.x, row = lane >> 3, col = lane & 7;
     // ds_bpermute byte addresses of lane ^ 1, 2, 4 (columns) and ^ 8, 16, 32 (rows)
     const int perm1 = (lane ^ 1) << 2, perm2 = (lane ^ 2) << 2, perm4 = (lane ^ 4) << 2;
     const int perm8 = (lane ^ 8) << 2, perm16 = (lane ^ 16) << 2, perm32 = (lane ^ 32) << 2;
+    static_assert(kNearSlots <= 16, "neighbour lists scanned within 16 lanes");
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
-        const int e = batch_entry(bm, item);
-        const EvalJob &J = jobs[bm.job[e]];
+        // (the entry and its job are the same in every lane: scalar)
+        const int e = uniform(batch_entry(bm, item));
+        const EvalJob &J = jobs[uniform(bm.job[e])];
         const int64_t it = item - bm.pre[e];
         if (it >= J.counts[0]) continue;
         const int32_t li = uniform(J.work_near[2 * it]), st = uniform(J.work_near[2 * it + 1]);
@@ -634,88 +650,145 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         for (int q = lane; q < kWide; q += 64) {
             // Padding targets: zero strength, far from every source and from
             // the padding source, so no separation in the tile is zero (the
-            // symmetric rounds have no zero-separation guard, and a zero
+            // neighbour rounds have no zero-separation guard, and a zero
             // there would turn a padding row's 0 x log 0 into a NaN in the
-            // B-side sums).
+            // second-side sums).
             const bool ok = q < m;
             sxy[q] = make_double2(ok ? J.tx[st + q] : -1e100, ok ? J.ty[st + q] : -1e100);
             sau[q] = ok ? J.su[st + q] : 0.0;
         }
-        if (lane < nw) {
+        // Lane k (1 <= k < nw) classifies neighbour slot k: its sources
+        // (none if the other leaf's items take the pair for both sides) and,
+        // if this item takes both sides, this leaf's slot in the other
+        // leaf's list, which names the second-side row.
+        int32_t b0 = 0, cnt = 0, slot = -1;
+        if (lane > 0 && lane < nw) {
             const int32_t c = J.near[li * nw + lane];
-            int32_t b0 = 0, e0 = 0, slot = 0;
-            int8_t mode = kCellSkip;
             if (c >= 0) {
                 b0 = J.sb[c];
-                e0 = J.se[c];
-                mode = kCellOne;
-                if (lane > 0 && c > gid && own_sym) {
-                    const int64_t lb = c - J.leaf_off;
-                    int k2 = 1;
-                    while (k2 < nw && J.near[lb * nw + k2] != (int32_t)gid) ++k2;
-                    if (k2 < nw) {
-                        mode = kCellSym;
-                        slot = (k2 - 1) * kSymChunks + chunk;
-                    }
-                } else if (lane > 0 && c < gid && sym_chunks(e0 - b0, kWide) <= kSymChunks) {
-                    mode = kCellSkip;
+                cnt = J.se[c] - b0;
+                if (c > gid && own_sym) {
+                    const int32_t *lc = J.near + (c - J.leaf_off) * nw;
+                    int k2 = nw;
+#pragma unroll
+                    for (int k = kNearSlots - 1; k >= 1; --k)   // independent loads
+                        if (k < nw && lc[k] == (int32_t)gid) k2 = k;
+                    if (k2 < nw) slot = (k2 - 1) * kSymChunks + chunk;
+                } else if (c < gid && sym_chunks(cnt, kWide) <= kSymChunks) {
+                    cnt = 0;
                 }
             }
-            if (mode == kCellSkip) e0 = b0;
-            cbeg[lane] = b0;
-            cend[lane] = e0;
-            cslot[lane] = slot;
-            cmode[lane] = mode;
         }
+        int32_t incl = cnt;   // inclusive prefix over lanes 0..15
+#pragma unroll
+        for (int d = 1; d < 16; d <<= 1) {
+            const int32_t v = __shfl_up(incl, d, 16);
+            if ((lane & 15) >= d) incl += v;
+        }
+        const uint64_t taken = __ballot(cnt > 0);
+        const int nc = __popcll(taken);
+        const int32_t total = uniform(__shfl(incl, 15));
+        if (cnt > 0) {
+            // second-side offsets fit 32 bits: the plan keeps
+            // (near width - 1) kSymChunks n_tgt below 2^31
+            const int32_t start = incl - cnt, base = b0 - start;
+            const int32_t row = slot >= 0 ? (int32_t)((int64_t)slot * J.n_tgt) + base : 0;
+            cinfo[__popcll(taken & ((1ull << lane) - 1))] = make_int4(incl, base, row, slot >= 0);
+        }
+        const int32_t c0 = uniform(J.near[li * nw]);   // slot 0: the leaf itself
+        const int32_t sb0 = c0 >= 0 ? uniform(J.sb[c0]) : 0, se0 = c0 >= 0 ? uniform(J.se[c0]) : 0;
         __syncthreads();
 
         struct Src {
             double x, y, w;
-            bool ok;
         };
-        auto fetch = [&](int k, int32_t b) {
+        auto load = [&](int32_t i) {
             Src r;
-            const int kk = k < nw ? k : 0;
-            const int32_t i = b + col;
-            r.ok = k < nw && i < cend[kk];
-            const int32_t ic = r.ok ? i : 0;
-            r.x = gload(J.sx, ic);
-            r.y = gload(J.sy, ic);
-            r.w = gload((const double *)J.su, ic);
+            r.x = gload(J.sx, i);
+            r.y = gload(J.sy, i);
+            r.w = gload((const double *)J.su, i);
             return r;
-        };
-        auto next_cell = [&](int k) {
-            while (k < nw && uniform(cbeg[k]) >= uniform(cend[k])) ++k;
-            return k;
         };
         // The item's rounds for NB target blocks (dispatched once per item,
         // so the accumulators stay in place from round to round).
         auto item_rounds = [&](auto nb_const) {
             constexpr int NB = decltype(nb_const)::value;
-            double ar[NB], ai[NB];
+            constexpr int NR = NB < kRegBlocks ? NB : kRegBlocks;   // blocks summed in registers
+            double ar[NR], ai[NR];
 #pragma unroll
-            for (int blk = 0; blk < NB; ++blk) ar[blk] = ai[blk] = 0.0;
-            int k = next_cell(0);
-            int32_t b = k < nw ? uniform(cbeg[k]) : 0;
-            Src nxt = fetch(k, b);
-            while (k < nw) {
-                const int32_t ce = uniform(cend[k]);
-                int k2 = k;
-                int32_t b2 = b + 8;
-                if (b2 >= ce) {
-                    k2 = next_cell(k + 1);
-                    b2 = k2 < nw ? uniform(cbeg[k2]) : 0;
+            for (int blk = 0; blk < NR; ++blk) ar[blk] = ai[blk] = 0.0;
+#pragma unroll
+            for (int blk = NR; blk < NB; ++blk) sacc[blk - NR][lane] = make_double2(0.0, 0.0);
+            // A's sum of block blk (a constant after unrolling) += w (lg, at)
+            auto add_a = [&](int blk, double w, double lg, double at) {
+                if (blk < NR) {
+                    const int b = blk < NR ? blk : 0;
+                    ar[b] = fma(w, lg, ar[b]);
+                    ai[b] = fma(w, at, ai[b]);
+                } else {
+                    double2 &v = sacc[blk < NR ? 0 : blk - NR][lane];
+                    const double2 o = v;
+                    v = make_double2(fma(w, lg, o.x), fma(w, at, o.y));
                 }
-                // padding: zero strength, far away
-                const double sx = nxt.ok ? nxt.x : 1e100, sy = nxt.ok ? nxt.y : 1e100;
-                const double su = nxt.ok ? nxt.w : 0.0;
-                nxt = fetch(k2, b2);
-                // The targets are read from LDS every round (an opaque copy of
-                // the row index keeps the reads in the loop): holding twelve
-                // blocks' coordinates and strengths in registers would spill.
-                int qrow = row;
-                asm volatile("" : "+v"(qrow));
-                if (uniform(cmode[k]) == kCellSym) {
+            };
+            // The leaf's own sources, one side; a zero separation (the point
+            // itself, or an equal point) is skipped.  Padding columns read
+            // source 0 with zero strength.
+            {
+                int32_t b = sb0;
+                bool ok = b + col < se0;
+                Src nxt = load(ok ? b + col : 0);
+                while (b < se0) {
+                    const double sx = nxt.x, sy = nxt.y, su = ok ? nxt.w : 0.0;
+                    b += 8;
+                    ok = b + col < se0;
+                    nxt = load(ok ? b + col : 0);
+                    // The targets are read from LDS every round (an opaque
+                    // copy of the row index keeps the reads in the loop):
+                    // holding twelve blocks' coordinates and strengths in
+                    // registers would spill.
+                    int qrow = row;
+                    asm volatile("" : "+v"(qrow));
+#pragma unroll
+                    for (int blk = 0; blk < NB; ++blk) {
+                        const int q = 8 * blk + qrow;
+                        const double2 t = sxy[q];
+                        const double dx = t.x - sx, dy = t.y - sy;
+                        const double r2 = fma(dx, dx, dy * dy);
+                        const bool live = r2 > 0.0;
+                        double lg, at;
+                        ln_atan2_f64(live ? r2 : 1.0, dy, live ? dx : 1.0, lg, at);
+                        add_a(blk, live ? su : 0.0, lg, at);
+                    }
+                }
+            }
+            // The other neighbours' sources, both sides where the cell has a
+            // second-side slot.  Each column keeps the sequence cell j of its
+            // source; the cell's record gives the source index and the
+            // second-side offset of a sequence position.
+            if (total > 0) {
+                int j = 0;
+                auto locate = [&](int32_t p) {
+                    while (p >= cinfo[j].x && j + 1 < nc) ++j;
+                    return cinfo[j];
+                };
+                int32_t p = col;
+                int4 c = locate(p);
+                bool ok = p < total;
+                int32_t dst = ok && c.w ? c.z + p : -1;   // the column's second-side sum
+                Src nxt = load(ok ? c.y + p : 0);
+                for (int32_t P = 0; P < total; P += 8) {
+                    // padding: zero strength, far away
+                    const double sx = ok ? nxt.x : 1e100, sy = ok ? nxt.y : 1e100;
+                    const double su = ok ? nxt.w : 0.0;
+                    const int32_t out = dst;
+                    p = P + 8 + col;
+                    c = locate(p);
+                    ok = p < total;
+                    dst = ok && c.w ? c.z + p : -1;
+                    nxt = load(ok ? c.y + p : 0);
+                    int qrow = row;
+                    asm volatile("" : "+v"(qrow));
                     double br = 0.0, bi = 0.0;
 #pragma unroll
                     for (int blk = 0; blk < NB; ++blk) {
@@ -724,8 +797,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                         const double dx = t.x - sx, dy = t.y - sy, u = sau[q];
                         double lg, at, atr;
                         ln_atan2_pair_f64(fma(dx, dx, dy * dy), dy, dx, lg, at, atr);
-                        ar[blk] = fma(su, lg, ar[blk]);
-                        ai[blk] = fma(su, at, ai[blk]);
+                        add_a(blk, su, lg, at);
                         br = fma(u, lg, br);
                         bi = fma(u, atr, bi);
                     }
@@ -737,33 +809,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                     bi += bperm_f64(perm16, bi);
                     br += bperm_f64(perm32, br);
                     bi += bperm_f64(perm32, bi);
-                    const int32_t i = b + col;
-                    if (row == 0 && i < ce)
-                        J.bside64[(int64_t)uniform(cslot[k]) * J.n_tgt + i] = make_double2(0.5 * br, bi);
-                } else {
-                    // one side; a zero separation (the point itself, or an
-                    // equal point) is skipped
-#pragma unroll
-                    for (int blk = 0; blk < NB; ++blk) {
-                        const int q = 8 * blk + qrow;
-                        const double2 t = sxy[q];
-                        const double dx = t.x - sx, dy = t.y - sy;
-                        const double r2 = fma(dx, dx, dy * dy);
-                        const bool live = r2 > 0.0;
-                        double lg, at;
-                        ln_atan2_f64(live ? r2 : 1.0, dy, live ? dx : 1.0, lg, at);
-                        const double w = live ? su : 0.0;
-                        ar[blk] = fma(w, lg, ar[blk]);
-                        ai[blk] = fma(w, at, ai[blk]);
-                    }
+                    if (row == 0 && out >= 0) J.bside64[(uint32_t)out] = make_double2(0.5 * br, bi);
                 }
-                k = k2;
-                b = b2;
             }
             // A's sums over the columns; column 0 writes
 #pragma unroll
             for (int blk = 0; blk < NB; ++blk) {
-                double vr = ar[blk], vi = ai[blk];
+                double vr, vi;
+                if (blk < NR) {
+                    vr = ar[blk < NR ? blk : 0];
+                    vi = ai[blk < NR ? blk : 0];
+                } else {
+                    const double2 v = sacc[blk < NR ? 0 : blk - NR][lane];
+                    vr = v.x;
+                    vi = v.y;
+                }
                 vr += bperm_f64(perm1, vr);
                 vi += bperm_f64(perm1, vi);
                 vr += bperm_f64(perm2, vr);

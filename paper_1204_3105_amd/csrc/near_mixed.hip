@@ -426,8 +426,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void
     const int perm16 = (lane ^ 16) << 2, perm32 = (lane ^ 32) << 2;   // ds_bpermute byte addresses
     const float half_ln2 = 0.34657359027997264f;
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
-        const int e = batch_entry(bm, item);
-        const EvalJob &J = jobs[bm.job[e]];
+        const int e = uniform(batch_entry(bm, item));
+        const EvalJob &J = jobs[uniform(bm.job[e])];
         const int64_t it = item - bm.pre[e];
         if (it >= J.counts[0]) continue;
         // (item values are the same in every lane: kept in scalar registers

@@ -594,6 +594,11 @@ static fmm_status depth_by_cost(PlanImpl *P, int tiling, const BBox &bb, int64_t
     return FMM_OK;
 }
 
+// The symmetric near field addresses its second-side sums by 32-bit offsets
+// ((slot) n + point); above that many points the plan takes the one-sided
+// kernels.
+static bool sym_offsets_fit(int nw, int64_t n) { return (int64_t)(nw - 1) * kSymChunks * n < ((int64_t)1 << 31); }
+
 static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t n_src,
                              const double *tgt, int64_t n_tgt, double eps, const fmm_options &o)
 {
@@ -791,7 +796,7 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
             P->txl = take<float>(P, M, &err);
             P->tyl = take<float>(P, M, &err);
         }
-        if (same && N > 0)
+        if (same && N > 0 && sym_offsets_fit(nw, N))
             P->bside = take<float2>(P, (int64_t)(nw - 1) * kSymChunks * N, &err);
         if (err) return fail(FMM_E_NOMEM, "device allocation failed (mixed)");
         launch_local_coords(P->sx, P->sy, P->skey, N, g, P->lev, P->dense, P->cx, P->cy, P->sxl,
@@ -821,7 +826,7 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     }
     P->phi_int = take<double>(P, 2 * std::max<int64_t>(M, 1), &err);
     P->nsum = take<double>(P, 2 * std::max<int64_t>(M, 1), &err);
-    if (P->precision != FMM_PREC_MIXED && same && N > 0)
+    if (P->precision != FMM_PREC_MIXED && same && N > 0 && sym_offsets_fit(nw, N))
         P->bside64 = take<double2>(P, (int64_t)(nw - 1) * kSymChunks * N, &err);
     if (P->lev[g.L].n == 0 || M == 0) FMM_HIP_CHECK(hipMemsetAsync(P->counts, 0, sizeof(int32_t), s));
     P->job_dev = take<EvalJob>(P, 1, &err);
