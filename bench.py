@@ -40,8 +40,8 @@ LANE_OPS = 256 * 4 * 16 * 2.4e9
 # symmetric figures are the per-evaluation slopes printed by
 # paper_1204_3105_amd/csrc/count_valu.py (per-round work excluded).
 VALU_PER_PAIR = {"fp64": 104.0, "mixed": 31.0}
-VALU_SYM_EVAL = {"mixed": 30.5, "fp64": 83.2}
-VALU_SYM_ONE_SIDED = {"mixed": 30.0, "fp64": 82.0}
+VALU_SYM_EVAL = {"mixed": 30.5, "fp64": 80.2}
+VALU_SYM_ONE_SIDED = {"mixed": 30.0, "fp64": 79.0}
 SYM_CHUNKS = 2   # a leaf of at most 2 x 64 targets evaluates its pairs with higher leaves for both sides
 
 

@@ -177,7 +177,7 @@ void launch_bbox_final(const double *partial, int nparts, double *out4, int32_t 
 // and the occupied-cell counts (out[0..2], accumulated); a short device copy.
 void launch_depth_hist(const GeoParams &g, const double *pts, int64_t n, int64_t stride, uint32_t *hist,
                        hipStream_t s);
-void launch_depth_stats(const uint32_t *hs, const uint32_t *ht, int64_t ncells, int64_t span,
+void launch_depth_stats(const uint32_t *hs, const uint32_t *ht, int64_t ncells0, int base, int nl,
                         unsigned long long *out, hipStream_t s);
 void launch_copy_u64(const unsigned long long *a, int n, unsigned long long *b, hipStream_t s);
 // Also clears zero[0 .. n_zero).

@@ -277,34 +277,50 @@ __global__ void k_depth_hist(GeoParams g, const double *__restrict__ pts, int64_
     if (k >= 0) atomicAdd(&hist[k], 1u);
 }
 
-// For one coarser level: cell c covers the trial-level keys [c span, (c+1)
-// span) (keys are digit prefixes).  Accumulates sum_c s_c t_c, the source-
-// and the target-occupied cell counts (64-bit integer sums: exact in any
-// order).  A bounded grid strides over the cells, so the three counters take
-// few atomics.
+// All candidate levels in one pass over the trial-level histogram: thread
+// per cell of the coarsest candidate level L0, which covers base^(nl-1)
+// trial-level keys (keys are digit prefixes); candidate level L0 + k groups
+// them base^(nl-1-k) at a time.  Accumulates per level sum_c s_c t_c and the
+// source- and target-occupied cell counts (64-bit integer sums: exact in any
+// order) over a bounded grid, three atomics per level and block.
+constexpr int kDepthLevels = 3;
 __global__ __launch_bounds__(256) void k_depth_stats(const uint32_t *__restrict__ hs, const uint32_t *__restrict__ ht,
-                                                      int64_t ncells, int64_t span, unsigned long long *__restrict__ out)
+                                                      int64_t ncells0, int base, int nl,
+                                                      unsigned long long *__restrict__ out)
 {
-    __shared__ unsigned long long part[3][4];
-    unsigned long long v[3] = {0, 0, 0};
-    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncells;
-         c += (int64_t)gridDim.x * blockDim.x) {
-        unsigned long long s = 0, t = 0;
-        for (int64_t j = c * span; j < (c + 1) * span; ++j) {
-            s += hs[j];
-            t += ht[j];
-        }
-        v[0] += s * t;
-        v[1] += s ? 1 : 0;
-        v[2] += t ? 1 : 0;
+    __shared__ unsigned long long part[3 * kDepthLevels][4];
+    int64_t span = 1;
+    int gsz[kDepthLevels];
+    for (int k = nl - 1; k >= 0; --k) {
+        gsz[k] = (int)span;
+        span *= base;
     }
-    // block sums first: three atomics per block
-    for (int q = 0; q < 3; ++q) {
+    span /= base;   // base^(nl-1)
+    unsigned long long v[3 * kDepthLevels] = {};
+    for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < ncells0;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        unsigned long long gs[kDepthLevels] = {}, gt[kDepthLevels] = {};
+        for (int64_t j = 0; j < span; ++j) {
+            const unsigned long long s = hs[c * span + j], t = ht[c * span + j];
+            for (int k = 0; k < nl; ++k) {
+                gs[k] += s;
+                gt[k] += t;
+                if ((j + 1) % gsz[k] == 0) {
+                    v[3 * k] += gs[k] * gt[k];
+                    v[3 * k + 1] += gs[k] ? 1 : 0;
+                    v[3 * k + 2] += gt[k] ? 1 : 0;
+                    gs[k] = gt[k] = 0;
+                }
+            }
+        }
+    }
+    // block sums first: three atomics per level and block
+    for (int q = 0; q < 3 * nl; ++q) {
         for (int o = 32; o > 0; o >>= 1) v[q] += __shfl_xor(v[q], o);
         if ((threadIdx.x & 63) == 0) part[q][threadIdx.x >> 6] = v[q];
     }
     __syncthreads();
-    if (threadIdx.x < 3) {
+    if (threadIdx.x < 3 * nl) {
         unsigned long long a = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) a += part[threadIdx.x][w];
         if (a) atomicAdd(&out[threadIdx.x], a);
@@ -324,12 +340,12 @@ void launch_depth_hist(const GeoParams &g, const double *pts, int64_t n, int64_t
     hipLaunchKernelGGL(k_depth_hist, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, g, pts, n, stride, hist);
 }
 
-void launch_depth_stats(const uint32_t *hs, const uint32_t *ht, int64_t ncells, int64_t span,
+void launch_depth_stats(const uint32_t *hs, const uint32_t *ht, int64_t ncells0, int base, int nl,
                         unsigned long long *out, hipStream_t s)
 {
-    const int64_t blocks = std::min<int64_t>((ncells + 255) / 256, 1024);
-    hipLaunchKernelGGL(k_depth_stats, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s, hs, ht, ncells,
-                       span, out);
+    const int64_t blocks = std::min<int64_t>((ncells0 + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_depth_stats, dim3((unsigned)std::max<int64_t>(blocks, 1)), dim3(256), 0, s, hs, ht, ncells0,
+                       base, nl, out);
 }
 
 void launch_copy_u64(const unsigned long long *a, int n, unsigned long long *b, hipStream_t s)

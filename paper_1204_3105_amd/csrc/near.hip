@@ -25,6 +25,9 @@ static constexpr double kPi2Hi = 1.5707963267948966, kPi2Lo = 6.123233995736766e
 static constexpr double kPi6Hi = 0.5235987755982989, kPi6Lo = -5.360408832255455e-17;
 static constexpr double kInvSqrt3 = 0.5773502691896257, kTanPi12 = 0.2679491924311227;
 static constexpr double kSqrtHalf = 0.7071067811865476;
+// ln(c sqrt 2) for c = kSqrtHalf (what the rounding of c leaves of
+// ln c + ln(2) / 2).
+static constexpr double kLnC2 = 6.835808657661923e-17;
 // Series remainders on the reduced intervals, weighted minimax fits from
 // gen_f64_poly.py: ln m = 2s (1 + z P(z)) with z = s^2 <= (3 - 2 sqrt2)^2
 // (|z dP| <= 1.3e-18), atan t = t (1 + w Q(w)) with w = t^2 <= (2 - sqrt3)^2
@@ -110,34 +113,35 @@ __device__ __forceinline__ double atan2_f64(double y, double x)
 
 
 // ln(r2) and atan2(y, x) together, as ln_f64 and atan2_f64 but with one
-// reciprocal for both divisions: with D = (m + 1) den, R = 1/D (hardware
-// reciprocal, two Newton steps), s = (m - 1) den R and t = num (m + 1) R;
-// each quotient is within a few ulp, far below what the FP64 near field needs.
+// reciprocal for both divisions.  The logarithm's reduction is shifted so
+// that frexp's mantissa m in [1/2, 1) needs no adjustment: with c = sqrt(1/2)
+// (rounded), s = (m - c)/(m + c) covers the same interval |s| <= 3 - 2 sqrt2
+// as (m' - 1)/(m' + 1) for m' in [sqrt(1/2), sqrt2), and ln m = ln c +
+// 2 atanh(s).  With D = (m + c) den, R = 1/D (hardware reciprocal, two Newton
+// steps), s = (m - c) den R and t = num (m + c) R; each quotient is within a
+// few ulp, far below what the FP64 near field needs.
 __device__ __forceinline__ void ln_atan2_f64(double r2, double y, double x, double &lnr2, double &at)
 {
     int e;
-    double m = frexp(r2, &e);
-    const bool lo = m < kSqrtHalf;
-    m = lo ? 2.0 * m : m;
-    e = lo ? e - 1 : e;
+    const double m = frexp(r2, &e);   // m in [1/2, 1)
     const double ax = fabs(x), ay = fabs(y);
     const double mn = fmin(ax, ay), mx = fmax(ax, ay);
     const bool red = mn > kTanPi12 * mx;
     const double num = red ? fma(-kInvSqrt3, mx, mn) : mn;
     const double den = red ? fma(kInvSqrt3, mn, mx) : mx;
-    const double mp1 = m + 1.0;
-    const double D = mp1 * den;
+    const double mpc = m + kSqrtHalf;
+    const double D = mpc * den;
     double R = __builtin_amdgcn_rcp(D);
     R = fma(R, fma(-D, R, 1.0), R);
     R = fma(R, fma(-D, R, 1.0), R);
-    const double s = ((m - 1.0) * den) * R;
-    const double t = (num * mp1) * R;
-    // ln r2 = e ln 2 + 2 atanh(s)
+    const double s = ((m - kSqrtHalf) * den) * R;   // m - c is exact
+    const double t = (num * mpc) * R;
+    // ln r2 = (e - 1/2) ln 2 + ln(c sqrt 2) + 2 atanh(s), s = (m - c)/(m + c)
     const double z = s * s;
     const double p = ln_poly(z);
     const double lm = 2.0 * s + 2.0 * s * (z * p);
-    const double de = (double)e;
-    lnr2 = fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
+    const double de = (double)e - 0.5;
+    lnr2 = fma(de, kLn2Hi, fma(de, kLn2Lo, lm + kLnC2));
     // atan t, then the octant
     const double w = t * t;
     const double q = atan_poly(w);
@@ -550,27 +554,24 @@ __device__ __forceinline__ void ln_atan2_pair_f64(double r2, double y, double x,
                                                   double &atr)
 {
     int e;
-    double m = frexp(r2, &e);
-    const bool lo = m < kSqrtHalf;
-    m = lo ? 2.0 * m : m;
-    e = lo ? e - 1 : e;
+    const double m = frexp(r2, &e);   // m in [1/2, 1)
     const double ax = fabs(x), ay = fabs(y);
     const double mn = fmin(ax, ay), mx = fmax(ax, ay);
     const bool red = mn > kTanPi12 * mx;
     const double num = red ? fma(-kInvSqrt3, mx, mn) : mn;
     const double den = red ? fma(kInvSqrt3, mn, mx) : mx;
-    const double mp1 = m + 1.0;
-    const double D = mp1 * den;
+    const double mpc = m + kSqrtHalf;
+    const double D = mpc * den;
     double R = __builtin_amdgcn_rcp(D);
     R = fma(R, fma(-D, R, 1.0), R);
     R = fma(R, fma(-D, R, 1.0), R);
-    const double s = ((m - 1.0) * den) * R;
-    const double t = (num * mp1) * R;
+    const double s = ((m - kSqrtHalf) * den) * R;
+    const double t = (num * mpc) * R;
     const double z = s * s;
     const double p = ln_poly(z);
     const double lm = 2.0 * s + 2.0 * s * (z * p);
-    const double de = (double)e;
-    lnr2 = fma(de, kLn2Hi, fma(de, kLn2Lo, lm));
+    const double de = (double)e - 0.5;
+    lnr2 = fma(de, kLn2Hi, fma(de, kLn2Lo, lm + kLnC2));
     const double w = t * t;
     const double q = atan_poly(w);
     double a = fma(t * w, q, t);

@@ -415,7 +415,7 @@ __device__ __forceinline__ float add_dpp(float v)
     return v + __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
 
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_near_mixed_sym(const EvalJob *__restrict__ jobs, BatchMap bm)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_near_mixed_sym(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
     __shared__ int32_t cbeg[kNearSlots], cend[kNearSlots], cslot[kNearSlots];
     __shared__ float cdx[kNearSlots], cdy[kNearSlots];

@@ -563,10 +563,9 @@ static fmm_status depth_by_cost(PlanImpl *P, int tiling, const BBox &bb, int64_t
     if (e == hipSuccess) {
         launch_depth_hist(gc, dsrc, N, ms, hs, s);
         if (!same) launch_depth_hist(gc, dtgt, M, mt, ht, s);
-        int64_t cells = 1, span = K;
-        for (int l = 0; l < L0; ++l) cells *= base, span /= base;
-        for (int l = L0; l <= Lc; ++l, cells *= base, span /= base)
-            launch_depth_stats(hs, ht, cells, span, acc + 3 * (l - L0), s);
+        int64_t cells0 = 1;
+        for (int l = 0; l < L0; ++l) cells0 *= base;
+        launch_depth_stats(hs, ht, cells0, base, nl, acc, s);
         launch_copy_u64(acc, 3 * nl, (unsigned long long *)rb->dev, s);
         e = hipGetLastError();
     }
