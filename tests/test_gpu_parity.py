@@ -47,7 +47,11 @@ def level_keys(keys, tiling, L, l):
     return keys >> (2 * (L - l))
 
 
-def check_tree(F, orc, plan, w, tiling):
+def check_tree(F, orc, plan, w, tiling, list_sample=None):
+    """Keys, permutations, cells, occupancy and ranges of every level
+    bit-exact against the oracle; E4 lists of the target cells of every
+    level >= 1 and near lists of the leaves against the oracle's, for all
+    target cells or, with list_sample, a seeded sample of that many per level."""
     g, inf = geom_of(orc, plan, tiling)
     L = inf["lmax"]
     ex = plan.export_points()
@@ -79,18 +83,21 @@ def check_tree(F, orc, plan, w, tiling):
         assert np.array_equal(lv["src_range"], src_range), ("src ranges", l)
         assert np.array_equal(lv["tgt_range"], tgt_range), ("tgt ranges", l)
         # E4 lists of target cells, restricted to source-occupied cells.
+        pick = np.flatnonzero((occ & 2) > 0)
+        if list_sample is not None and len(pick) > list_sample:
+            pick = np.sort(np.random.default_rng(l).choice(pick, list_sample, replace=False))
         if l >= 1:
-            tc = cells[(occ & 2) > 0]
+            tc = cells[pick]
             out, cnt = orc.e4_many(g, tc, l)
-            rows = lv["e4"][(occ & 2) > 0]
+            rows = lv["e4"][pick]
             for i in range(len(tc)):
                 want = np.sort(out[i, : cnt[i]][np.isin(out[i, : cnt[i]], us)])
                 got = rows[i][rows[i] >= 0]
                 assert np.array_equal(got, want), ("e4", l, tc[i])
         if l == L:
-            tc = cells[(occ & 2) > 0]
+            tc = cells[pick]
             out, cnt = orc.neighbors_many(g, tc, l)
-            rows = lv["near"][(occ & 2) > 0]
+            rows = lv["near"][pick]
             for i in range(len(tc)):
                 nb = np.concatenate([out[i, : cnt[i]], [tc[i]]])
                 want = np.sort(nb[np.isin(nb, us)])
