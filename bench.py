@@ -45,11 +45,15 @@ VALU_SYM_ONE_SIDED = {"mixed": 30.0, "fp64": 79.0}
 SYM_CHUNKS = 2   # a leaf of at most 2 x 64 targets evaluates its pairs with higher leaves for both sides
 
 
-def near_valu_ops(lv, prec, same, n_pairs):
-    """VALU lane-operations of one near-field launch, from the plan's leaf
-    level (point counts and neighbour lists)."""
+def near_work(lv, same, n_pairs):
+    """Pair evaluations of one near-field launch, from the plan's leaf level
+    (point counts and neighbour lists): (symmetric evaluations, one-sided
+    evaluations).  With targets = sources a neighbour pair of leaves whose
+    lower leaf has at most SYM_CHUNKS chunks is evaluated once for both
+    sides; the leaf itself and the other pairs one-sided; otherwise every
+    pair is one-sided."""
     if not same:
-        return n_pairs * VALU_PER_PAIR[prec]
+        return 0.0, float(n_pairs)
     keys = lv["keys"]
     n = (lv["src_range"][:, 1] - lv["src_range"][:, 0]).astype(np.float64)
     near = lv["near"]
@@ -62,8 +66,16 @@ def near_valu_ops(lv, prec, same, n_pairs):
     sym = np.ceil(n[a] / 64.0) <= SYM_CHUNKS
     prod = n[a] * n[b]
     self_pairs = float(np.sum(n * n))
-    return (VALU_SYM_EVAL[prec] * float(np.sum(prod[sym]))
-            + VALU_SYM_ONE_SIDED[prec] * (self_pairs + 2.0 * float(np.sum(prod[~sym]))))
+    return float(np.sum(prod[sym])), self_pairs + 2.0 * float(np.sum(prod[~sym]))
+
+
+def near_valu_ops(lv, prec, same, n_pairs):
+    """VALU lane-operations of one near-field launch: its evaluations times
+    the per-evaluation instruction counts."""
+    if not same:
+        return n_pairs * VALU_PER_PAIR[prec]
+    sym, one = near_work(lv, same, n_pairs)
+    return VALU_SYM_EVAL[prec] * sym + VALU_SYM_ONE_SIDED[prec] * one
 
 
 HBM_PEAK = 8.0e12
@@ -133,6 +145,8 @@ def parse():
                     help="1: each stream's solves are issued by a host thread of its own")
     ap.add_argument("--near-stream", default="own", choices=["own", "side"],
                     help="near field on each solve's own stream (own) or beside its far field (side)")
+    ap.add_argument("--probe-rounds", type=int, default=2000,
+                    help="rounds of the pair-rate probe kernel (0 = skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one plain 512 MiB device copy first (HBM counter calibration)")
     return ap.parse_args()
@@ -202,6 +216,7 @@ def timed(F, torch, pts, u, tilings, eps, prec, leaf, steps, warmup, outs, n_str
     for t, plan in kept.items():
         inf = plan.info()
         lv = plan.export_level(inf["lmax"])
+        inf["near_evals"] = sum(near_work(lv, inf["targets_are_sources"], inf["n_near_pairs"]))
         inf["near_valu_ops"] = near_valu_ops(lv, inf["precision"], inf["targets_are_sources"],
                                              inf["n_near_pairs"])
         infos[t] = [inf]
@@ -291,6 +306,7 @@ def near_roofline(infos, tilings, prec):
     pair mix and the kernel's per-pair instruction count."""
     near_ms = np.mean([i["stage_ms"][3] for t in tilings for i in infos[t]])
     pairs = np.mean([i["n_near_pairs"] for t in tilings for i in infos[t]])
+    evals = np.mean([i["near_evals"] for t in tilings for i in infos[t]])
     ops = np.mean([i["near_valu_ops"] for t in tilings for i in infos[t]])
     ach = ops / (near_ms * 1e-3)
     sym = all(i["targets_are_sources"] for t in tilings for i in infos[t])
@@ -299,7 +315,7 @@ def near_roofline(infos, tilings, prec):
     return {"bound": "alu", "kernel": "near field (P2P), %s" % kname, "achieved": ach / 1e9,
             "peak": LANE_OPS / 1e9, "unit": "G VALU lane-op/s", "frac": ach / LANE_OPS, "traffic": traffic,
             "avg_launch_ms": float(near_ms), "pairs_per_launch": float(pairs),
-            "valu_ops_per_launch": float(ops),
+            "evals_per_launch": float(evals), "valu_ops_per_launch": float(ops),
             "valu_per_pair": ({"symmetric_eval": VALU_SYM_EVAL[prec],
                                "one_sided": VALU_SYM_ONE_SIDED[prec]}
                               if sym else VALU_PER_PAIR[prec])}
@@ -563,6 +579,17 @@ def main():
     value = len(tilings) * a.n * a.steps / wall
     print("bench: timed %.3f s -> %.4g targets/s (fp64)" % (wall, value), file=sys.stderr, flush=True)
     roofline = near_roofline(infos, tilings, "fp64")
+    # The pair function's own rate with its operands in registers: the
+    # ceiling the near-field kernel's evaluation rate is measured against.
+    probe = F.probe_pair_rate(a.probe_rounds) if a.probe_rounds > 0 else None
+    ceiling = None
+    if probe:
+        kev = roofline["evals_per_launch"] / (roofline["avg_launch_ms"] * 1e-3)
+        ceiling = {"probe_evals_per_s": probe, "kernel_evals_per_s": kev, "kernel_of_probe": kev / probe,
+                   "probe_valu_lane_ops_per_s_at_model_count": probe * VALU_SYM_EVAL["fp64"],
+                   "probe_of_peak_at_model_count": probe * VALU_SYM_EVAL["fp64"] / LANE_OPS}
+        print("bench: pair-rate probe %.4g evals/s, near kernel %.4g evals/s (%.2f of the probe)" % (
+            probe, kev, kev / probe), file=sys.stderr, flush=True)
 
     def per_tiling(infos):
         pt = {}
@@ -579,6 +606,7 @@ def main():
         return pt
 
     extra = {"per_tiling": per_tiling(infos), "m2l_mfma": m2l_mfma(infos, tilings, "fp64"),
+             "pair_rate_ceiling": ceiling,
              "errors": error_check(oracle, w, outs, infos, tilings, a.check)}
 
     if a.mixed:

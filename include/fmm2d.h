@@ -242,6 +242,20 @@ fmm_status fmm_direct(const double *src, int64_t n_src, const double *tgt, int64
 fmm_status fmm_direct_noalloc(const double *src, int64_t n_src, const double *tgt, int64_t n_tgt,
                               const double *u, double *phi, void *stream);
 
+/* Pair-evaluation ceiling of the FP64 near field (Sec. 2, eq. 2: the log
+ * kernel's terms): runs a probe kernel in which every lane evaluates the
+ * near field's FP64 pair function (ln r^2 and both arguments of the pair)
+ * for `rounds` rounds of eight independent pairs held in registers -- no
+ * loads, no reductions -- in one-wave blocks at the near field's occupancy,
+ * on `blocks` blocks (0: 3072, three waves on each of the GPU's 1024 SIMDs),
+ * and returns the measured evaluations per second in *evals_per_s.  The
+ * near-field kernel's own evaluation rate divided by this one measures its
+ * efficiency against what the chip sustains for this code.  Synchronous,
+ * on the current device, on a stream of its own; allocates 512 B per block.
+ * Errors: FMM_E_INVALID for rounds < 1, blocks < 0 or a null output;
+ * FMM_E_DEVICE on device failures. */
+fmm_status fmm_probe_pair_rate(int32_t rounds, int32_t blocks, double *evals_per_s);
+
 /* ------------------------------------------------------------------ serving
  * A request loop that admits independent solves by free device memory,
  * keeps their plans resident, and runs the same phase of every admitted

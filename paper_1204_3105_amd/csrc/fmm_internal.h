@@ -250,6 +250,8 @@ int64_t plan_bytes_estimate(int tiling, int64_t n_src, int64_t n_tgt, bool same,
 // Direct sum: slices of the sources per target block (direct_slices), with
 // partial sums in part (slices * n_tgt complex128; unused for one slice).
 int direct_slices(int64_t n_src, int64_t n_tgt);
+// FP64 pair-evaluation rate of k_pair_rate (evaluations per second); nonzero on failure.
+int probe_pair_rate(int rounds, int blocks, double *evals_per_s);
 void launch_direct(const double *src, int64_t n_src, const double *tgt, int64_t n_tgt, const double *u,
                    double *phi, double *part, int slices, hipStream_t s);
 int mixed_setup(Plan &P);

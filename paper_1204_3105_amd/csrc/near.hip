@@ -856,6 +856,61 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     }
 }
 
+// Issue-rate probe of the FP64 pair evaluation: every lane evaluates
+// ln_atan2_pair_f64 for `rounds` rounds of eight independent pairs whose
+// separations it steps in registers (no loads, no LDS, no second-side
+// reductions), summing the three results, which it stores so that no
+// evaluation is dropped.  One-wave blocks at three waves per SIMD, as the
+// near field runs: the rate it reaches is the pair-evaluation ceiling of
+// this code on the chip as it clocks under the load.
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_pair_rate(int rounds, double *out)
+{
+    const int lane = threadIdx.x;
+    double dx[8], dy[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        dx[j] = 0.37 + 0.011 * lane - 0.29 * j;
+        dy[j] = -0.21 + 0.005 * (blockIdx.x & 63) + 0.17 * j;
+    }
+    double sl = 0.0, sa = 0.0, sr = 0.0;
+    for (int r = 0; r < rounds; ++r) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            double lg, at, atr;
+            ln_atan2_pair_f64(fma(dx[j], dx[j], dy[j] * dy[j]), dy[j], dx[j], lg, at, atr);
+            sl += lg;
+            sa += at;
+            sr += atr;
+            dx[j] += 1e-3;
+        }
+    }
+    out[blockIdx.x * 64 + lane] = sl + sa + sr;
+}
+
+int probe_pair_rate(int rounds, int blocks, double *evals_per_s)
+{
+    double *out = nullptr;
+    hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+    int err = hipMalloc(&out, sizeof(double) * 64 * (size_t)blocks) != hipSuccess;
+    err = err || hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess;
+    err = err || hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess;
+    if (!err) {
+        hipLaunchKernelGGL(k_pair_rate, dim3(blocks), dim3(64), 0, s, 1, out);   // warm-up
+        hipEventRecord(a, s);
+        hipLaunchKernelGGL(k_pair_rate, dim3(blocks), dim3(64), 0, s, rounds, out);
+        hipEventRecord(b, s);
+        float ms = 0.0f;
+        err = hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess || ms <= 0.0f;
+        if (!err) *evals_per_s = 64.0 * blocks * 8.0 * rounds / (ms * 1e-3);
+    }
+    if (a) hipEventDestroy(a);
+    if (b) hipEventDestroy(b);
+    if (s) hipStreamDestroy(s);
+    if (out) hipFree(out);
+    return err;
+}
+
 void batch_near_fp64_sym(const EvalJob *jobs, const BatchMap &m, hipStream_t s)
 {
     if (m.n <= 0 || m.pre[m.n] <= 0) return;

@@ -942,6 +942,15 @@ fmm_status fmm_direct_noalloc(const double *src, int64_t n_src, const double *tg
     return FMM_OK;
 }
 
+fmm_status fmm_probe_pair_rate(int32_t rounds, int32_t blocks, double *evals_per_s)
+{
+    g_err.clear();
+    if (rounds < 1 || blocks < 0 || !evals_per_s) return fail(FMM_E_INVALID, "bad probe arguments");
+    if (probe_pair_rate(rounds, blocks ? blocks : 3072, evals_per_s))
+        return fail(FMM_E_DEVICE, "pair-rate probe failed");
+    return FMM_OK;
+}
+
 fmm_status fmm_plan(fmm_tiling tiling, const double *src, int64_t n_src, const double *tgt,
                     int64_t n_tgt, double eps, const fmm_options *opt, fmm_plan_t *out)
 {

@@ -67,7 +67,7 @@ EXPORTED = ["fmm_options_default", "fmm_plan", "fmm_eval", "fmm_plan_info_get",
             "fmm_plan_export_points", "fmm_plan_export_level", "fmm_plan_destroy",
             "fmm_last_error", "fmm_order_for_eps", "fmm_server_create", "fmm_submit",
             "fmm_poll", "fmm_server_drain", "fmm_server_destroy", "fmm_direct",
-            "fmm_eval_field", "fmm_direct_noalloc"]
+            "fmm_eval_field", "fmm_direct_noalloc", "fmm_probe_pair_rate"]
 
 _lib = None
 
@@ -117,6 +117,8 @@ def lib():
     L.fmm_direct.restype = C.c_int
     L.fmm_direct_noalloc.argtypes = [P, C.c_int64, P, C.c_int64, P, P, P]
     L.fmm_direct_noalloc.restype = C.c_int
+    L.fmm_probe_pair_rate.argtypes = [C.c_int32, C.c_int32, C.POINTER(C.c_double)]
+    L.fmm_probe_pair_rate.restype = C.c_int
     L.fmm_server_create.argtypes = [C.POINTER(ServerOptions), C.POINTER(P)]
     L.fmm_server_create.restype = C.c_int
     L.fmm_submit.argtypes = [P, C.POINTER(Request), C.POINTER(C.c_uint64)]
@@ -413,6 +415,16 @@ def direct_noalloc(src, tgt, u, out, stream=None):
                                 tgt.numel(), C.c_void_p(u.data_ptr()), C.c_void_p(out.data_ptr()),
                                 C.c_void_p(st.cuda_stream)))
     return out
+
+
+def probe_pair_rate(rounds: int = 2000, blocks: int = 0) -> float:
+    """fmm_probe_pair_rate: FP64 pair evaluations per second that the near
+    field's pair function reaches with its operands in registers (the
+    near-field kernel's ceiling on this chip)."""
+    L = lib()
+    r = C.c_double(0.0)
+    _check(L.fmm_probe_pair_rate(int(rounds), int(blocks), C.byref(r)))
+    return float(r.value)
 
 
 class Server:

@@ -82,9 +82,9 @@ def test_near_roofline_from_plan_infos():
     # two tilings, one launch each: VALU operations over the launch time
     # against the issue rate; traffic only from a committed counter summary
     # whose kernel source is unchanged
-    infos = {"quad": [{"stage_ms": [0, 0, 0, 0.5, 0], "n_near_pairs": 100, "near_valu_ops": 4e9,
+    infos = {"quad": [{"stage_ms": [0, 0, 0, 0.5, 0], "n_near_pairs": 100, "near_valu_ops": 4e9, "near_evals": 5e7,
                        "targets_are_sources": True}],
-             "tri": [{"stage_ms": [0, 0, 0, 1.5, 0], "n_near_pairs": 300, "near_valu_ops": 8e9,
+             "tri": [{"stage_ms": [0, 0, 0, 1.5, 0], "n_near_pairs": 300, "near_valu_ops": 8e9, "near_evals": 1e8,
                       "targets_are_sources": True}]}
     r = bench.near_roofline(infos, ["quad", "tri"], "fp64")
     assert r["kernel"].endswith("k_near_fp64_sym")
