@@ -218,6 +218,11 @@ void launch_local_coords(const double *x, const double *y, const uint32_t *key, 
                          const double *cx, const double *cy, float *xl, float *yl, hipStream_t s);
 void launch_near_items(const LevelInfo *lev, int L, const int32_t *tb, const int32_t *te,
                        int32_t *counts, hipStream_t s);
+// Items reordered by decreasing estimated cost into out (2 cap ints); keys,
+// vals (cap each) and tmp (radix_tmp_bytes(cap)) are scratch.
+void launch_near_items_order(int64_t leaf_off, int nw, int32_t cap, const int32_t *count, const int32_t *items,
+                             const int32_t *te, const int32_t *near, const int32_t *sb, const int32_t *se,
+                             uint32_t *keys, int32_t *vals, void *tmp, int32_t *out, hipStream_t s);
 void launch_near_items_fill(const LevelInfo *lev, int L, const int32_t *tb, const int32_t *te,
                             const int32_t *offs, int32_t *items, hipStream_t s);
 void launch_count_pairs(const LevelInfo *lev, int L, int e4w, int nw, const int32_t *e4,

@@ -778,6 +778,17 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
     launch_near_items(P->lev, g.L, P->tb, P->te, ncount, s);
     scan_exclusive(ncount, ncount, P->lev[g.L].n, P->counts + 0, scan_tmp, s);
     launch_near_items_fill(P->lev, g.L, P->tb, P->te, ncount, P->work_near, s);
+    if (P->lev[g.L].n > 0 && M > 0) {
+        // the items in decreasing order of estimated cost
+        uint32_t *ikeys = take<uint32_t>(P, items_cap, &err);
+        int32_t *ivals = take<int32_t>(P, items_cap, &err);
+        int32_t *sorted = take<int32_t>(P, 2 * items_cap, &err);
+        char *itmp = take<char>(P, (int64_t)radix_tmp_bytes(items_cap), &err);
+        if (err) return fail(FMM_E_NOMEM, "device allocation failed (near items)");
+        launch_near_items_order(P->lev[g.L].cell_off, nw, (int32_t)items_cap, P->counts + 0, P->work_near, P->te,
+                                P->near, P->sb, P->se, ikeys, ivals, itmp, sorted, s);
+        P->work_near = sorted;
+    }
     P->m2l_pm = m2l_pm_for(P->p);
     if (P->m2l_pm > 0 && g.L >= 1) {
         double *tab = take<double>(P, (int64_t)m2l_table_doubles(*P, P->m2l_pm), &err);

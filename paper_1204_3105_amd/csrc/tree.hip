@@ -590,6 +590,58 @@ void launch_near_items_fill(const LevelInfo *lev, int L, const int32_t *tb, cons
                        lev[L].cell_off, n, tb, te, offs, items);
 }
 
+// Near-field items in decreasing order of their estimated cost, so that the
+// launch ends on its cheapest items (a persistent grid otherwise ends on
+// whichever items happen to come last).  Key of item i < *count: 0xFFFF
+// minus the estimate ceil(m / 8) x (sources of the leaf's whole near list)
+// / 64, clipped; items past the count key 0xFFFF (after every item); the
+// value is the item's index.
+__global__ void k_near_cost(int64_t leaf_off, int nw, int32_t cap, const int32_t *__restrict__ count,
+                            const int32_t *__restrict__ items, const int32_t *__restrict__ te,
+                            const int32_t *__restrict__ near, const int32_t *__restrict__ sb,
+                            const int32_t *__restrict__ se, uint32_t *__restrict__ keys,
+                            int32_t *__restrict__ vals)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    uint32_t key = 0xFFFFu;
+    if (i < *count) {
+        const int32_t li = items[2 * i], st = items[2 * i + 1];
+        const int32_t m = min(kChunk, te[leaf_off + li] - st);
+        int64_t srcs = 0;
+        for (int k = 0; k < nw; ++k) {
+            const int32_t c = near[(int64_t)li * nw + k];
+            if (c >= 0) srcs += se[c] - sb[c];
+        }
+        const int64_t cost = (int64_t)((m + 7) / 8) * srcs / 64;
+        key = 0xFFFFu - (uint32_t)min<int64_t>(cost, 0xFFFF);
+    }
+    keys[i] = key;
+    vals[i] = i;
+}
+
+__global__ void k_items_gather(int32_t cap, const int32_t *__restrict__ order, const int32_t *__restrict__ items,
+                               int32_t *__restrict__ out)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= cap) return;
+    const int32_t j = order[i];
+    out[2 * i] = items[2 * j];
+    out[2 * i + 1] = items[2 * j + 1];
+}
+
+void launch_near_items_order(int64_t leaf_off, int nw, int32_t cap, const int32_t *count, const int32_t *items,
+                             const int32_t *te, const int32_t *near, const int32_t *sb, const int32_t *se,
+                             uint32_t *keys, int32_t *vals, void *tmp, int32_t *out, hipStream_t s)
+{
+    if (cap <= 0) return;
+    const unsigned g = (unsigned)((cap + 255) / 256);
+    hipLaunchKernelGGL(k_near_cost, dim3(g), dim3(256), 0, s, leaf_off, nw, cap, count, items, te, near, sb, se,
+                       keys, vals);
+    radix_sort(keys, vals, cap, 16, tmp, s);
+    hipLaunchKernelGGL(k_items_gather, dim3(g), dim3(256), 0, s, cap, vals, items, out);
+}
+
 // ------------------------------------------------------------ pair counts
 __global__ void k_count_pairs(int64_t leaf_off, int64_t n_cells, int64_t n_leaf, int e4w, int nw,
                               const int32_t *__restrict__ e4, const int32_t *__restrict__ near,
