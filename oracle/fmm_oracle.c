@@ -313,8 +313,20 @@ static void sept_center_polar(const orc_geom *g, int64_t key, int l, double *cx,
     *cy = g->oy + y;
 }
 
+/* Leaf key of the lattice point b * (digit-1 unit) + c * (digit-2 unit):
+ * the two GBT multiples summed with (+); -1 if it needs more than L digits,
+ * i.e. lies outside the root aggregate. */
+static int64_t sept_key_of_lattice(const orc_geom *g, int64_t b, int64_t c)
+{
+    gbt_num u, v;
+    if (gbt_multiple(b, 1, 4, &u)) return -1;
+    if (gbt_multiple(c, 2, 5, &v)) return -1;
+    if (gbt_add(&u, &v)) return -1;
+    return gbt_to_key(&u, g->L);
+}
+
 /* CellIndex at the leaf level (Sec. 5): change of basis, four candidate
- * lattice points, nearest by squared distance, then u (+) v. */
+ * lattice points, nearest by squared distance, then its GBT index. */
 static int64_t sept_leaf_index(const orc_geom *g, double x, double y)
 {
     const double r = g->size, s3 = sqrt(3.0);
@@ -337,22 +349,27 @@ static int64_t sept_leaf_index(const orc_geom *g, double x, double y)
         }
     }
     if (fabs(cb[best]) > 1e12 || fabs(cc[best]) > 1e12) return -1;
-    gbt_num u, v;
-    if (gbt_multiple((int64_t)cb[best], 1, 4, &u)) return -1;
-    if (gbt_multiple((int64_t)cc[best], 2, 5, &v)) return -1;
-    if (gbt_add(&u, &v)) return -1;
-    return gbt_to_key(&u, g->L);
+    return sept_key_of_lattice(g, (int64_t)cb[best], (int64_t)cc[best]);
 }
 
-static int sept_neighbors(int64_t key, int l, int64_t *out)
+/* Neighbours of a level-l cell (Sec. 5): the cells whose centres sit one
+ * level-l lattice step away, i.e. the centre plus the lattice vector of each
+ * unit digit followed by L - l zeros.  Each such point is a level-l centre,
+ * so its leaf index ends in L - l zero digits; points outside the root
+ * aggregate have no index and are dropped. */
+static int sept_neighbors(const orc_geom *g, int64_t key, int l, int64_t *out)
 {
+    int64_t B, C;
+    sept_lattice(g, key, l, &B, &C);
+    const int64_t scale = ipow(7, g->L - l);
     int cnt = 0;
     for (int d = 1; d <= 6; ++d) {
-        gbt_num n;
-        gbt_from_key(key, &n);
-        if (gbt_add_unit(&n, 0, d)) continue;
-        int64_t k = gbt_to_key(&n, l);
-        if (k >= 0) out[cnt++] = k;
+        int64_t db, dc;
+        sept_zero_ext(d, g->L - l, &db, &dc);
+        int64_t k = sept_key_of_lattice(g, B + db, C + dc);
+        if (k < 0) continue;
+        if (k % scale) abort(); /* a level-l lattice point always ends in zeros */
+        out[cnt++] = k / scale;
     }
     return cnt;
 }
@@ -362,11 +379,6 @@ static int sept_neighbors(int64_t key, int l, int64_t *out)
 /* 3 right.  Centres in integer units: x = U * (sqrt(3)/2) r,            */
 /* y = V * r/2 (leaf circumradius r).                                    */
 /* ===================================================================== */
-
-/* Table D: destination type for (source type, direction L/R/V), and the
- * star marking a sibling. */
-static const int tq_D[4][3] = {{2, 3, 1}, {3, 2, 0}, {1, 0, 2}, {0, 1, 3}};
-static const int tq_star[4][3] = {{1, 1, 1}, {0, 0, 1}, {0, 1, 0}, {1, 0, 0}};
 
 static int tq_digit(int64_t key, int l, int i) /* t_i, i = 1 is left-most */
 {
@@ -388,52 +400,6 @@ static int tq_is_up(int64_t key, int l)
     int m = (par + l - nd + 1) % 2;
     if (m < 0) m += 2;
     return 2 * m - 1;
-}
-
-/* Ancestor-sibling-reflect (Sec. 6): returns 1 and the neighbour, or 0. */
-static int tq_adjacent(int64_t key, int l, int dir, int64_t *out)
-{
-    int t[64];
-    for (int i = 1; i <= l; ++i) t[i] = tq_digit(key, l, i);
-    for (int i = l; i >= 1; --i) {
-        if (tq_star[t[i]][dir]) {
-            t[i] = tq_D[t[i]][dir];
-            for (int j = i + 1; j <= l; ++j) t[j] = tq_D[t[j]][dir];
-            int64_t k = 0;
-            for (int j = 1; j <= l; ++j) k = (k << 2) | t[j];
-            *out = k;
-            return 1;
-        }
-    }
-    return 0;
-}
-
-static int tq_neighbors(int64_t key, int l, int64_t *out)
-{
-    enum { DL = 0, DR = 1, DV = 2 };
-    int64_t Lc, Rc, Vc, VL, VR, LL, RR, LV, RV, VLL, VRR, LVR;
-    int hL = tq_adjacent(key, l, DL, &Lc);
-    int hR = tq_adjacent(key, l, DR, &Rc);
-    int hV = tq_adjacent(key, l, DV, &Vc);
-    int hVL = hV && tq_adjacent(Vc, l, DL, &VL);
-    int hVR = hV && tq_adjacent(Vc, l, DR, &VR);
-    int hLL = hL && tq_adjacent(Lc, l, DL, &LL);
-    int hRR = hR && tq_adjacent(Rc, l, DR, &RR);
-    int hLV = hL && tq_adjacent(Lc, l, DV, &LV);
-    int hRV = hR && tq_adjacent(Rc, l, DV, &RV);
-    int hVLL = hVL && tq_adjacent(VL, l, DL, &VLL);
-    int hVRR = hVR && tq_adjacent(VR, l, DR, &VRR);
-    int hLVR = hLV && tq_adjacent(LV, l, DR, &LVR);
-    int64_t cand[12] = {Lc, Rc, Vc, VL, VR, LL, RR, LV, RV, VLL, VRR, LVR};
-    int have[12] = {hL, hR, hV, hVL, hVR, hLL, hRR, hLV, hRV, hVLL, hVRR, hLVR};
-    int cnt = 0;
-    for (int i = 0; i < 12; ++i) {
-        if (!have[i] || cand[i] == key) continue;
-        int dup = 0;
-        for (int j = 0; j < cnt; ++j) dup |= (out[j] == cand[i]);
-        if (!dup) out[cnt++] = cand[i];
-    }
-    return cnt;
 }
 
 /* Integer-unit centre (U, V) of a cell, by the F(t, i) translations. */
@@ -502,6 +468,64 @@ static int64_t tq_cell_index(const orc_geom *g, double x, double y, int l)
         key = key * 4 + best;
     }
     return key;
+}
+
+/* Cell at level l whose centroid is the integer-unit point (U, V), by
+ * CellIndex of that point; 0 if it lies outside the root triangle.  A
+ * lattice centroid is an inradius away from every edge, far beyond
+ * rounding, so CellIndex returns the triangle it is the centroid of. */
+static int tq_cell_at(const orc_geom *g, int64_t U, int64_t V, int l, int64_t *out)
+{
+    const double r = g->size, s3 = sqrt(3.0);
+    double ax = (s3 * r) / 2.0, ay = r / 2.0;
+    int64_t k = tq_cell_index(g, g->ox + (double)U * ax, g->oy + (double)V * ay, l);
+    if (k < 0) return 0;
+    int64_t U2, V2;
+    tq_center_units(g, k, l, &U2, &V2);
+    if (U2 != U || V2 != V) abort(); /* not a lattice centroid of level l */
+    *out = k;
+    return 1;
+}
+
+/* The cell across one edge (Sec. 6; direction 0 = left, 1 = right, 2 =
+ * vertical).  A triangle of orientation o (+1 up) and circumradius s units
+ * has its vertices at (0, 2os), (-s, -os), (s, -os) from its centroid; the
+ * triangle across the edge opposite a vertex is its mirror image in that
+ * edge, with the centroid at minus that vertex offset: vertical (0, -2os),
+ * left (-s, os), right (s, os). */
+static int tq_adjacent(const orc_geom *g, int64_t key, int l, int dir, int64_t *out)
+{
+    int64_t U, V;
+    tq_center_units(g, key, l, &U, &V);
+    const int64_t s = (int64_t)1 << (g->L - l);
+    const int o = tq_is_up(key, l);
+    const int64_t dU[3] = {-s, s, 0}, dV[3] = {o * s, o * s, -2 * o * s};
+    return tq_cell_at(g, U + dU[dir], V + dV[dir], l, out);
+}
+
+/* Neighbours (Sec. 6): every cell sharing a vertex with the cell.  Six
+ * triangles meet at each lattice vertex, their centroids one circumradius
+ * from it in the directions -90 + 60k degrees: (0, -2s), (s, -s), (s, s),
+ * (0, 2s), (-s, s), (-s, -s) in integer units.  Over the three vertices,
+ * less the cell itself and repeats, that is up to twelve cells. */
+static int tq_neighbors(const orc_geom *g, int64_t key, int l, int64_t *out)
+{
+    int64_t U, V;
+    tq_center_units(g, key, l, &U, &V);
+    const int64_t s = (int64_t)1 << (g->L - l);
+    const int o = tq_is_up(key, l);
+    const int64_t vU[3] = {0, -s, s}, vV[3] = {2 * o * s, -o * s, -o * s};
+    const int64_t wU[6] = {0, s, s, 0, -s, -s}, wV[6] = {-2 * s, -s, s, 2 * s, s, -s};
+    int cnt = 0;
+    for (int v = 0; v < 3; ++v)
+        for (int w = 0; w < 6; ++w) {
+            int64_t k;
+            if (!tq_cell_at(g, U + vU[v] + wU[w], V + vV[v] + wV[w], l, &k) || k == key) continue;
+            int dup = 0;
+            for (int j = 0; j < cnt; ++j) dup |= (out[j] == k);
+            if (!dup) out[cnt++] = k;
+        }
+    return cnt;
 }
 
 /* ===================================================================== */
@@ -578,9 +602,9 @@ int32_t orc_neighbors(const orc_geom *g, int64_t key, int32_t l, int64_t *out)
     case TIL_QUAD:
         return quad_neighbors(key, l, out);
     case TIL_SEPT:
-        return sept_neighbors(key, l, out);
+        return sept_neighbors(g, key, l, out);
     default:
-        return tq_neighbors(key, l, out);
+        return tq_neighbors(g, key, l, out);
     }
 }
 
@@ -628,9 +652,14 @@ int64_t orc_gbt_add(int64_t a, int64_t b)
     return gbt_to_key(&x, 22);
 }
 
+/* Edge neighbour of a triangle-quadtree cell (0 = left, 1 = right, 2 =
+ * vertical); adjacency does not depend on the placement, so a unit tree of
+ * depth l is used. */
 int32_t orc_tq_adjacent(int64_t key, int32_t l, int32_t dir, int64_t *out)
 {
-    return tq_adjacent(key, l, dir, out);
+    if (l < 1 || dir < 0 || dir > 2) return 0;
+    orc_geom g = {TIL_TRI, l, 0.0, 0.0, 1.0};
+    return tq_adjacent(&g, key, l, dir, out);
 }
 
 int32_t orc_tq_is_up(int64_t key, int32_t l) { return tq_is_up(key, l); }

@@ -175,6 +175,24 @@ def test_paper_tq_examples(orc):
                 assert res == int(ent[0])
             else:
                 assert res is None
+    # Deeper, the neighbour across an edge (found from the lattice) has the
+    # table's destination type as its last digit, and a starred entry means
+    # the neighbour is a sibling (same parent); the way back crosses the same
+    # edge, which is the other cell's right edge for a left step and so on.
+    D = [[int(e[0]) for e in row] for row in EX["tq_table_D"]["rows"]]
+    star = [[e.endswith("*") for e in row] for row in EX["tq_table_D"]["rows"]]
+    for lvl in range(2, 6):
+        for key in range(4 ** lvl):
+            t = key & 3
+            for d in range(3):
+                res = orc.tq_adjacent(key, lvl, d)
+                if star[t][d]:
+                    assert res is not None and res >> 2 == key >> 2, (lvl, key, d)
+                else:
+                    assert res is None or res >> 2 != key >> 2, (lvl, key, d)
+                if res is not None:
+                    assert res & 3 == D[t][d], (lvl, key, d)
+                    assert orc.tq_adjacent(res, lvl, (1, 0, 2)[d]) == key
 
 
 def test_tq_isup_is_zero_parity(orc):
