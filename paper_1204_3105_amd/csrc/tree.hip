@@ -592,10 +592,11 @@ void launch_near_items_fill(const LevelInfo *lev, int L, const int32_t *tb, cons
 
 // Near-field items in decreasing order of their estimated cost, so that the
 // launch ends on its cheapest items (a persistent grid otherwise ends on
-// whichever items happen to come last).  Key of item i < *count: 0xFFFF
-// minus the estimate ceil(m / 8) x (sources of the leaf's whole near list)
-// / 64, clipped; items past the count key 0xFFFF (after every item); the
-// value is the item's index.
+// whichever items happen to come last).  The estimate is ceil(m / 8) x
+// (sources of the leaf's whole near list); the key of item i < *count is 255
+// minus the estimate as an 8-bit float (5-bit exponent, 3-bit mantissa), so
+// one radix pass sorts them; items past the count key 255 (after every
+// item); the value is the item's index.
 __global__ void k_near_cost(int64_t leaf_off, int nw, int32_t cap, const int32_t *__restrict__ count,
                             const int32_t *__restrict__ items, const int32_t *__restrict__ te,
                             const int32_t *__restrict__ near, const int32_t *__restrict__ sb,
@@ -604,7 +605,7 @@ __global__ void k_near_cost(int64_t leaf_off, int nw, int32_t cap, const int32_t
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cap) return;
-    uint32_t key = 0xFFFFu;
+    uint32_t key;
     if (i < *count) {
         const int32_t li = items[2 * i], st = items[2 * i + 1];
         const int32_t m = min(kChunk, te[leaf_off + li] - st);
@@ -613,8 +614,12 @@ __global__ void k_near_cost(int64_t leaf_off, int nw, int32_t cap, const int32_t
             const int32_t c = near[(int64_t)li * nw + k];
             if (c >= 0) srcs += se[c] - sb[c];
         }
-        const int64_t cost = (int64_t)((m + 7) / 8) * srcs / 64;
-        key = 0xFFFFu - (uint32_t)min<int64_t>(cost, 0xFFFF);
+        const uint64_t cost = (uint64_t)((m + 7) / 8) * (uint64_t)srcs + 1;
+        const int e = 63 - __builtin_clzll(cost);                      // cost in [2^e, 2^(e+1))
+        const uint32_t mant = e >= 3 ? (uint32_t)(cost >> (e - 3)) & 7u : (uint32_t)(cost << (3 - e)) & 7u;
+        key = 255u - min(255u, ((uint32_t)min(e, 31) << 3) | mant);
+    } else {
+        key = 255u;
     }
     keys[i] = key;
     vals[i] = i;
@@ -638,7 +643,7 @@ void launch_near_items_order(int64_t leaf_off, int nw, int32_t cap, const int32_
     const unsigned g = (unsigned)((cap + 255) / 256);
     hipLaunchKernelGGL(k_near_cost, dim3(g), dim3(256), 0, s, leaf_off, nw, cap, count, items, te, near, sb, se,
                        keys, vals);
-    radix_sort(keys, vals, cap, 16, tmp, s);
+    radix_sort(keys, vals, cap, 8, tmp, s);
     hipLaunchKernelGGL(k_items_gather, dim3(g), dim3(256), 0, s, cap, vals, items, out);
 }
 
