@@ -39,9 +39,9 @@ LANE_OPS = 256 * 4 * 16 * 2.4e9
 # pair serves both of its sides and the leaf itself is one-sided.  The FP64
 # symmetric figures are the per-evaluation slopes printed by
 # paper_1204_3105_amd/csrc/count_valu.py (per-round work excluded).
-VALU_PER_PAIR = {"fp64": 104.0, "mixed": 31.0}
-VALU_SYM_EVAL = {"mixed": 30.5, "fp64": 80.2}
-VALU_SYM_ONE_SIDED = {"mixed": 30.0, "fp64": 79.0}
+VALU_PER_PAIR = {"fp64": 84.0, "mixed": 31.0}
+VALU_SYM_EVAL = {"mixed": 30.5, "fp64": 73.2}
+VALU_SYM_ONE_SIDED = {"mixed": 30.0, "fp64": 72.0}
 SYM_CHUNKS = 2   # a leaf of at most 2 x 64 targets evaluates its pairs with higher leaves for both sides
 
 

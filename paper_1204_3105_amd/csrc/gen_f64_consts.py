@@ -2,9 +2,9 @@
 60-digit decimal arithmetic: ln 2 = 2 atanh(1/3), pi = 16 atan(1/5) -
 4 atan(1/239) (Machin).  ln 2 is split so that its high part has 32
 significant bits (e * ln2_hi is exact for |e| < 2^21).  c = sqrt(1/2)
-rounded to double is the logarithm's reduction point; ln_c2 = ln(c sqrt 2)
-(= 2 atanh((y - 1)/(y + 1)), y = c sqrt 2) is what the rounding of c leaves
-of ln c + ln(2)/2."""
+rounded to double is the logarithm's reduction point; ln_c = ln c, formed as
+ln(c sqrt 2) - ln(2)/2 with ln(c sqrt 2) = 2 atanh((y - 1)/(y + 1)),
+y = c sqrt 2."""
 import math
 from decimal import Decimal, getcontext
 
@@ -44,4 +44,4 @@ if __name__ == "__main__":
     print("inv_sqrt3 %r tan_pi_12 %r" % (float(1 / Decimal(3).sqrt()), float(2 - Decimal(3).sqrt())))
     c = math.sqrt(0.5)
     y = Decimal(c) * Decimal(2).sqrt()
-    print("sqrt_half %r ln_c2 %r" % (c, float(2 * atanh_inv((y - 1) / (y + 1)))))
+    print("sqrt_half %r ln_c %r" % (c, float(2 * atanh_inv((y - 1) / (y + 1)) - ln2 / 2)))

@@ -25,14 +25,18 @@ static constexpr double kPi2Hi = 1.5707963267948966, kPi2Lo = 6.123233995736766e
 static constexpr double kPi6Hi = 0.5235987755982989, kPi6Lo = -5.360408832255455e-17;
 static constexpr double kInvSqrt3 = 0.5773502691896257, kTanPi12 = 0.2679491924311227;
 static constexpr double kSqrtHalf = 0.7071067811865476;
-// ln(c sqrt 2) for c = kSqrtHalf (what the rounding of c leaves of
-// ln c + ln(2) / 2).
-static constexpr double kLnC2 = 6.835808657661923e-17;
+// ln c for c = kSqrtHalf, the rounded sqrt(1/2).
+static constexpr double kLnC = -0.3465735902799726;
 // Series remainders on the reduced intervals, weighted minimax fits from
 // gen_f64_poly.py: ln m = 2s (1 + z P(z)) with z = s^2 <= (3 - 2 sqrt2)^2
 // (|z dP| <= 1.3e-18), atan t = t (1 + w Q(w)) with w = t^2 <= (2 - sqrt3)^2
 // (|w dQ| <= 1.6e-17); coefficient k multiplies z^k (w^k).
 static constexpr double kLnPoly[7] = {0.3333333333333367, 0.19999999999707335, 0.14285714371194552, 0.11111099286525694, 0.090917821661685105, 0.076570252032999594, 0.073979755249923215};
+// kLnPoly scaled for the doubled variables s2 = 2s, z4 = s2^2 = 4z:
+// z P(z) = z4 P4(z4) with coefficient k of P4 = that of P / 4^(k+1) (powers
+// of two, so every Horner step is the same number scaled exactly).
+static constexpr double kLnPoly4[7] = {kLnPoly[0] / 4, kLnPoly[1] / 16, kLnPoly[2] / 64, kLnPoly[3] / 256,
+                                       kLnPoly[4] / 1024, kLnPoly[5] / 4096, kLnPoly[6] / 16384};
 static constexpr double kAtanPoly64[8] = {-0.33333333333331033, 0.19999999998955142, -0.14285714123172341, 0.11111098862513553, -0.090903969460381456, 0.076797606015821029, -0.064863446745019704, 0.044493669821161291};
 
 __device__ __forceinline__ double ln_poly(double z)
@@ -44,6 +48,17 @@ __device__ __forceinline__ double ln_poly(double z)
     p = fma(p, z, kLnPoly[2]);
     p = fma(p, z, kLnPoly[1]);
     return fma(p, z, kLnPoly[0]);
+}
+
+__device__ __forceinline__ double ln_poly4(double z4)
+{
+    double p = kLnPoly4[6];
+    p = fma(p, z4, kLnPoly4[5]);
+    p = fma(p, z4, kLnPoly4[4]);
+    p = fma(p, z4, kLnPoly4[3]);
+    p = fma(p, z4, kLnPoly4[2]);
+    p = fma(p, z4, kLnPoly4[1]);
+    return fma(p, z4, kLnPoly4[0]);
 }
 
 __device__ __forceinline__ double atan_poly(double w)
@@ -112,42 +127,48 @@ __device__ __forceinline__ double atan2_f64(double y, double x)
 }
 
 
-// ln(r2) and atan2(y, x) together, as ln_f64 and atan2_f64 but with one
-// reciprocal for both divisions.  The logarithm's reduction is shifted so
-// that frexp's mantissa m in [1/2, 1) needs no adjustment: with c = sqrt(1/2)
-// (rounded), s = (m - c)/(m + c) covers the same interval |s| <= 3 - 2 sqrt2
-// as (m' - 1)/(m' + 1) for m' in [sqrt(1/2), sqrt2), and ln m = ln c +
-// 2 atanh(s).  With D = (m + c) den, R = 1/D (hardware reciprocal, two Newton
-// steps), s = (m - c) den R and t = num (m + c) R; each quotient is within a
-// few ulp, far below what the FP64 near field needs.
-__device__ __forceinline__ void ln_atan2_f64(double r2, double y, double x, double &lnr2, double &at)
+// ln(r2) and the angle of (|x|, |y|) in [0, pi/2] together, as ln_f64 and
+// atan2_f64 but with one reciprocal for both divisions.  The logarithm's
+// reduction is shifted so that frexp's mantissa m in [1/2, 1) needs no
+// adjustment: with c = sqrt(1/2) (rounded), s = (m - c)/(m + c) covers the
+// same interval |s| <= 3 - 2 sqrt2 as (m' - 1)/(m' + 1) for m' in
+// [sqrt(1/2), sqrt2), and ln r2 = e ln 2 + ln c + 2 atanh(s).  With
+// D = (m + c) den and R = 1/D, s2 = 2s = 2(m - c) den R (2(m - c) exact) and
+// t = num (m + c) R; each quotient is within a few ulp, far below what the
+// FP64 near field needs.  R refines the hardware reciprocal R0 (relative error
+// d = 1 - D R0) as R0 (1 + d + d^2), leaving d^3.  The pi/6 rotation of
+// atan2_f64 is applied with a 0/1 factor instead of selects; with the factor
+// 0 every step returns its input unchanged.
+__device__ __forceinline__ void ln_angle_f64(double r2, double ax, double ay, double &lnr2, double &a)
 {
     int e;
     const double m = frexp(r2, &e);   // m in [1/2, 1)
-    const double ax = fabs(x), ay = fabs(y);
     const double mn = fmin(ax, ay), mx = fmax(ax, ay);
-    const bool red = mn > kTanPi12 * mx;
-    const double num = red ? fma(-kInvSqrt3, mx, mn) : mn;
-    const double den = red ? fma(kInvSqrt3, mn, mx) : mx;
+    const double rot = mn > kTanPi12 * mx ? 1.0 : 0.0;
+    const double k = rot * kInvSqrt3;
+    const double num = fma(-k, mx, mn), den = fma(k, mn, mx);
     const double mpc = m + kSqrtHalf;
     const double D = mpc * den;
-    double R = __builtin_amdgcn_rcp(D);
-    R = fma(R, fma(-D, R, 1.0), R);
-    R = fma(R, fma(-D, R, 1.0), R);
-    const double s = ((m - kSqrtHalf) * den) * R;   // m - c is exact
+    const double R0 = __builtin_amdgcn_rcp(D);
+    const double d = fma(-D, R0, 1.0);
+    const double R = fma(R0, fma(d, d, d), R0);
+    const double s2 = (fma(m, 2.0, -2.0 * kSqrtHalf) * den) * R;
     const double t = (num * mpc) * R;
-    // ln r2 = (e - 1/2) ln 2 + ln(c sqrt 2) + 2 atanh(s), s = (m - c)/(m + c)
-    const double z = s * s;
-    const double p = ln_poly(z);
-    const double lm = 2.0 * s + 2.0 * s * (z * p);
-    const double de = (double)e - 0.5;
-    lnr2 = fma(de, kLn2Hi, fma(de, kLn2Lo, lm + kLnC2));
-    // atan t, then the octant
+    const double z4 = s2 * s2;
+    const double lm = fma(s2, z4 * ln_poly4(z4), s2);   // 2 atanh(s)
+    const double de = (double)e;
+    lnr2 = fma(de, kLn2Hi, fma(de, kLn2Lo, lm + kLnC));
     const double w = t * t;
-    const double q = atan_poly(w);
-    double a = fma(t * w, q, t);
-    a = red ? kPi6Hi + (kPi6Lo + a) : a;
+    a = fma(t * w, atan_poly(w), t);
+    a = fma(rot, kPi6Hi, fma(rot, kPi6Lo, a));
     a = (ay > ax) ? kPi2Hi + (kPi2Lo - a) : a;
+}
+
+// ln(r2) and atan2(y, x) on (-pi, pi] (y = -0 read as +0).
+__device__ __forceinline__ void ln_atan2_f64(double r2, double y, double x, double &lnr2, double &at)
+{
+    double a;
+    ln_angle_f64(r2, fabs(x), fabs(y), lnr2, a);
     a = (x < 0.0) ? kPiHi + (kPiLo - a) : a;
     at = (y < 0.0) ? -a : a;
 }
@@ -163,7 +184,7 @@ __device__ __forceinline__ void ln_atan2_f64(double r2, double y, double x, doub
 // kernel also sums u / (y - x) = u (dx - i dy) / r^2 into the field's near
 // sums (bm.nfield).
 template <bool FIELD>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 3 : 5, 8))) void k_near_fp64(const EvalJob *__restrict__ jobs, BatchMap bm)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 3 : 4, 8))) void k_near_fp64(const EvalJob *__restrict__ jobs, BatchMap bm)
 {
     constexpr int kStage = kNearSlots * 9;   // g (cl + 1) <= 117 for every g
     __shared__ double shbuf[3 * kStage];
@@ -248,7 +269,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 3 : 
                     const bool live = r2 > 0.0;
                     double lg, at;
                     ln_atan2_f64(live ? r2 : 1.0, dy, live ? dx : 1.0, lg, at);
-                    re = fma(live ? su[j] : 0.0, 0.5 * lg, re);
+                    re = fma(live ? su[j] : 0.0, lg, re);   // halved at the end
                     im = fma(live ? su[j] : 0.0, at, im);
                     if (FIELD) {
                         const double w = live ? div_f64(su[j], r2) : 0.0;
@@ -264,7 +285,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 3 : 
                     const double r2 = dx * dx + dy * dy;
                     double lg, at;
                     ln_atan2_f64(r2, dy, dx, lg, at);
-                    re = fma(u, 0.5 * lg, re);
+                    re = fma(u, lg, re);
                     im = fma(u, at, im);
                     if (FIELD) {
                         const double w = div_f64(u, r2);
@@ -284,7 +305,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FIELD ? 3 : 
                 }
             }
         }
-        red[0][lane] = re;   // the last round's barrier freed the staging buffers
+        red[0][lane] = 0.5 * re;   // ln r = ln(r2) / 2; the last round's barrier freed the staging buffers
         red[1][lane] = im;
         if (FIELD) {
             red[2][lane] = fr;
@@ -553,30 +574,8 @@ void launch_direct(const double *src, int64_t n_src, const double *tgt, int64_t 
 __device__ __forceinline__ void ln_atan2_pair_f64(double r2, double y, double x, double &lnr2, double &at,
                                                   double &atr)
 {
-    int e;
-    const double m = frexp(r2, &e);   // m in [1/2, 1)
-    const double ax = fabs(x), ay = fabs(y);
-    const double mn = fmin(ax, ay), mx = fmax(ax, ay);
-    const bool red = mn > kTanPi12 * mx;
-    const double num = red ? fma(-kInvSqrt3, mx, mn) : mn;
-    const double den = red ? fma(kInvSqrt3, mn, mx) : mx;
-    const double mpc = m + kSqrtHalf;
-    const double D = mpc * den;
-    double R = __builtin_amdgcn_rcp(D);
-    R = fma(R, fma(-D, R, 1.0), R);
-    R = fma(R, fma(-D, R, 1.0), R);
-    const double s = ((m - kSqrtHalf) * den) * R;
-    const double t = (num * mpc) * R;
-    const double z = s * s;
-    const double p = ln_poly(z);
-    const double lm = 2.0 * s + 2.0 * s * (z * p);
-    const double de = (double)e - 0.5;
-    lnr2 = fma(de, kLn2Hi, fma(de, kLn2Lo, lm + kLnC2));
-    const double w = t * t;
-    const double q = atan_poly(w);
-    double a = fma(t * w, q, t);
-    a = red ? kPi6Hi + (kPi6Lo + a) : a;
-    a = (ay > ax) ? kPi2Hi + (kPi2Lo - a) : a;
+    double a;
+    ln_angle_f64(r2, fabs(x), fabs(y), lnr2, a);
     const double pa = kPiHi + (kPiLo - a);
     const double af = (x < 0.0) ? pa : a, ab = (x > 0.0) ? pa : a;
     at = (y < 0.0) ? -af : af;
