@@ -2,16 +2,18 @@
 the gfx950 assembly the compiler emits for near.hip (the counts the
 benchmark's near-field roofline uses).
 
-The kernel's round loops are specialised on the number NB of eight-row target
-blocks (1..12); a round evaluates NB pairs per lane.  Each loop is found by
-the compiler's loop annotations and its VALU instructions counted (v_* except
-MFMA); the one v_rcp_f64 per evaluation gives NB.  A straight-line fit of
-VALU against NB over NB = 4..12 gives the instructions per evaluation (the
-slope: everything an evaluation costs, including its share of the
-accumulation and sign selection) and per round (the intercept: source loads,
-the column cursor, the second-side reduction and store, loop control), for
-the two loop kinds: the leaf's own sources (one side, a zero-separation
-guard) and the neighbours' sources (both sides, ds_bpermute row sums).
+The kernel's round loops are specialised on the tile (target blocks of eight
+rows and eight sources per round, or four rows and sixteen sources) and on
+the number NB of target blocks; a round evaluates NB pairs per lane.  Each
+loop is found by the compiler's loop annotations and its VALU instructions
+counted (v_* except MFMA); the one v_rcp_f64 per evaluation gives NB, the
+loop's scalar step (8 or 16 sources) the tile.  A straight-line fit of VALU
+against NB over NB = 4..12 gives the instructions per evaluation (the slope:
+everything an evaluation costs, including its share of the accumulation and
+sign selection) and per round (the intercept: source loads, the column
+cursor, the second-side reduction and store, loop control), for the two
+loop kinds: the leaf's own sources (one side, a zero-separation guard) and
+the neighbours' sources (both sides, ds_bpermute row sums).
 
     python count_valu.py            # compiles near.hip with the build's flags
 """
@@ -42,7 +44,7 @@ def loops(lines, fn):
     for l in lines[start:end]:
         m = re.match(r"^\.LBB(\d+_\d+):(.*)", l)
         if m:
-            cur = {"name": m.group(1), "note": m.group(2), "ins": []}
+            cur = {"name": m.group(1), "note": m.group(2), "ins": [], "full": []}
             blocks.append(cur)
         elif cur is not None:
             t = l.strip()
@@ -50,6 +52,7 @@ def loops(lines, fn):
                 cur["note"] += " header"
             elif t and not t.startswith(";") and not t.startswith("."):
                 cur["ins"].append(t.split()[0])
+                cur["full"].append(t.split(";")[0].strip())
     groups = {}
     for b in blocks:
         m = re.search(r"Header=BB(\d+_\d+) Depth=", b["note"])
@@ -59,12 +62,14 @@ def loops(lines, fn):
     out = []
     for bl in groups.values():
         ins = [i for b in bl for i in b["ins"]]
+        full = [i for b in bl for i in b["full"]]
         nb = sum(i.startswith("v_rcp_f64") for i in ins)
         if nb == 0:
             continue
         valu = sum(i.startswith("v_") and not i.startswith("v_mfma") for i in ins)
         two = any(i.startswith("ds_bpermute") for i in ins)
-        out.append((two, nb, valu))
+        step = [int(m.group(1)) for i in full for m in [re.match(r"s_add_i32 s\d+, s\d+, (8|16)$", i)] if m]
+        out.append((two, step[0] if step else 0, nb, valu))
     return out
 
 
@@ -80,11 +85,14 @@ def fit(points):
 
 def main():
     found = loops(assembly(), KERNEL)
-    for two, name in ((True, "neighbours, both sides"), (False, "own leaf, one side")):
-        pts = sorted((nb, v) for t, nb, v in found if t == two and nb >= 4)
-        slope, icpt = fit(pts)
-        print("%-24s VALU per evaluation %.1f, per round %.1f  (NB, VALU: %s)" % (
-            name, slope, icpt, ", ".join("%d:%d" % p for p in pts)))
+    for tc, tile in ((8, "8 x 8"), (16, "4 x 16")):
+        for two, name in ((True, "neighbours, both sides"), (False, "own leaf, one side")):
+            pts = sorted((nb, v) for t, c, nb, v in found if t == two and c == tc and nb >= 4)
+            if len(pts) < 2:
+                continue
+            slope, icpt = fit(pts)
+            print("%-6s %-24s VALU per evaluation %.1f, per round %.1f  (NB, VALU: %s)" % (
+                tile, name, slope, icpt, ", ".join("%d:%d" % p for p in pts)))
 
 
 if __name__ == "__main__":

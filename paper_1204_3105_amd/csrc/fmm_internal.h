@@ -39,6 +39,10 @@ constexpr int kSymChunks = 2;
 // kChunk points is not split into a full and a nearly empty item; the mixed
 // one splits every leaf into chunks of kChunk.
 constexpr int kWide = 96;
+// Items of the FP64 symmetric kernel with at most this many targets use
+// target blocks of four rows and sixteen sources per round (else eight and
+// eight).
+constexpr int kSmall = 48;
 // Chunks of a leaf with n targets in a symmetric kernel whose single items
 // hold up to `wide` targets (kWide for FP64, kChunk for mixed): one up to
 // `wide`, else ceil(n / kChunk).  Its second-side sums take one slot per chunk.
@@ -219,10 +223,13 @@ void launch_local_coords(const double *x, const double *y, const uint32_t *key, 
 void launch_near_items(const LevelInfo *lev, int L, const int32_t *tb, const int32_t *te,
                        int32_t *counts, hipStream_t s);
 // Items reordered by decreasing estimated cost into out (2 cap ints); keys,
-// vals (cap each) and tmp (radix_tmp_bytes(cap)) are scratch.
-void launch_near_items_order(int64_t leaf_off, int nw, int32_t cap, const int32_t *count, const int32_t *items,
-                             const int32_t *te, const int32_t *near, const int32_t *sb, const int32_t *se,
-                             uint32_t *keys, int32_t *vals, void *tmp, int32_t *out, hipStream_t s);
+// vals (cap each) and tmp (radix_tmp_bytes(cap)) are scratch.  `wide`: a
+// leaf of at most that many targets is one item; `small`: items of at most
+// that many targets use the four-row tile (0 = none).
+void launch_near_items_order(int64_t leaf_off, int nw, int wide, int small, int32_t cap, const int32_t *count,
+                             const int32_t *items, const int32_t *tb, const int32_t *te, const int32_t *near,
+                             const int32_t *sb, const int32_t *se, uint32_t *keys, int32_t *vals, void *tmp,
+                             int32_t *out, hipStream_t s);
 void launch_near_items_fill(const LevelInfo *lev, int L, const int32_t *tb, const int32_t *te,
                             const int32_t *offs, int32_t *items, hipStream_t s);
 void launch_count_pairs(const LevelInfo *lev, int L, int e4w, int nw, const int32_t *e4,

@@ -594,14 +594,17 @@ __device__ __forceinline__ double bperm_f64(int addr, double v)
 // The FP64 near field for a plan whose targets are its sources: a neighbour
 // pair {A, B} (A the lower cell id, with at most kSymChunks chunks) is
 // evaluated once, by A's items, for both sides; the leaf itself, and pairs
-// whose lower leaf is larger, one-sided.  An 8 x 8 lane tile: A's targets
-// (all of a leaf of up to kWide = 96, else a chunk of 64) in LDS in blocks
-// of eight rows, eight sources per round in the columns (absolute
-// coordinates, loaded a round ahead), so every separation, and with it the
-// sign of dy, is exact.  The item runs two loops: the leaf's own sources
-// (one side, zero separations skipped), then the sources of its other
-// neighbour cells as one concatenated sequence, so a round's eight columns
-// may come from two cells and only the sequence's last round is padded.
+// whose lower leaf is larger, one-sided.  A lane tile of R target rows by
+// 64 / R source columns: A's targets (all of a leaf of up to kWide = 96,
+// else a chunk of 64) in LDS in blocks of R rows, 64 / R sources per round in
+// the columns (absolute coordinates, loaded a round ahead), so every
+// separation, and with it the sign of dy, is exact; R = 8, or R = 4 for
+// items of at most kSmall = 48 targets, whose last block then pads at most
+// three rows and whose per-round work is spread over twice the sources.  The
+// item runs two loops: the leaf's own sources (one side, zero separations
+// skipped), then the sources of its other neighbour cells as one
+// concatenated sequence, so a round's columns may come from two cells and
+// only the sequence's last round is padded.
 // Each column keeps a cursor (cell, position) into the sequence.  Sums are
 // FP64 throughout: A's in the lanes, reduced over the columns at the end;
 // each round's second-side sums reduced over the rows and stored per
@@ -622,10 +625,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
     // waves per SIMD, and leaves register room for other kernels' waves.
     constexpr int kRegBlocks = 2;
     __shared__ double2 sacc[kWide / 8 - kRegBlocks][64];
-    const int lane = threadIdx.x, row = lane >> 3, col = lane & 7;
-    // ds_bpermute byte addresses of lane ^ 1, 2, 4 (columns) and ^ 8, 16, 32 (rows)
-    const int perm1 = (lane ^ 1) << 2, perm2 = (lane ^ 2) << 2, perm4 = (lane ^ 4) << 2;
-    const int perm8 = (lane ^ 8) << 2, perm16 = (lane ^ 16) << 2, perm32 = (lane ^ 32) << 2;
+    const int lane = threadIdx.x;
     static_assert(kNearSlots <= 16, "neighbour lists scanned within 16 lanes");
     for (int64_t item = blockIdx.x; item < bm.pre[bm.n]; item += gridDim.x) {
         // (the entry and its job are the same in every lane: scalar)
@@ -709,11 +709,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
             r.w = gload((const double *)J.su, i);
             return r;
         };
-        // The item's rounds for NB target blocks (dispatched once per item,
-        // so the accumulators stay in place from round to round).
-        auto item_rounds = [&](auto nb_const) {
-            constexpr int NB = decltype(nb_const)::value;
+        // The item's rounds for NB target blocks of R rows (dispatched once
+        // per item, so the accumulators stay in place from round to round):
+        // lane = row x TC + column, TC = 64 / R sources per round.
+        auto item_rounds = [&](auto r_const, auto nb_const) {
+            constexpr int R = decltype(r_const)::value, NB = decltype(nb_const)::value;
+            constexpr int TC = 64 / R;
             constexpr int NR = NB < kRegBlocks ? NB : kRegBlocks;   // blocks summed in registers
+            static_assert(NB - NR <= kWide / 8 - kRegBlocks && R * NB <= kWide, "LDS sums and targets");
+            const int row = lane / TC, col = lane % TC;
             double ar[NR], ai[NR];
 #pragma unroll
             for (int blk = 0; blk < NR; ++blk) ar[blk] = ai[blk] = 0.0;
@@ -740,7 +744,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 Src nxt = load(ok ? b + col : 0);
                 while (b < se0) {
                     const double sx = nxt.x, sy = nxt.y, su = ok ? nxt.w : 0.0;
-                    b += 8;
+                    b += TC;
                     ok = b + col < se0;
                     nxt = load(ok ? b + col : 0);
                     // The targets are read from LDS every round (an opaque
@@ -751,7 +755,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                     asm volatile("" : "+v"(qrow));
 #pragma unroll
                     for (int blk = 0; blk < NB; ++blk) {
-                        const int q = 8 * blk + qrow;
+                        const int q = R * blk + qrow;
                         const double2 t = sxy[q];
                         const double dx = t.x - sx, dy = t.y - sy;
                         const double r2 = fma(dx, dx, dy * dy);
@@ -777,12 +781,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                 bool ok = p < total;
                 int32_t dst = ok && c.w ? c.z + p : -1;   // the column's second-side sum
                 Src nxt = load(ok ? c.y + p : 0);
-                for (int32_t P = 0; P < total; P += 8) {
+                for (int32_t P = 0; P < total; P += TC) {
                     // padding: zero strength, far away
                     const double sx = ok ? nxt.x : 1e100, sy = ok ? nxt.y : 1e100;
                     const double su = ok ? nxt.w : 0.0;
                     const int32_t out = dst;
-                    p = P + 8 + col;
+                    p = P + TC + col;
                     c = locate(p);
                     ok = p < total;
                     dst = ok && c.w ? c.z + p : -1;
@@ -792,7 +796,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                     double br = 0.0, bi = 0.0;
 #pragma unroll
                     for (int blk = 0; blk < NB; ++blk) {
-                        const int q = 8 * blk + qrow;
+                        const int q = R * blk + qrow;
                         const double2 t = sxy[q];
                         const double dx = t.x - sx, dy = t.y - sy, u = sau[q];
                         double lg, at, atr;
@@ -801,14 +805,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                         br = fma(u, lg, br);
                         bi = fma(u, atr, bi);
                     }
-                    // B's sums over the rows (lane ^ 8, ^ 16, ^ 32), with
-                    // permute addresses computed once
-                    br += bperm_f64(perm8, br);
-                    bi += bperm_f64(perm8, bi);
-                    br += bperm_f64(perm16, br);
-                    bi += bperm_f64(perm16, bi);
-                    br += bperm_f64(perm32, br);
-                    bi += bperm_f64(perm32, bi);
+                    // B's sums over the rows (lane ^ TC, ^ 2 TC, ..., ^ 32)
+#pragma unroll
+                    for (int k = TC; k < 64; k <<= 1) {
+                        const int a = (lane ^ k) << 2;
+                        br += bperm_f64(a, br);
+                        bi += bperm_f64(a, bi);
+                    }
                     if (row == 0 && out >= 0) J.bside64[(uint32_t)out] = make_double2(0.5 * br, bi);
                 }
             }
@@ -824,33 +827,49 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
                     vr = v.x;
                     vi = v.y;
                 }
-                vr += bperm_f64(perm1, vr);
-                vi += bperm_f64(perm1, vi);
-                vr += bperm_f64(perm2, vr);
-                vi += bperm_f64(perm2, vi);
-                vr += bperm_f64(perm4, vr);
-                vi += bperm_f64(perm4, vi);
-                const int q = 8 * blk + row;
+#pragma unroll
+                for (int k = 1; k < TC; k <<= 1) {
+                    const int a = (lane ^ k) << 2;
+                    vr += bperm_f64(a, vr);
+                    vi += bperm_f64(a, vi);
+                }
+                const int q = R * blk + row;
                 if (col == 0 && q < m) {
                     J.nsum[2 * (st + q)] = 0.5 * vr;
                     J.nsum[2 * (st + q) + 1] = vi;
                 }
             }
         };
-        static_assert(kWide == 96, "one case per number of target blocks");
-        switch (nblk) {
-        case 1: item_rounds(std::integral_constant<int, 1>{}); break;
-        case 2: item_rounds(std::integral_constant<int, 2>{}); break;
-        case 3: item_rounds(std::integral_constant<int, 3>{}); break;
-        case 4: item_rounds(std::integral_constant<int, 4>{}); break;
-        case 5: item_rounds(std::integral_constant<int, 5>{}); break;
-        case 6: item_rounds(std::integral_constant<int, 6>{}); break;
-        case 7: item_rounds(std::integral_constant<int, 7>{}); break;
-        case 8: item_rounds(std::integral_constant<int, 8>{}); break;
-        case 9: item_rounds(std::integral_constant<int, 9>{}); break;
-        case 10: item_rounds(std::integral_constant<int, 10>{}); break;
-        case 11: item_rounds(std::integral_constant<int, 11>{}); break;
-        default: item_rounds(std::integral_constant<int, 12>{}); break;
+        // Items of at most kSmall targets take blocks of four rows and sixteen
+        // sources per round (less padding and per-round work for small
+        // leaves), larger ones blocks of eight rows and eight sources.
+        static_assert(kWide == 96 && kSmall == 48, "one case per number of target blocks");
+        using I4 = std::integral_constant<int, 4>;
+        using I8 = std::integral_constant<int, 8>;
+        if (m <= kSmall) {
+            switch ((m + 3) >> 2) {
+            case 1: item_rounds(I4{}, std::integral_constant<int, 1>{}); break;
+            case 2: item_rounds(I4{}, std::integral_constant<int, 2>{}); break;
+            case 3: item_rounds(I4{}, std::integral_constant<int, 3>{}); break;
+            case 4: item_rounds(I4{}, std::integral_constant<int, 4>{}); break;
+            case 5: item_rounds(I4{}, std::integral_constant<int, 5>{}); break;
+            case 6: item_rounds(I4{}, std::integral_constant<int, 6>{}); break;
+            case 7: item_rounds(I4{}, std::integral_constant<int, 7>{}); break;
+            case 8: item_rounds(I4{}, std::integral_constant<int, 8>{}); break;
+            case 9: item_rounds(I4{}, std::integral_constant<int, 9>{}); break;
+            case 10: item_rounds(I4{}, std::integral_constant<int, 10>{}); break;
+            case 11: item_rounds(I4{}, std::integral_constant<int, 11>{}); break;
+            default: item_rounds(I4{}, std::integral_constant<int, 12>{}); break;
+            }
+        } else {
+            switch (nblk) {
+            case 7: item_rounds(I8{}, std::integral_constant<int, 7>{}); break;
+            case 8: item_rounds(I8{}, std::integral_constant<int, 8>{}); break;
+            case 9: item_rounds(I8{}, std::integral_constant<int, 9>{}); break;
+            case 10: item_rounds(I8{}, std::integral_constant<int, 10>{}); break;
+            case 11: item_rounds(I8{}, std::integral_constant<int, 11>{}); break;
+            default: item_rounds(I8{}, std::integral_constant<int, 12>{}); break;
+            }
         }
     }
 }

@@ -785,8 +785,12 @@ static fmm_status build_plan(PlanImpl *P, int tiling, const double *src, int64_t
         int32_t *sorted = take<int32_t>(P, 2 * items_cap, &err);
         char *itmp = take<char>(P, (int64_t)radix_tmp_bytes(items_cap), &err);
         if (err) return fail(FMM_E_NOMEM, "device allocation failed (near items)");
-        launch_near_items_order(P->lev[g.L].cell_off, nw, (int32_t)items_cap, P->counts + 0, P->work_near, P->te,
-                                P->near, P->sb, P->se, ikeys, ivals, itmp, sorted, s);
+        // (the FP64 symmetric kernel takes leaves of up to kWide targets as
+        // one item and small items in its four-row tile)
+        const bool sym64 = P->precision != FMM_PREC_MIXED && same && N > 0 && sym_offsets_fit(nw, N);
+        launch_near_items_order(P->lev[g.L].cell_off, nw, sym64 ? kWide : kChunk, sym64 ? kSmall : 0,
+                                (int32_t)items_cap, P->counts + 0, P->work_near, P->tb, P->te, P->near, P->sb, P->se,
+                                ikeys, ivals, itmp, sorted, s);
         P->work_near = sorted;
     }
     P->m2l_pm = m2l_pm_for(P->p);

@@ -592,34 +592,42 @@ void launch_near_items_fill(const LevelInfo *lev, int L, const int32_t *tb, cons
 
 // Near-field items in decreasing order of their estimated cost, so that the
 // launch ends on its cheapest items (a persistent grid otherwise ends on
-// whichever items happen to come last).  The estimate is ceil(m / 8) x
-// (sources of the leaf's whole near list); the key of item i < *count is 255
-// minus the estimate as an 8-bit float (5-bit exponent, 3-bit mantissa), so
-// one radix pass sorts them; items past the count key 255 (after every
-// item); the value is the item's index.
-__global__ void k_near_cost(int64_t leaf_off, int nw, int32_t cap, const int32_t *__restrict__ count,
-                            const int32_t *__restrict__ items, const int32_t *__restrict__ te,
+// whichever items happen to come last).  The estimate is the item's rounds
+// times its target blocks, in units of sixteen sources: with a leaf's whole
+// near list of `srcs` sources and m targets, 2 ceil(m / 8) srcs for the
+// eight-row tile, ceil(m / 4) srcs for the four-row tile (items of at most
+// `small` targets; 0 = never).  A leaf of at most `wide` targets is one item,
+// its first; the other items of such a leaf cost nothing.  The key of item
+// i < *count is 255 minus the estimate as an 8-bit float (5-bit exponent,
+// 3-bit mantissa), so one radix pass sorts them; items past the count key
+// 255 (after every item); the value is the item's index.
+__global__ void k_near_cost(int64_t leaf_off, int nw, int wide, int small, int32_t cap,
+                            const int32_t *__restrict__ count, const int32_t *__restrict__ items,
+                            const int32_t *__restrict__ tb, const int32_t *__restrict__ te,
                             const int32_t *__restrict__ near, const int32_t *__restrict__ sb,
                             const int32_t *__restrict__ se, uint32_t *__restrict__ keys,
                             int32_t *__restrict__ vals)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= cap) return;
-    uint32_t key;
+    uint32_t key = 255u;
     if (i < *count) {
         const int32_t li = items[2 * i], st = items[2 * i + 1];
-        const int32_t m = min(kChunk, te[leaf_off + li] - st);
-        int64_t srcs = 0;
-        for (int k = 0; k < nw; ++k) {
-            const int32_t c = near[(int64_t)li * nw + k];
-            if (c >= 0) srcs += se[c] - sb[c];
+        const int32_t b = tb[leaf_off + li], e = te[leaf_off + li];
+        const bool one = e - b <= wide;
+        if (!one || st == b) {
+            const int32_t m = one ? e - b : min(kChunk, e - st);
+            int64_t srcs = 0;
+            for (int k = 0; k < nw; ++k) {
+                const int32_t c = near[(int64_t)li * nw + k];
+                if (c >= 0) srcs += se[c] - sb[c];
+            }
+            const uint64_t blocks = m <= small ? (uint64_t)((m + 3) / 4) : 2 * (uint64_t)((m + 7) / 8);
+            const uint64_t cost = blocks * (uint64_t)srcs + 1;
+            const int x = 63 - __builtin_clzll(cost);   // cost in [2^x, 2^(x+1))
+            const uint32_t mant = x >= 3 ? (uint32_t)(cost >> (x - 3)) & 7u : (uint32_t)(cost << (3 - x)) & 7u;
+            key = 255u - min(255u, ((uint32_t)min(x, 31) << 3) | mant);
         }
-        const uint64_t cost = (uint64_t)((m + 7) / 8) * (uint64_t)srcs + 1;
-        const int e = 63 - __builtin_clzll(cost);                      // cost in [2^e, 2^(e+1))
-        const uint32_t mant = e >= 3 ? (uint32_t)(cost >> (e - 3)) & 7u : (uint32_t)(cost << (3 - e)) & 7u;
-        key = 255u - min(255u, ((uint32_t)min(e, 31) << 3) | mant);
-    } else {
-        key = 255u;
     }
     keys[i] = key;
     vals[i] = i;
@@ -635,14 +643,15 @@ __global__ void k_items_gather(int32_t cap, const int32_t *__restrict__ order, c
     out[2 * i + 1] = items[2 * j + 1];
 }
 
-void launch_near_items_order(int64_t leaf_off, int nw, int32_t cap, const int32_t *count, const int32_t *items,
-                             const int32_t *te, const int32_t *near, const int32_t *sb, const int32_t *se,
-                             uint32_t *keys, int32_t *vals, void *tmp, int32_t *out, hipStream_t s)
+void launch_near_items_order(int64_t leaf_off, int nw, int wide, int small, int32_t cap, const int32_t *count,
+                             const int32_t *items, const int32_t *tb, const int32_t *te, const int32_t *near,
+                             const int32_t *sb, const int32_t *se, uint32_t *keys, int32_t *vals, void *tmp,
+                             int32_t *out, hipStream_t s)
 {
     if (cap <= 0) return;
     const unsigned g = (unsigned)((cap + 255) / 256);
-    hipLaunchKernelGGL(k_near_cost, dim3(g), dim3(256), 0, s, leaf_off, nw, cap, count, items, te, near, sb, se,
-                       keys, vals);
+    hipLaunchKernelGGL(k_near_cost, dim3(g), dim3(256), 0, s, leaf_off, nw, wide, small, cap, count, items, tb, te,
+                       near, sb, se, keys, vals);
     radix_sort(keys, vals, cap, 8, tmp, s);
     hipLaunchKernelGGL(k_items_gather, dim3(g), dim3(256), 0, s, cap, vals, items, out);
 }
