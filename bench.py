@@ -30,8 +30,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # VALU lane-operations per second of one MI355X: 256 CUs x 4 SIMDs x 16 lanes
-# x 2.4 GHz (FP64 and non-packed FP32 issue at the same rate).
+# x 2.4 GHz for FP64 instructions (a wave64 FP64 instruction holds a SIMD for
+# four cycles: 78.6 TFLOP/s counting an FMA as two), twice that for 32-bit
+# ones (two cycles: 157.3 TFLOP/s FP32), which the mixed near field is
+# measured against.
 LANE_OPS = 256 * 4 * 16 * 2.4e9
+LANE_OPS_32 = 2 * LANE_OPS
 # VALU instructions per source-target pair in the near-field inner loops of
 # the gfx950 code (counted in the kernels' AMD assembly as the compiler emits
 # it): the one-sided kernels (FP64, and mixed with separate targets), and the
@@ -302,8 +306,9 @@ def cpu_baseline(orc, w, infos, tilings, sample, sample_1core):
 
 def near_roofline(infos, tilings, prec):
     """The dominant kernel, the P2P near-field launch, against the VALU issue
-    rate (FP64 VALU issues at the FP32 rate on this chip), from the plan's
-    pair mix and the kernel's per-pair instruction count."""
+    rate (FP64 instructions for the FP64 kernels, 32-bit ones for the mixed
+    kernels), from the plan's pair mix and the kernel's per-pair instruction
+    count."""
     near_ms = np.mean([i["stage_ms"][3] for t in tilings for i in infos[t]])
     pairs = np.mean([i["n_near_pairs"] for t in tilings for i in infos[t]])
     evals = np.mean([i["near_evals"] for t in tilings for i in infos[t]])
@@ -312,8 +317,9 @@ def near_roofline(infos, tilings, prec):
     sym = all(i["targets_are_sources"] for t in tilings for i in infos[t])
     kname = ("k_near_mixed" if prec == "mixed" else "k_near_fp64") + ("_sym" if sym else "")
     traffic = committed_traffic(kname)
+    peak = LANE_OPS_32 if prec == "mixed" else LANE_OPS
     return {"bound": "alu", "kernel": "near field (P2P), %s" % kname, "achieved": ach / 1e9,
-            "peak": LANE_OPS / 1e9, "unit": "G VALU lane-op/s", "frac": ach / LANE_OPS, "traffic": traffic,
+            "peak": peak / 1e9, "unit": "G VALU lane-op/s", "frac": ach / peak, "traffic": traffic,
             "avg_launch_ms": float(near_ms), "pairs_per_launch": float(pairs),
             "evals_per_launch": float(evals), "valu_ops_per_launch": float(ops),
             "valu_per_pair": ({"symmetric_eval": VALU_SYM_EVAL[prec],

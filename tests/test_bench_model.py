@@ -92,6 +92,11 @@ def test_near_roofline_from_plan_infos():
     assert abs(r["achieved"] * 1e9 - 6e9 / 1e-3) < 1.0
     assert abs(r["frac"] - 6e12 / bench.LANE_OPS) < 1e-12
     assert r["valu_per_pair"] == {"symmetric_eval": 73.2, "one_sided": 72.0}
+    # the mixed kernel against the 32-bit issue rate, twice the FP64 one
+    rm = bench.near_roofline(infos, ["quad", "tri"], "mixed")
+    assert rm["kernel"].endswith("k_near_mixed_sym")
+    assert abs(rm["frac"] - 6e12 / (2 * bench.LANE_OPS)) < 1e-12
+    assert rm["peak"] == 2 * r["peak"]
 
 
 def test_m2l_flop_model_by_hand():
