@@ -52,6 +52,7 @@ struct Fence {
     hipEvent_t ev = nullptr;
     uint64_t id = 0;
     hipStream_t stream = nullptr;   // the stream the event was recorded on
+    bool passed = false;            // the event was seen complete (it is never recorded again)
     ~Fence()
     {
         if (ev) hipEventDestroy(ev);
@@ -104,21 +105,28 @@ void *dev_alloc(size_t bytes, int *err, std::vector<uint64_t> *waited, hipStream
         // fence, a fence on this stream, or one already passed), so plans on
         // different streams do not wait for each other's work; then the
         // smallest.
+        // (A fence seen complete is remembered, so each event is queried
+        // until it passes and not after; an exact fit that needs no wait ends
+        // the search.)
         int best = -1, best_rank = 3;
         for (int i = 0; i < (int)g_pool.size(); ++i) {
             const PoolBlock &b = g_pool[i];
             if (b.device != dev || b.bytes < bytes || b.bytes > 2 * bytes) continue;
             int rank = 0;
-            if (b.fence && !(waited && b.fence->stream == stream))
-                rank = event_query(b.fence->ev) == hipSuccess ? 1 : 2;
+            if (b.fence && !(waited && b.fence->stream == stream)) {
+                if (!b.fence->passed && event_query(b.fence->ev) == hipSuccess) b.fence->passed = true;
+                rank = b.fence->passed ? 1 : 2;
+            }
             if (best < 0 || rank < best_rank || (rank == best_rank && b.bytes < g_pool[best].bytes)) {
                 best = i;
                 best_rank = rank;
             }
+            if (best_rank == 0 && g_pool[best].bytes == bytes) break;
         }
         if (best >= 0) {
             p = g_pool[best].p;
             fence = std::move(g_pool[best].fence);
+            if (fence && fence->passed) fence.reset();   // nothing to wait for
             g_pool_cached -= g_pool[best].bytes;
             g_pool.erase(g_pool.begin() + best);
         }
