@@ -847,8 +847,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(3, 8))) void
         using I4 = std::integral_constant<int, 4>;
         using I8 = std::integral_constant<int, 8>;
         if (m <= kSmall) {
-            switch ((m + 3) >> 2) {
-            case 1: item_rounds(I4{}, std::integral_constant<int, 1>{}); break;
+            // (an item of up to four targets takes two blocks: the one-block
+            // loop alone would raise the kernel from 154 to 168 VGPRs, which
+            // leaves no registers for other kernels' waves beside its three
+            // per SIMD)
+            switch (m <= 4 ? 2 : (m + 3) >> 2) {
             case 2: item_rounds(I4{}, std::integral_constant<int, 2>{}); break;
             case 3: item_rounds(I4{}, std::integral_constant<int, 3>{}); break;
             case 4: item_rounds(I4{}, std::integral_constant<int, 4>{}); break;

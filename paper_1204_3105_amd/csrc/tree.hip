@@ -595,7 +595,7 @@ void launch_near_items_fill(const LevelInfo *lev, int L, const int32_t *tb, cons
 // whichever items happen to come last).  The estimate is the item's rounds
 // times its target blocks, in units of sixteen sources: with a leaf's whole
 // near list of `srcs` sources and m targets, 2 ceil(m / 8) srcs for the
-// eight-row tile, ceil(m / 4) srcs for the four-row tile (items of at most
+// eight-row tile, max(2, ceil(m / 4)) srcs for the four-row tile (items of at most
 // `small` targets; 0 = never).  A leaf of at most `wide` targets is one item,
 // its first; the other items of such a leaf cost nothing.  The key of item
 // i < *count is 255 minus the estimate as an 8-bit float (5-bit exponent,
@@ -622,7 +622,7 @@ __global__ void k_near_cost(int64_t leaf_off, int nw, int wide, int small, int32
                 const int32_t c = near[(int64_t)li * nw + k];
                 if (c >= 0) srcs += se[c] - sb[c];
             }
-            const uint64_t blocks = m <= small ? (uint64_t)((m + 3) / 4) : 2 * (uint64_t)((m + 7) / 8);
+            const uint64_t blocks = m <= small ? (uint64_t)max(2, (m + 3) / 4) : 2 * (uint64_t)((m + 7) / 8);
             const uint64_t cost = blocks * (uint64_t)srcs + 1;
             const int x = 63 - __builtin_clzll(cost);   // cost in [2^x, 2^(x+1))
             const uint32_t mant = x >= 3 ? (uint32_t)(cost >> (x - 3)) & 7u : (uint32_t)(cost << (3 - x)) & 7u;

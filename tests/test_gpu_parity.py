@@ -230,7 +230,7 @@ def test_fp64_symmetric_uneven_leaves(F, orc, tiling):
 def test_fp64_symmetric_every_tile_shape(F, orc):
     """FP64, targets = sources, quadtree at explicit depths chosen so that the
     leaves take every shape of the symmetric near field: blocks of four rows
-    (items of up to 48 targets, 1..12 blocks), blocks of eight rows (49..96
+    (items of up to 48 targets, 2..12 blocks), blocks of eight rows (49..96
     targets, 7..12 blocks) and chunks of 64 (larger leaves).  Same bar as
     every FP64 potential."""
     seen = set()
@@ -244,11 +244,11 @@ def test_fp64_symmetric_every_tile_shape(F, orc):
         for m in sizes[sizes > 0]:
             items = [m] if m <= 96 else [64] * (m // 64) + ([m % 64] if m % 64 else [])
             for c in items:
-                seen.add((4, (c + 3) // 4) if c <= 48 else (8, (c + 7) // 8))
+                seen.add((4, max(2, (c + 3) // 4)) if c <= 48 else (8, (c + 7) // 8))
         g = orc.geom("quad", L, *inf["geometry"])
         ref = orc.fmm(g, inf["p"], w.xs, w.ys, w.u, w.xt, w.yt)
         e = rel(phi, ref)
         say("tile shapes: n=%d L=%d leaves %d..%d, rel_l2=%.3e" % (n, L, sizes[sizes > 0].min(), sizes.max(), e))
         assert e <= 1e-12
-    need = {(4, b) for b in range(1, 13)} | {(8, b) for b in range(7, 13)}
+    need = {(4, b) for b in range(2, 13)} | {(8, b) for b in range(7, 13)}
     assert need <= seen, sorted(need - seen)
